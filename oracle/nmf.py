@@ -1,0 +1,251 @@
+"""FP64 reference NMF: the Gram and large products, the MU / HALS / ABPP
+updates and the relative error, following Algorithm 1 step by step.
+
+Test infrastructure only; see the package docstring.
+
+Shapes follow the paper's notation (Section 1 and Table 2): A is m x n,
+W is m x k, H is k x n. A may be a dense ndarray or a scipy.sparse matrix.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .bpp import bpp_nnls
+
+# Section 4.1 gives MU without a rule for a zero denominator. The oracle adds
+# this constant to every denominator (reading taken for the whole build);
+# for positive data the denominators are many orders larger.
+MU_EPS = 1e-16
+
+
+def _f64(X):
+    return np.asarray(X, dtype=np.float64)
+
+
+def _is_sparse(A) -> bool:
+    return hasattr(A, "tocsr") and not isinstance(A, np.ndarray)
+
+
+# --- the four products of Algorithm 1 ------------------------------------
+
+def gram_fixed_H(H):
+    """H H^T (k x k), used by the W update (Algorithm 1, W step)."""
+    H = _f64(H)
+    return H @ H.T
+
+
+def gram_fixed_W(W):
+    """W^T W (k x k), used by the H update (Algorithm 1, H step)."""
+    W = _f64(W)
+    return W.T @ W
+
+
+def product_AHt(A, H):
+    """A H^T (m x k)."""
+    H = _f64(H)
+    if _is_sparse(A):
+        return np.asarray(A.tocsr().astype(np.float64) @ H.T)
+    return _f64(A) @ H.T
+
+
+def product_WtA(A, W):
+    """W^T A (k x n)."""
+    W = _f64(W)
+    if _is_sparse(A):
+        return np.asarray(A.tocsc().astype(np.float64).T @ W).T
+    return W.T @ _f64(A)
+
+
+# --- Section 4.1: multiplicative update, Eq. (3) -------------------------
+
+def mu_update_W(W, Q, P, eps=MU_EPS):
+    """w_ij <- w_ij (A H^T)_ij / (W H H^T)_ij, all entries at once.
+
+    Q = H H^T, P = A H^T. ``eps`` is added to the denominator.
+    """
+    W = _f64(W)
+    return W * _f64(P) / (W @ _f64(Q) + eps)
+
+
+def mu_update_H(H, S, R, eps=MU_EPS):
+    """h_ij <- h_ij (W^T A)_ij / (W^T W H)_ij.  S = W^T W, R = W^T A (k x n)."""
+    H = _f64(H)
+    return H * _f64(R) / (_f64(S) @ H + eps)
+
+
+# --- Section 4.2: HALS, Eqs. (4)-(5) -------------------------------------
+
+def hals_update_W(W, H, Q, P, on_column=None):
+    """One HALS sweep over the columns of W, then the column normalisation.
+
+    Eq. (5) updates w^i for i = 1..k in order, each time with the newest
+    values of the other columns (Section 4.2 says the columns are updated in
+    order so that the most up-to-date values are used), and normalises w^i.
+
+    Readings taken (the printed rule omits the divisor and leaves H alone):
+    HALS is the 2k-block coordinate descent of Eq. (4), so the exact
+    minimiser of ||A - sum_j w^j h_j||_F over w^i >= 0 with everything else
+    fixed is used,
+
+        w^i <- max(0, w^i + ((A H^T)^i - W (H H^T)^i) / (H H^T)_ii),
+
+    skipped when (H H^T)_ii = 0; and the normalisation w^i <- w^i / s_i,
+    s_i = ||w^i||_2 > 0, is compensated by h_i <- s_i h_i so that W H is
+    unchanged. After rescaling row i of H, Q and P are rescaled to match
+    (Q_i. and Q_.i by s_i, P^i by s_i), which is what recomputing them from
+    the new H would give.
+
+    Returns (W_new, H_rescaled). ``on_column(i, W, H)``, if given, is called
+    right after column i is updated and before it is normalised.
+    """
+    W = _f64(W).copy()
+    H = _f64(H).copy()
+    Q = _f64(Q).copy()
+    P = _f64(P).copy()
+    k = W.shape[1]
+    for i in range(k):
+        if Q[i, i] > 0:
+            W[:, i] = np.maximum(0.0, W[:, i] + (P[:, i] - W @ Q[:, i]) / Q[i, i])
+        if on_column is not None:
+            on_column(i, W.copy(), H.copy())
+        s = np.linalg.norm(W[:, i])
+        if s > 0:
+            W[:, i] /= s
+            H[i, :] *= s
+            Q[i, :] *= s
+            Q[:, i] *= s
+            P[:, i] *= s
+    return W, H
+
+
+def hals_update_H(H, S, R, on_row=None):
+    """One HALS sweep over the rows of H (Eq. (5), third rule).
+
+        h_i <- max(0, h_i + ((W^T A)_i - (W^T W)_i H) / (W^T W)_ii),
+
+    for i = 1..k in order with the newest rows, skipped when S_ii = 0. After
+    the W normalisation S_ii = 1 for every nonzero column, so the division
+    only matters for robustness; the paper prints the rule without it.
+    """
+    H = _f64(H).copy()
+    S = _f64(S)
+    R = _f64(R)
+    k = H.shape[0]
+    for i in range(k):
+        if S[i, i] > 0:
+            H[i, :] = np.maximum(0.0, H[i, :] + (R[i, :] - S[i, :] @ H) / S[i, i])
+        if on_row is not None:
+            on_row(i, H.copy())
+    return H
+
+
+# --- Section 4.3: ANLS with BPP ------------------------------------------
+
+def abpp_update_W(Q, P, max_pivots=None):
+    """W <- argmin_{W>=0} ||A - W H||_F, row by row (Eq. (2), first line).
+
+    Row r of W solves min_{x>=0} 1/2 x^T Q x - p_r^T x with Q = H H^T and
+    p_r the r-th row of P = A H^T, i.e. SolveBPP(H H^T, H A^T)^T.
+    """
+    return bpp_nnls(Q, _f64(P).T, max_pivots=max_pivots).T
+
+
+def abpp_update_H(S, R, max_pivots=None):
+    """H <- argmin_{H>=0} ||A - W H||_F column by column: SolveBPP(W^T W, W^T A)."""
+    return bpp_nnls(S, R, max_pivots=max_pivots)
+
+
+# --- Section 6.2: relative error -----------------------------------------
+
+def objective_sq(A, W, H, row_block: int = 2048) -> float:
+    """||A - W H||_F^2 evaluated directly.
+
+    Dense A: the residual is formed explicitly, a row block at a time.
+    Sparse A: sum over stored entries of (a_ij - (WH)_ij)^2 - (WH)_ij^2, plus
+    ||W H||_F^2 = <W^T W, H H^T>; the stored-entry part is the residual at
+    those entries and the rest accounts for the zeros, so the value is
+    ||A - W H||_F^2 exactly (up to rounding).
+    """
+    W = _f64(W)
+    H = _f64(H)
+    if _is_sparse(A):
+        C = A.tocoo()
+        total = float(np.sum(gram_fixed_W(W) * gram_fixed_H(H)))
+        rows = C.row.astype(np.int64)
+        cols = C.col.astype(np.int64)
+        vals = C.data.astype(np.float64)
+        step = 1 << 20
+        for s in range(0, vals.size, step):
+            r, c, v = rows[s:s + step], cols[s:s + step], vals[s:s + step]
+            wh = np.einsum("ij,ji->i", W[r], H[:, c])
+            total += float(np.sum((v - wh) ** 2 - wh ** 2))
+        return total
+    total = 0.0
+    m = W.shape[0]
+    for r0 in range(0, m, row_block):
+        r1 = min(m, r0 + row_block)
+        D = _f64(A[r0:r1]) - W[r0:r1] @ H
+        total += float(np.sum(D * D))
+    return total
+
+
+def _norm_sq(A) -> float:
+    if _is_sparse(A):
+        d = A.tocoo().data.astype(np.float64)
+        return float(np.sum(d * d))
+    total = 0.0
+    for r0 in range(0, A.shape[0], 4096):
+        blk = _f64(A[r0:r0 + 4096])
+        total += float(np.sum(blk * blk))
+    return total
+
+
+def relative_error(A, W, H, normA_sq: float | None = None) -> float:
+    """||A - W H||_F / ||A||_F (Section 6.2)."""
+    if normA_sq is None:
+        normA_sq = _norm_sq(A)
+    return float(np.sqrt(max(objective_sq(A, W, H), 0.0) / normA_sq))
+
+
+# --- Algorithm 1 ---------------------------------------------------------
+
+def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
+        max_pivots=None, track_error: bool = True):
+    """AU-NMF (Algorithm 1) for ``iters`` iterations from (W0, H0).
+
+    One iteration: Q = H H^T, P = A H^T, update W; S = W^T W, R = W^T A,
+    update H. ABPP does not read W0 (its W update is an exact solve). Returns
+    (W, H, rel_err) with rel_err[t] the relative error after t iterations
+    (rel_err[0] at the initial factors), or an empty list when
+    ``track_error`` is False.
+    """
+    algo = algo.lower()
+    if algo not in ("mu", "hals", "abpp"):
+        raise ValueError("unknown algorithm %r" % algo)
+    W = _f64(W0).copy()
+    H = _f64(H0).copy()
+    assert W.shape[1] == k and H.shape[0] == k
+    errs = []
+    normA_sq = _norm_sq(A) if track_error else None
+    if track_error:
+        errs.append(relative_error(A, W, H, normA_sq))
+    for _ in range(iters):
+        Q = gram_fixed_H(H)
+        P = product_AHt(A, H)
+        if algo == "mu":
+            W = mu_update_W(W, Q, P, eps)
+        elif algo == "hals":
+            W, H = hals_update_W(W, H, Q, P)
+        else:
+            W = abpp_update_W(Q, P, max_pivots)
+        S = gram_fixed_W(W)
+        R = product_WtA(A, W)
+        if algo == "mu":
+            H = mu_update_H(H, S, R, eps)
+        elif algo == "hals":
+            H = hals_update_H(H, S, R)
+        else:
+            H = abpp_update_H(S, R, max_pivots)
+        if track_error:
+            errs.append(relative_error(A, W, H, normA_sq))
+    return W, H, errs
