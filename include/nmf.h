@@ -1,0 +1,217 @@
+/*
+ * nmf.h -- C ABI of the MI355X (gfx950) alternating-updating NMF library.
+ *
+ * Problem (Section 1, Eq. (1)): given a nonnegative m x n matrix A and a rank
+ * k, find W (m x k) >= 0 and H (k x n) >= 0 that reduce ||A - W H||_F.
+ * Method (Algorithm 1, AU-NMF): repeat { update W from H H^T and A H^T;
+ * update H from W^T W and W^T A } for a fixed number of iterations, the
+ * stopping rule of Section 6.1.3. The local update is one of
+ *   NMF_MU   -- multiplicative update, Section 4.1, Eq. (3);
+ *   NMF_HALS -- hierarchical alternating least squares, Section 4.2, Eq. (5);
+ *   NMF_ABPP -- exact nonnegative least squares by block principal pivoting,
+ *               Section 4.3, Eqs. (6)-(7).
+ * The relative error ||A - W H||_F / ||A||_F of Section 6.2 can be reported
+ * after every iteration.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrix arguments are DEVICE pointers on the context's GPU, row-major,
+ *   with the leading dimension (elements between consecutive rows) given
+ *   where stated and otherwise equal to the number of columns. Host pointers
+ *   are marked "host".
+ * - The caller owns every array it passes. The library reads A (and the CSR
+ *   arrays), reads and overwrites W and H in place, and writes outputs.
+ *   The context owns only its workspace, which it frees in nmf_destroy.
+ * - Work is enqueued on the context's HIP stream. A call returns once its
+ *   work is enqueued, except that a call given a host rel_err or stats
+ *   pointer, or one that must check a device-side error flag (ABPP, input
+ *   checks), synchronises the stream before returning.
+ * - Errors are reported as nmf_status codes only; no exception or abort
+ *   crosses the ABI. Argument checks run on the host before any device
+ *   work, so an NMF_EINVAL return has touched no device memory.
+ *   nmf_last_error() describes the most recent failure on a context.
+ * - Element types: NMF_F64 runs everything in double; NMF_F32 stores A, W, H
+ *   in float and accumulates the large products in float on the matrix
+ *   cores, with the Gram split-sums and the objective accumulated in double.
+ * - 1 <= k <= NMF_MAX_K and k <= min(m, n) is not required, but k must not
+ *   exceed NMF_MAX_K. m, n >= 1.
+ * - Calls on one context must not overlap (one stream, shared workspace).
+ */
+#ifndef NMF_MI355X_H
+#define NMF_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NMF_MAX_K 128
+
+typedef enum {
+  NMF_OK = 0,
+  NMF_EINVAL = 1,    /* bad argument (null pointer, size, enum, layout)      */
+  NMF_ENOMEM = 2,    /* device allocation failed                             */
+  NMF_EDEVICE = 3,   /* a HIP call failed                                    */
+  NMF_ENUMERIC = 4,  /* NaN/Inf/negative input (check_input) or a singular   */
+                     /* passive-set system in ABPP                           */
+  NMF_ENOTCONV = 5   /* ABPP: pivot cap reached before the KKT conditions    */
+} nmf_status;
+
+typedef enum { NMF_MU = 0, NMF_HALS = 1, NMF_ABPP = 2 } nmf_algo;
+
+typedef enum { NMF_F64 = 0, NMF_F32 = 1 } nmf_dtype;
+
+typedef enum {
+  NMF_OBJ_NONE = 0,    /* do not evaluate the objective                    */
+  NMF_OBJ_DIRECT = 1   /* ||A - W H||_F from the residual: dense A forms   */
+                       /* A - W H tile by tile; CSR A sums (a - wh)^2 -    */
+                       /* wh^2 over stored entries plus <W^T W, H H^T>     */
+} nmf_objective;
+
+typedef struct {
+  int algo;          /* nmf_algo                                             */
+  int iters;         /* number of AU-NMF iterations (>= 0)                   */
+  double eps_mu;     /* MU: added to every denominator (Eq. (3) has no zero  */
+                     /* guard); 1e-16 is the documented default             */
+  int max_pivots;    /* ABPP: cap on passive-set solves per right-hand side; */
+                     /* <= 0 selects 50 k                                    */
+  int objective;     /* nmf_objective, evaluated at start and after each it. */
+  int timers;        /* nonzero: fill the per-phase times in nmf_stats       */
+  int check_input;   /* nonzero: scan A for NaN/Inf/negative entries and the */
+                     /* CSR arrays for out-of-range or unsorted columns      */
+} nmf_opts;
+
+typedef struct {
+  double ms_total;   /* wall time of the iterations (hipEvents)              */
+  double ms_mm;      /* large products A H^T, W^T A (Section 6.3.1 "MM")     */
+  double ms_luc;     /* local update computations ("LUC")                    */
+  double ms_gram;    /* H H^T and W^T W ("Gram")                             */
+  double ms_obj;     /* objective evaluations                                */
+  double ms_setup;   /* layout copies, CSR transpose                         */
+  long long bpp_pivots; /* ABPP: total passive-set solves over all RHS       */
+} nmf_stats;
+
+typedef struct nmf_ctx nmf_ctx;
+
+/* Fills *opts with the defaults: MU, 0 iterations, eps_mu 1e-16,
+ * max_pivots 0 (= 50 k), no objective, no timers, no input check. */
+void nmf_default_opts(nmf_opts* opts);
+
+/* Creates a context bound to HIP device `device` and the HIP stream
+ * `hip_stream` (a hipStream_t; NULL means the default stream).
+ * device = -1 creates a context bound to no device: every call on it runs
+ * its argument checks and then returns NMF_EDEVICE (argument checking on a
+ * machine without a GPU). */
+nmf_status nmf_create(nmf_ctx** out, int device, void* hip_stream);
+void nmf_destroy(nmf_ctx* ctx);
+/* Rebinds the context to another stream on the same device. */
+nmf_status nmf_set_stream(nmf_ctx* ctx, void* hip_stream);
+
+const char* nmf_status_str(nmf_status s);
+const char* nmf_last_error(const nmf_ctx* ctx);
+
+/* Full AU-NMF on a dense A (Algorithm 1).
+ *   A       m x n, leading dimension lda >= n, element type a_dtype.
+ *   W       m x k (leading dimension k), same element type: the initial W on
+ *           entry (read by MU and HALS, ignored by ABPP, whose W step is an
+ *           exact solve), the final W on return.
+ *   H       k x n (leading dimension n): initial H on entry, final H on return.
+ *   rel_err host array of iters+1 doubles or NULL; requires opts->objective.
+ *   stats   host pointer or NULL.
+ * HALS returns W with unit-norm nonzero columns, the scale carried by H. */
+nmf_status nmf_dense(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
+                     const void* A, int64_t lda, int k, const nmf_opts* opts,
+                     void* W, void* H, double* rel_err, nmf_stats* stats);
+
+/* Full AU-NMF on a sparse A in CSR form, float32 values.
+ *   rowptr  m+1 int64, rowptr[0] = 0, rowptr[m] = nnz, nondecreasing.
+ *   colidx  nnz int32 column ids in [0, n), increasing within each row.
+ *   vals    nnz floats >= 0.
+ * W (m x k) and H (k x n) are float32 as for nmf_dense. The transpose of A
+ * (needed for W^T A) is built once per call on the device. */
+nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                   const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                   int k, const nmf_opts* opts, float* W, float* H,
+                   double* rel_err, nmf_stats* stats);
+
+/* ---- Per-step entry points (one phase of Algorithm 1 each) --------------
+ * These use the same row layout as the iteration driver: the fixed factor
+ * is given with one row per row (W, m x k) or per column (H^T, n x k) of A,
+ * so the two half-steps of Algorithm 1 are the same calls with A and A^T.
+ */
+
+/* G = X^T X for X rows x k (leading dimension ldx >= k); G is k x k.
+ * With X = W this is W^T W; with X = H^T it is H H^T (Algorithm 1). */
+nmf_status nmf_gram(nmf_ctx* ctx, nmf_dtype dtype, int64_t rows, int k,
+                    const void* X, int64_t ldx, void* G);
+
+/* P = A F for dense A (m x n, lda) and F (n x k, ldf): with F = H^T this is
+ * the A H^T of the W update. Output P is m x k (leading dimension k). */
+nmf_status nmf_dense_AF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
+                        const void* A, int64_t lda, int k, const void* F,
+                        int64_t ldf, void* P);
+
+/* R = A^T F for dense A (m x n, lda) and F (m x k, ldf): with F = W this is
+ * (W^T A)^T of the H update. Output R is n x k (leading dimension k). */
+nmf_status nmf_dense_AtF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
+                         const void* A, int64_t lda, int k, const void* F,
+                         int64_t ldf, void* R);
+
+/* P = A F for CSR A (m x n, float32) and dense F (n x k, float32, leading
+ * dimension k). With the CSR arrays of A^T this computes A^T W instead. */
+nmf_status nmf_csr_AF(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                      const int64_t* rowptr, const int32_t* colidx,
+                      const float* vals, int k, const float* F, float* P);
+
+/* CSR of A^T (n rows) from CSR of A: rowptr_t has n+1 entries, colidx_t and
+ * vals_t have nnz; columns within each output row are increasing. */
+nmf_status nmf_csr_transpose(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                             const int64_t* rowptr, const int32_t* colidx,
+                             const float* vals, int64_t* rowptr_t,
+                             int32_t* colidx_t, float* vals_t);
+
+/* One local update of X (rows x k, leading dimension k) in place, given the
+ * Gram G (k x k) of the fixed factor and the product P (rows x k) of A with
+ * it: row r of X is the row of W (or of H^T) that Algorithm 1 updates from
+ * G and row r of P.
+ *   NMF_MU:   x <- x .* p ./ (x G + eps_mu)                      (Eq. (3))
+ *   NMF_HALS: for i = 1..k in order: if G_ii > 0,
+ *             x_i <- max(0, x_i + (p_i - x G_:i) / G_ii)        (Eq. (5))
+ *             (no normalisation here; see nmf_hals_normalize)
+ *   NMF_ABPP: x <- argmin_{x >= 0} 1/2 x^T G x - p^T x          (Eqs. (6)-(7))
+ *             by block principal pivoting; the incoming X is ignored.
+ *             pivots (host, nullable) receives the total number of
+ *             passive-set solves. */
+nmf_status nmf_update(nmf_ctx* ctx, nmf_algo algo, nmf_dtype dtype,
+                      int64_t rows, int k, const void* G, const void* P,
+                      void* X, const nmf_opts* opts, long long* pivots);
+
+/* HALS column normalisation with compensation (Section 4.2): for every
+ * i < k with s_i = ||w^i||_2 > 0, w^i <- w^i / s_i and h_i <- s_i h_i, so
+ * W H is unchanged. W is m x k, Ht = H^T is n x k (both leading dimension
+ * k), both updated in place. S (k x k, nullable) receives W^T W of the
+ * normalised W; norms (k entries, nullable, device) receives s. */
+nmf_status nmf_hals_normalize(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
+                              int64_t n, int k, void* W, void* Ht, void* S,
+                              void* norms);
+
+/* Relative error ||A - W H||_F / ||A||_F of Section 6.2 for dense A, with W
+ * (m x k) and Ht = H^T (n x k). Residual formed explicitly, squares summed
+ * in double. Result written to the host double *out (synchronises). */
+nmf_status nmf_dense_relerr(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
+                            int64_t n, const void* A, int64_t lda, int k,
+                            const void* W, const void* Ht, double* out);
+
+/* Same for CSR A: sum over stored entries of (a - wh)^2 - wh^2, plus
+ * <W^T W, H H^T> for the zeros. */
+nmf_status nmf_csr_relerr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                          const int64_t* rowptr, const int32_t* colidx,
+                          const float* vals, int k, const float* W,
+                          const float* Ht, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMF_MI355X_H */

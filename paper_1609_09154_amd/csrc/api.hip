@@ -1,0 +1,922 @@
+// C ABI of the NMF library: argument checks, workspace, and the AU-NMF
+// iteration driver (Algorithm 1) that sequences the kernels of gemm.hip,
+// update.hip, bpp.hip, sparse.hip and objective.hip on one HIP stream.
+//
+// Internal layout ("row layout"): the factor updated in each half-step is
+// stored with one row per right-hand side, padded to KP columns:
+//   W  (m x KP)  rows of W;        P = A H^T   (m x KP),  Q = H H^T (KP x KP)
+//   Ht (n x KP)  rows of H^T;      R = A^T W   (n x KP),  S = W^T W (KP x KP)
+// so the W step (Q, P -> W) and the H step (S, R -> Ht) run the same kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "nmf.h"
+
+using nmfk::cdiv;
+using nmfk::round_up;
+
+struct nmf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace {
+
+nmf_status fail(nmf_ctx* c, nmf_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+nmf_status hip_fail(nmf_ctx* c, hipError_t e, const char* where) {
+  std::string msg = std::string(where) + ": " + hipGetErrorString(e);
+  if (c) c->err = msg;
+  return e == hipErrorOutOfMemory ? NMF_ENOMEM : NMF_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+  } while (0)
+
+// Bump allocator over the context workspace (256-byte aligned slices).
+struct Carve {
+  size_t off = 0;
+  template <typename P> size_t take(size_t count) {
+    const size_t at = off;
+    off = round_up(off + count * sizeof(P), 256);
+    return at;
+  }
+};
+
+nmf_status ensure_ws(nmf_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return NMF_OK;
+  if (ctx->ws) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  const size_t want = round_up(bytes, (size_t)1 << 20);
+  hipError_t e = hipMalloc(&ctx->ws, want);
+  if (e != hipSuccess) {
+    ctx->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, NMF_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  ctx->ws_bytes = want;
+  return NMF_OK;
+}
+
+template <typename P> P* at(nmf_ctx* ctx, size_t off) {
+  return reinterpret_cast<P*>(reinterpret_cast<char*>(ctx->ws) + off);
+}
+
+int kp_dense(int k) { return (int)round_up(k, 16); }
+int kp_sparse(int k) {
+  int kp = 16;
+  while (kp < k) kp *= 2;
+  return kp;
+}
+
+// Splits of the reduction index for the large products: enough workgroups to
+// give every CU at least two, each split still long.
+int64_t product_splits(int64_t wgs, int64_t K) {
+  int64_t s = 1;
+  while (wgs * s < 512 && K / (2 * s) >= 4096 && s < 16) s *= 2;
+  return s;
+}
+int64_t gram_splits(int64_t rows) {
+  int64_t s = cdiv(rows, 256);
+  return s < 1 ? 1 : (s > 1024 ? 1024 : s);
+}
+
+nmf_status bind_device(nmf_ctx* ctx) {
+  if (ctx->device < 0) return fail(ctx, NMF_EDEVICE, "context is not bound to a device");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NMF_EDEVICE, "hipSetDevice failed");
+  return NMF_OK;
+}
+
+nmf_status check_common(nmf_ctx* ctx, int64_t m, int64_t n, int k) {
+  if (!ctx) return NMF_EINVAL;
+  if (m < 1 || n < 1) return fail(ctx, NMF_EINVAL, "m and n must be >= 1");
+  if (k < 1 || k > NMF_MAX_K) return fail(ctx, NMF_EINVAL, "k must be in [1, NMF_MAX_K]");
+  if (m > ((int64_t)1 << 40) || n > ((int64_t)1 << 40))
+    return fail(ctx, NMF_EINVAL, "m or n too large");
+  return NMF_OK;
+}
+
+nmf_status check_opts(nmf_ctx* ctx, const nmf_opts* o, int k, bool have_relerr) {
+  if (!o) return fail(ctx, NMF_EINVAL, "opts is NULL");
+  if (o->algo < NMF_MU || o->algo > NMF_ABPP) return fail(ctx, NMF_EINVAL, "unknown algorithm");
+  if (o->iters < 0) return fail(ctx, NMF_EINVAL, "iters must be >= 0");
+  if (o->objective < NMF_OBJ_NONE || o->objective > NMF_OBJ_DIRECT)
+    return fail(ctx, NMF_EINVAL, "unknown objective mode");
+  if (have_relerr && o->objective == NMF_OBJ_NONE)
+    return fail(ctx, NMF_EINVAL, "rel_err requested with objective NMF_OBJ_NONE");
+  if (o->algo == NMF_MU && !(o->eps_mu >= 0.0)) return fail(ctx, NMF_EINVAL, "eps_mu must be >= 0");
+  if (o->algo == NMF_ABPP && k > 64) return fail(ctx, NMF_EINVAL, "ABPP supports k <= 64");
+  return NMF_OK;
+}
+
+// Per-phase hipEvent timing.
+struct Timers {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<std::pair<hipEvent_t, int>> marks;  // event, phase that starts here (-1 = end)
+  void mark(int phase) {
+    if (!on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+    hipEventRecord(e, st);
+    marks.push_back({e, phase});
+  }
+  void collect(nmf_stats* s) {
+    if (!on || marks.empty()) return;
+    hipEventSynchronize(marks.back().first);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (size_t i = 0; i + 1 < marks.size(); ++i) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, marks[i].first, marks[i + 1].first);
+      if (marks[i].second >= 0) acc[marks[i].second] += ms;
+    }
+    s->ms_mm += acc[0];
+    s->ms_luc += acc[1];
+    s->ms_gram += acc[2];
+    s->ms_obj += acc[3];
+    s->ms_setup += acc[4];
+    for (auto& m : marks) hipEventDestroy(m.first);
+    marks.clear();
+  }
+  ~Timers() {
+    for (auto& m : marks) hipEventDestroy(m.first);
+  }
+};
+enum { PH_MM = 0, PH_LUC = 1, PH_GRAM = 2, PH_OBJ = 3, PH_SETUP = 4, PH_END = -1 };
+
+template <typename T> nmf_dtype dtype_of();
+template <> nmf_dtype dtype_of<float>() { return NMF_F32; }
+template <> nmf_dtype dtype_of<double>() { return NMF_F64; }
+
+// Everything one AU-NMF call needs on the device.
+template <typename T> struct Work {
+  T *W, *Ht, *P, *R, *Q, *S, *norms, *part;
+  double *obj_part, *relerr, *normA;
+  int* status;
+  unsigned long long* pivots;
+  int64_t obj_np;
+};
+
+template <typename T>
+nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, int64_t rows,
+                        int k, int KP, const nmf_opts* o, int* status,
+                        unsigned long long* pivots) {
+  hipStream_t st = ctx->stream;
+  if (algo == NMF_MU) HIP_TRY(nmfk::mu_rows<T>(X, Pm, G, rows, k, KP, (T)o->eps_mu, st));
+  else if (algo == NMF_HALS) HIP_TRY(nmfk::hals_rows<T>(X, Pm, G, rows, k, KP, st));
+  else {
+    const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
+    HIP_TRY(nmfk::bpp_rows<T>(X, Pm, G, rows, k, KP, cap, status, pivots, st));
+  }
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part) {
+  nmfk::GemmArgs<T> a{X, KP, X, KP, G, KP, KP, KP, rows};
+  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(rows), part, ctx->stream));
+  return NMF_OK;
+}
+
+template <typename T>
+int64_t mw_rows() { return 16 * 4 * 4; }  // rows per workgroup of the product kernels
+
+// Workspace offsets for an AU-NMF call on an m x n problem.
+template <typename T>
+size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_t extra_part,
+                 Carve& cv, size_t off[12]) {
+  const int64_t ps_p = product_splits(cdiv(m, mw_rows<T>()), n);
+  const int64_t ps_r = product_splits(cdiv(n, mw_rows<T>()), m);
+  int64_t part = ps_p > 1 ? ps_p * m * KP : 0;
+  part = std::max<int64_t>(part, ps_r > 1 ? ps_r * n * KP : 0);
+  part = std::max<int64_t>(part, gram_splits(std::max(m, n)) * KP * KP);
+  part = std::max<int64_t>(part, extra_part);
+  off[0] = cv.take<T>(m * KP);
+  off[1] = cv.take<T>(n * KP);
+  off[2] = cv.take<T>(m * KP);
+  off[3] = cv.take<T>(n * KP);
+  off[4] = cv.take<T>(KP * KP);
+  off[5] = cv.take<T>(KP * KP);
+  off[6] = cv.take<T>(KP);
+  off[7] = cv.take<T>(part);
+  off[8] = cv.take<double>(obj_np + 1);
+  off[9] = cv.take<double>(iters + 2);
+  off[10] = cv.take<int>(4);
+  off[11] = cv.take<unsigned long long>(2);
+  return cv.off;
+}
+
+template <typename T>
+Work<T> bind_work(nmf_ctx* ctx, const size_t off[12], int64_t obj_np) {
+  Work<T> w;
+  w.W = at<T>(ctx, off[0]);
+  w.Ht = at<T>(ctx, off[1]);
+  w.P = at<T>(ctx, off[2]);
+  w.R = at<T>(ctx, off[3]);
+  w.Q = at<T>(ctx, off[4]);
+  w.S = at<T>(ctx, off[5]);
+  w.norms = at<T>(ctx, off[6]);
+  w.part = at<T>(ctx, off[7]);
+  w.obj_part = at<double>(ctx, off[8]);
+  w.normA = w.obj_part + obj_np;
+  w.relerr = at<double>(ctx, off[9]);
+  w.status = at<int>(ctx, off[10]);
+  w.pivots = at<unsigned long long>(ctx, off[11]);
+  w.obj_np = obj_np;
+  return w;
+}
+
+nmf_status read_status(nmf_ctx* ctx, const int* dstatus, const unsigned long long* dpiv,
+                       long long* pivots_out) {
+  int s[2] = {0, 0};
+  unsigned long long pv = 0;
+  HIP_TRY(hipMemcpyAsync(s, dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(&pv, dpiv, sizeof(pv), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (pivots_out) *pivots_out = (long long)pv;
+  if (s[1]) return fail(ctx, NMF_ENUMERIC, "input contains NaN, Inf, negative or malformed entries");
+  if (s[0] & 1) return fail(ctx, NMF_ENUMERIC, "ABPP: passive-set system not positive definite");
+  if (s[0] & 2) return fail(ctx, NMF_ENOTCONV, "ABPP: pivot cap reached before the KKT conditions held");
+  return NMF_OK;
+}
+
+// Problem description shared by the dense and CSR drivers.
+template <typename T> struct Prob {
+  bool sparse = false;
+  const T* A = nullptr; int64_t lda = 0;                 // dense
+  const int64_t* rp = nullptr; const int32_t* ci = nullptr; const float* cv = nullptr;  // CSR A
+  const int64_t* rpt = nullptr; const int32_t* cit = nullptr; const float* cvt = nullptr; // CSR A^T
+  int64_t nnz = 0;
+};
+
+template <typename T>
+nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int KP,
+                      T* Pout, T* part) {
+  if (pb.sparse) {
+    if constexpr (sizeof(T) == 4) {
+      HIP_TRY(nmfk::csr_spmm(pb.rp, pb.ci, pb.cv, m, F, KP, Pout, ctx->stream));
+      return NMF_OK;
+    }
+    return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
+  }
+  nmfk::GemmArgs<T> a{pb.A, pb.lda, F, KP, Pout, KP, m, KP, n};
+  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::NN, a, product_splits(cdiv(m, mw_rows<T>()), n), part,
+                            ctx->stream));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int KP,
+                       T* Rout, T* part) {
+  if (pb.sparse) {
+    if constexpr (sizeof(T) == 4) {
+      HIP_TRY(nmfk::csr_spmm(pb.rpt, pb.cit, pb.cvt, n, F, KP, Rout, ctx->stream));
+      return NMF_OK;
+    }
+    return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
+  }
+  nmfk::GemmArgs<T> a{pb.A, pb.lda, F, KP, Rout, KP, n, KP, m};
+  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, product_splits(cdiv(n, mw_rows<T>()), m), part,
+                            ctx->stream));
+  return NMF_OK;
+}
+
+// Relative error of the current (W, Ht) into relerr[slot]. q_current says
+// whether w.Q holds the Gram of the current Ht (the sparse form needs it).
+template <typename T>
+nmf_status objective(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
+                     Work<T>& w, int slot) {
+  hipStream_t st = ctx->stream;
+  if (pb.sparse) {
+    if constexpr (sizeof(T) == 4) {
+      // <W^T W, H H^T> covers the zeros; both Grams of the current factors.
+      nmf_status s = gram<T>(ctx, w.W, m, KP, w.S, w.part);
+      if (s != NMF_OK) return s;
+      s = gram<T>(ctx, w.Ht, n, KP, w.Q, w.part);
+      if (s != NMF_OK) return s;
+      HIP_TRY(nmfk::csr_residual_sq(pb.rp, pb.ci, pb.cv, m, w.W, w.Ht, KP, w.obj_part, st));
+      HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, nmfk::csr_residual_partials(m), w.S, w.Q, KP,
+                                     w.normA, w.relerr + slot, st));
+      return NMF_OK;
+    }
+    return NMF_EINVAL;
+  }
+  HIP_TRY(nmfk::residual_sq<T>(pb.A, pb.lda, m, n, w.W, w.Ht, KP, w.obj_part, st));
+  HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, nmfk::residual_partials<T>(m, n), (const T*)nullptr,
+                                 (const T*)nullptr, KP, w.normA, w.relerr + slot, st));
+  (void)k;
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status norm_sq_A(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, Work<T>& w) {
+  hipStream_t st = ctx->stream;
+  if (pb.sparse) {
+    if constexpr (sizeof(T) == 4) {
+      const int64_t np = std::min<int64_t>(w.obj_np, 1024);
+      HIP_TRY(nmfk::csr_sumsq(pb.cv, pb.nnz, w.obj_part, np, st));
+      HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, np, (const T*)nullptr, (const T*)nullptr, 0,
+                                     (const double*)nullptr, w.normA, st));
+      return NMF_OK;
+    }
+    return NMF_EINVAL;
+  }
+  HIP_TRY(nmfk::sumsq<T>(pb.A, pb.lda, m, n, w.obj_part, st));
+  HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, nmfk::sumsq_partials<T>(m, n), (const T*)nullptr,
+                                 (const T*)nullptr, 0, (const double*)nullptr, w.normA, st));
+  return NMF_OK;
+}
+
+// Algorithm 1 on the prepared workspace.
+template <typename T>
+nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
+                      const nmf_opts* o, Work<T>& w, bool want_obj, Timers& tm) {
+  hipStream_t st = ctx->stream;
+  nmf_status s = NMF_OK;
+#define RUN(x) do { s = (x); if (s != NMF_OK) return s; } while (0)
+  if (want_obj) {
+    tm.mark(PH_OBJ);
+    RUN(norm_sq_A<T>(ctx, pb, m, n, w));
+    RUN(objective<T>(ctx, pb, m, n, k, KP, w, 0));
+  }
+  for (int t = 0; t < o->iters; ++t) {
+    // W given H: Q = H H^T, P = A H^T, UpdateW.
+    tm.mark(PH_GRAM);
+    RUN(gram<T>(ctx, w.Ht, n, KP, w.Q, w.part));
+    tm.mark(PH_MM);
+    RUN(product_AF<T>(ctx, pb, m, n, w.Ht, KP, w.P, w.part));
+    tm.mark(PH_LUC);
+    RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots));
+    // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
+    tm.mark(PH_GRAM);
+    RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
+    if (o->algo == NMF_HALS) {
+      tm.mark(PH_LUC);
+      HIP_TRY(nmfk::hals_normalize<T>(w.W, m, w.Ht, n, w.S, w.norms, k, KP, st));
+    }
+    tm.mark(PH_MM);
+    RUN(product_AtF<T>(ctx, pb, m, n, w.W, KP, w.R, w.part));
+    tm.mark(PH_LUC);
+    RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots));
+    if (want_obj) {
+      tm.mark(PH_OBJ);
+      RUN(objective<T>(ctx, pb, m, n, k, KP, w, t + 1));
+    }
+  }
+  tm.mark(PH_END);
+#undef RUN
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_obj,
+                       double* rel_err, nmf_stats* stats, Timers& tm, hipEvent_t t0,
+                       hipEvent_t t1) {
+  long long piv = 0;
+  const bool need_status = o->algo == NMF_ABPP || o->check_input;
+  if (need_status) {
+    nmf_status s = read_status(ctx, w.status, w.pivots, &piv);
+    if (s != NMF_OK) return s;
+  }
+  if (rel_err && want_obj) {
+    HIP_TRY(hipMemcpyAsync(rel_err, w.relerr, sizeof(double) * (o->iters + 1),
+                           hipMemcpyDeviceToHost, ctx->stream));
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    HIP_TRY(hipEventSynchronize(t1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+    stats->ms_total = ms;
+    tm.collect(stats);
+    stats->bpp_pivots = piv;
+  }
+  if (rel_err || stats) HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t lda, int k,
+                      const nmf_opts* o, T* W, T* H, double* rel_err, nmf_stats* stats) {
+  const int KP = kp_dense(k);
+  const bool want_obj = o->objective != NMF_OBJ_NONE;
+  const int64_t obj_np = std::max(nmfk::residual_partials<T>(m, n), nmfk::sumsq_partials<T>(m, n));
+  Carve cv;
+  size_t off[12];
+  plan_work<T>(m, n, KP, o->iters, obj_np, 0, cv, off);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  Work<T> w = bind_work<T>(ctx, off, obj_np);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(hipMemsetAsync(w.status, 0, 4 * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(w.pivots, 0, 2 * sizeof(unsigned long long), st));
+  if (o->check_input) HIP_TRY(nmfk::check_dense<T>(A, lda, m, n, w.status + 1, st));
+  Timers tm;
+  tm.on = stats && o->timers;
+  tm.st = st;
+  tm.mark(PH_SETUP);
+  HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, st));
+  HIP_TRY(nmfk::transpose_in<T>(H, k, n, w.Ht, KP, st));
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, st));
+  }
+  Prob<T> pb;
+  pb.A = A;
+  pb.lda = lda;
+  s = run_au_nmf<T>(ctx, pb, m, n, k, KP, o, w, want_obj, tm);
+  if (stats) HIP_TRY(hipEventRecord(t1, st));
+  if (s == NMF_OK) {
+    HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
+    HIP_TRY(nmfk::transpose_out<T>(w.Ht, k, n, KP, H, st));
+    s = finish_call<T>(ctx, o, w, want_obj, rel_err, stats, tm, t0, t1);
+  }
+  if (t0) hipEventDestroy(t0);
+  if (t1) hipEventDestroy(t1);
+  return s;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Exported C ABI
+// ===========================================================================
+extern "C" {
+
+void nmf_default_opts(nmf_opts* o) {
+  if (!o) return;
+  o->algo = NMF_MU;
+  o->iters = 0;
+  o->eps_mu = 1e-16;
+  o->max_pivots = 0;
+  o->objective = NMF_OBJ_NONE;
+  o->timers = 0;
+  o->check_input = 0;
+}
+
+const char* nmf_status_str(nmf_status s) {
+  switch (s) {
+    case NMF_OK: return "NMF_OK";
+    case NMF_EINVAL: return "NMF_EINVAL";
+    case NMF_ENOMEM: return "NMF_ENOMEM";
+    case NMF_EDEVICE: return "NMF_EDEVICE";
+    case NMF_ENUMERIC: return "NMF_ENUMERIC";
+    case NMF_ENOTCONV: return "NMF_ENOTCONV";
+  }
+  return "NMF_UNKNOWN";
+}
+
+const char* nmf_last_error(const nmf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+nmf_status nmf_create(nmf_ctx** out, int device, void* hip_stream) {
+  if (!out) return NMF_EINVAL;
+  *out = nullptr;
+  if (device == -1) {
+    nmf_ctx* c = new nmf_ctx();
+    c->device = -1;
+    *out = c;
+    return NMF_OK;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return NMF_EDEVICE;
+  if (device < 0 || device >= count) return NMF_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return NMF_EDEVICE;
+  nmf_ctx* c = new nmf_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return NMF_OK;
+}
+
+void nmf_destroy(nmf_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->ws && ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->ws);
+  }
+  delete ctx;
+}
+
+nmf_status nmf_set_stream(nmf_ctx* ctx, void* hip_stream) {
+  if (!ctx) return NMF_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return NMF_OK;
+}
+
+nmf_status nmf_dense(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const void* A,
+                     int64_t lda, int k, const nmf_opts* opts, void* W, void* H, double* rel_err,
+                     nmf_stats* stats) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if ((s = check_opts(ctx, opts, k, rel_err != nullptr)) != NMF_OK) return s;
+  if (!A || !W || !H) return fail(ctx, NMF_EINVAL, "null A, W or H");
+  if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
+  if (dtype != NMF_F32 && dtype != NMF_F64) return fail(ctx, NMF_EINVAL, "unknown dtype");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return dense_impl<float>(ctx, m, n, (const float*)A, lda, k, opts, (float*)W, (float*)H,
+                             rel_err, stats);
+  return dense_impl<double>(ctx, m, n, (const double*)A, lda, k, opts, (double*)W, (double*)H,
+                            rel_err, stats);
+}
+
+nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                   const int32_t* colidx, const float* vals, int k, const nmf_opts* opts,
+                   float* W, float* H, double* rel_err, nmf_stats* stats) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if ((s = check_opts(ctx, opts, k, rel_err != nullptr)) != NMF_OK) return s;
+  if (!rowptr || !W || !H || (nnz > 0 && (!colidx || !vals)))
+    return fail(ctx, NMF_EINVAL, "null CSR array, W or H");
+  if (nnz < 0 || nnz > ((int64_t)1 << 40)) return fail(ctx, NMF_EINVAL, "bad nnz");
+  if (n > INT32_MAX) return fail(ctx, NMF_EINVAL, "n must fit int32 column ids");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  typedef float T;
+  const int KP = kp_sparse(k);
+  const bool want_obj = opts->objective != NMF_OBJ_NONE;
+  const int64_t obj_np = std::max<int64_t>(nmfk::csr_residual_partials(m), 1024);
+  Carve cv;
+  size_t off[12];
+  plan_work<T>(m, n, KP, opts->iters, obj_np, 0, cv, off);
+  const size_t o_rpt = cv.take<int64_t>(n + 1);
+  const size_t o_cit = cv.take<int32_t>(nnz);
+  const size_t o_cvt = cv.take<float>(nnz);
+  const size_t o_tw = cv.take<char>(nmfk::csr_transpose_work_bytes(m, n, nnz));
+  if ((s = ensure_ws(ctx, cv.off)) != NMF_OK) return s;
+  Work<T> w = bind_work<T>(ctx, off, obj_np);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(hipMemsetAsync(w.status, 0, 4 * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(w.pivots, 0, 2 * sizeof(unsigned long long), st));
+  if (opts->check_input) {
+    HIP_TRY(nmfk::check_csr(rowptr, colidx, vals, m, n, nnz, w.status + 1, st));
+    // Structure must be valid before the transpose and SpMM read it.
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, w.status + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (flag) return fail(ctx, NMF_ENUMERIC, "CSR input malformed or has NaN/Inf/negative values");
+  }
+  Timers tm;
+  tm.on = stats && opts->timers;
+  tm.st = st;
+  tm.mark(PH_SETUP);
+  Prob<T> pb;
+  pb.sparse = true;
+  pb.rp = rowptr;
+  pb.ci = colidx;
+  pb.cv = vals;
+  pb.nnz = nnz;
+  pb.rpt = at<int64_t>(ctx, o_rpt);
+  pb.cit = at<int32_t>(ctx, o_cit);
+  pb.cvt = at<float>(ctx, o_cvt);
+  HIP_TRY(nmfk::csr_transpose(rowptr, colidx, vals, m, n, nnz, (int64_t*)pb.rpt, (int32_t*)pb.cit,
+                              (float*)pb.cvt, at<char>(ctx, o_tw), st));
+  HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, st));
+  HIP_TRY(nmfk::transpose_in<T>(H, k, n, w.Ht, KP, st));
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, st));
+  }
+  s = run_au_nmf<T>(ctx, pb, m, n, k, KP, opts, w, want_obj, tm);
+  if (stats) HIP_TRY(hipEventRecord(t1, st));
+  if (s == NMF_OK) {
+    HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
+    HIP_TRY(nmfk::transpose_out<T>(w.Ht, k, n, KP, H, st));
+    s = finish_call<T>(ctx, opts, w, want_obj, rel_err, stats, tm, t0, t1);
+  }
+  if (t0) hipEventDestroy(t0);
+  if (t1) hipEventDestroy(t1);
+  return s;
+}
+
+}  // extern "C"
+
+// ---- per-step entry points ------------------------------------------------
+
+namespace {
+template <typename T>
+nmf_status gram_impl(nmf_ctx* ctx, int64_t rows, int k, const T* X, int64_t ldx, T* G) {
+  const int KP = kp_dense(k);
+  Carve cv;
+  const size_t oX = cv.take<T>(rows * KP);
+  const size_t oG = cv.take<T>(KP * KP);
+  const size_t oP = cv.take<T>(gram_splits(rows) * KP * KP);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  T* Xp = at<T>(ctx, oX);
+  T* Gp = at<T>(ctx, oG);
+  hipStream_t st = ctx->stream;
+  if (ldx == k) HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
+  else {
+    HIP_TRY(hipMemsetAsync(Xp, 0, sizeof(T) * rows * KP, st));
+    HIP_TRY(hipMemcpy2DAsync(Xp, KP * sizeof(T), X, ldx * sizeof(T), k * sizeof(T), rows,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  if ((s = gram<T>(ctx, Xp, rows, KP, Gp, at<T>(ctx, oP))) != NMF_OK) return s;
+  HIP_TRY(nmfk::unpad_rows<T>(Gp, k, k, KP, G, st));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status pad_any(nmf_ctx* ctx, const T* X, int64_t rows, int k, int64_t ldx, T* Xp, int KP) {
+  hipStream_t st = ctx->stream;
+  if (ldx == k) HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
+  else {
+    HIP_TRY(hipMemsetAsync(Xp, 0, sizeof(T) * rows * KP, st));
+    HIP_TRY(hipMemcpy2DAsync(Xp, KP * sizeof(T), X, ldx * sizeof(T), k * sizeof(T), rows,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status dense_prod_impl(nmf_ctx* ctx, bool transA, int64_t m, int64_t n, const T* A,
+                           int64_t lda, int k, const T* F, int64_t ldf, T* Out) {
+  const int KP = kp_dense(k);
+  const int64_t frows = transA ? m : n, orows = transA ? n : m;
+  const int64_t splits = transA ? product_splits(cdiv(n, mw_rows<T>()), m)
+                                : product_splits(cdiv(m, mw_rows<T>()), n);
+  Carve cv;
+  const size_t oF = cv.take<T>(frows * KP);
+  const size_t oO = cv.take<T>(orows * KP);
+  const size_t oP = cv.take<T>(splits > 1 ? splits * orows * KP : 1);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  T* Fp = at<T>(ctx, oF);
+  T* Op = at<T>(ctx, oO);
+  if ((s = pad_any<T>(ctx, F, frows, k, ldf, Fp, KP)) != NMF_OK) return s;
+  Prob<T> pb;
+  pb.A = A;
+  pb.lda = lda;
+  s = transA ? product_AtF<T>(ctx, pb, m, n, Fp, KP, Op, at<T>(ctx, oP))
+             : product_AF<T>(ctx, pb, m, n, Fp, KP, Op, at<T>(ctx, oP));
+  if (s != NMF_OK) return s;
+  HIP_TRY(nmfk::unpad_rows<T>(Op, orows, k, KP, Out, ctx->stream));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, const T* Pm,
+                       T* X, const nmf_opts* o, long long* pivots) {
+  const int KP = kp_dense(k);
+  Carve cv;
+  const size_t oG = cv.take<T>(KP * KP);
+  const size_t oP = cv.take<T>(rows * KP);
+  const size_t oX = cv.take<T>(rows * KP);
+  const size_t oS = cv.take<int>(4);
+  const size_t oV = cv.take<unsigned long long>(2);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  T* Gp = at<T>(ctx, oG);
+  T* Pp = at<T>(ctx, oP);
+  T* Xp = at<T>(ctx, oX);
+  int* dst = at<int>(ctx, oS);
+  unsigned long long* dpv = at<unsigned long long>(ctx, oV);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(hipMemsetAsync(dst, 0, 4 * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(dpv, 0, 2 * sizeof(unsigned long long), st));
+  HIP_TRY(nmfk::pad_rows<T>(G, k, k, Gp, KP, st));
+  if (KP > k) HIP_TRY(hipMemsetAsync(Gp + (size_t)k * KP, 0, sizeof(T) * (KP - k) * KP, st));
+  HIP_TRY(nmfk::pad_rows<T>(Pm, rows, k, Pp, KP, st));
+  HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
+  if ((s = local_update<T>(ctx, algo, Xp, Pp, Gp, rows, k, KP, o, dst, dpv)) != NMF_OK) return s;
+  HIP_TRY(nmfk::unpad_rows<T>(Xp, rows, k, KP, X, st));
+  if (algo == NMF_ABPP) return read_status(ctx, dst, dpv, pivots);
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status normalize_impl(nmf_ctx* ctx, int64_t m, int64_t n, int k, T* W, T* Ht, T* S,
+                          T* norms) {
+  const int KP = kp_dense(k);
+  Carve cv;
+  const size_t oW = cv.take<T>(m * KP);
+  const size_t oH = cv.take<T>(n * KP);
+  const size_t oS = cv.take<T>(KP * KP);
+  const size_t oN = cv.take<T>(KP);
+  const size_t oP = cv.take<T>(gram_splits(m) * KP * KP);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  T* Wp = at<T>(ctx, oW);
+  T* Hp = at<T>(ctx, oH);
+  T* Sp = at<T>(ctx, oS);
+  T* Np = at<T>(ctx, oN);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(nmfk::pad_rows<T>(W, m, k, Wp, KP, st));
+  HIP_TRY(nmfk::pad_rows<T>(Ht, n, k, Hp, KP, st));
+  if ((s = gram<T>(ctx, Wp, m, KP, Sp, at<T>(ctx, oP))) != NMF_OK) return s;
+  HIP_TRY(nmfk::hals_normalize<T>(Wp, m, Hp, n, Sp, Np, k, KP, st));
+  HIP_TRY(nmfk::unpad_rows<T>(Wp, m, k, KP, W, st));
+  HIP_TRY(nmfk::unpad_rows<T>(Hp, n, k, KP, Ht, st));
+  if (S) HIP_TRY(nmfk::unpad_rows<T>(Sp, k, k, KP, S, st));
+  if (norms) HIP_TRY(hipMemcpyAsync(norms, Np, sizeof(T) * k, hipMemcpyDeviceToDevice, st));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status relerr_impl(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, const T* W,
+                       const T* Ht, double* out) {
+  const int KP = pb.sparse ? kp_sparse(k) : kp_dense(k);
+  const int64_t obj_np = pb.sparse ? std::max<int64_t>(nmfk::csr_residual_partials(m), 1024)
+                                   : std::max(nmfk::residual_partials<T>(m, n),
+                                              nmfk::sumsq_partials<T>(m, n));
+  Carve cv;
+  size_t off[12];
+  plan_work<T>(m, n, KP, 0, obj_np, 0, cv, off);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  Work<T> w = bind_work<T>(ctx, off, obj_np);
+  HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, ctx->stream));
+  HIP_TRY(nmfk::pad_rows<T>(Ht, n, k, w.Ht, KP, ctx->stream));
+  if ((s = norm_sq_A<T>(ctx, pb, m, n, w)) != NMF_OK) return s;
+  if ((s = objective<T>(ctx, pb, m, n, k, KP, w, 0)) != NMF_OK) return s;
+  HIP_TRY(hipMemcpyAsync(out, w.relerr, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return NMF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+nmf_status nmf_gram(nmf_ctx* ctx, nmf_dtype dtype, int64_t rows, int k, const void* X,
+                    int64_t ldx, void* G) {
+  nmf_status s = check_common(ctx, rows, 1, k);
+  if (s != NMF_OK) return s;
+  if (!X || !G) return fail(ctx, NMF_EINVAL, "null X or G");
+  if (ldx < k) return fail(ctx, NMF_EINVAL, "ldx < k");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32) return gram_impl<float>(ctx, rows, k, (const float*)X, ldx, (float*)G);
+  if (dtype == NMF_F64) return gram_impl<double>(ctx, rows, k, (const double*)X, ldx, (double*)G);
+  return fail(ctx, NMF_EINVAL, "unknown dtype");
+}
+
+}  // extern "C"
+
+static nmf_status dense_prod(nmf_ctx* ctx, bool transA, nmf_dtype dtype, int64_t m, int64_t n,
+                             const void* A, int64_t lda, int k, const void* F, int64_t ldf,
+                             void* Out) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if (!A || !F || !Out) return fail(ctx, NMF_EINVAL, "null A, F or output");
+  if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
+  if (ldf < k) return fail(ctx, NMF_EINVAL, "ldf < k");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return dense_prod_impl<float>(ctx, transA, m, n, (const float*)A, lda, k, (const float*)F,
+                                  ldf, (float*)Out);
+  if (dtype == NMF_F64)
+    return dense_prod_impl<double>(ctx, transA, m, n, (const double*)A, lda, k,
+                                   (const double*)F, ldf, (double*)Out);
+  return fail(ctx, NMF_EINVAL, "unknown dtype");
+}
+
+extern "C" {
+
+nmf_status nmf_dense_AF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const void* A,
+                        int64_t lda, int k, const void* F, int64_t ldf, void* P) {
+  return dense_prod(ctx, false, dtype, m, n, A, lda, k, F, ldf, P);
+}
+
+nmf_status nmf_dense_AtF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const void* A,
+                         int64_t lda, int k, const void* F, int64_t ldf, void* R) {
+  return dense_prod(ctx, true, dtype, m, n, A, lda, k, F, ldf, R);
+}
+
+nmf_status nmf_csr_AF(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                      const int32_t* colidx, const float* vals, int k, const float* F, float* P) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if (!rowptr || !F || !P || (nnz > 0 && (!colidx || !vals)))
+    return fail(ctx, NMF_EINVAL, "null CSR array, F or P");
+  if (nnz < 0) return fail(ctx, NMF_EINVAL, "bad nnz");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  const int KP = kp_sparse(k);
+  Carve cv;
+  const size_t oF = cv.take<float>(n * KP);
+  const size_t oO = cv.take<float>(m * KP);
+  if ((s = ensure_ws(ctx, cv.off)) != NMF_OK) return s;
+  float* Fp = at<float>(ctx, oF);
+  float* Op = at<float>(ctx, oO);
+  HIP_TRY(nmfk::pad_rows<float>(F, n, k, Fp, KP, ctx->stream));
+  HIP_TRY(nmfk::csr_spmm(rowptr, colidx, vals, m, Fp, KP, Op, ctx->stream));
+  HIP_TRY(nmfk::unpad_rows<float>(Op, m, k, KP, P, ctx->stream));
+  return NMF_OK;
+}
+
+nmf_status nmf_csr_transpose(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
+                             const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                             int64_t* rowptr_t, int32_t* colidx_t, float* vals_t) {
+  nmf_status s = check_common(ctx, m, n, 1);
+  if (s != NMF_OK) return s;
+  if (!rowptr || !rowptr_t || (nnz > 0 && (!colidx || !vals || !colidx_t || !vals_t)))
+    return fail(ctx, NMF_EINVAL, "null CSR array");
+  if (nnz < 0 || n > INT32_MAX || m > INT32_MAX) return fail(ctx, NMF_EINVAL, "bad sizes");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  Carve cv;
+  const size_t oT = cv.take<char>(nmfk::csr_transpose_work_bytes(m, n, nnz));
+  if ((s = ensure_ws(ctx, cv.off)) != NMF_OK) return s;
+  HIP_TRY(nmfk::csr_transpose(rowptr, colidx, vals, m, n, nnz, rowptr_t, colidx_t, vals_t,
+                              at<char>(ctx, oT), ctx->stream));
+  return NMF_OK;
+}
+
+nmf_status nmf_update(nmf_ctx* ctx, nmf_algo algo, nmf_dtype dtype, int64_t rows, int k,
+                      const void* G, const void* P, void* X, const nmf_opts* opts,
+                      long long* pivots) {
+  nmf_status s = check_common(ctx, rows, 1, k);
+  if (s != NMF_OK) return s;
+  if (!G || !P || !X) return fail(ctx, NMF_EINVAL, "null G, P or X");
+  nmf_opts o;
+  nmf_default_opts(&o);
+  if (opts) o = *opts;
+  o.algo = algo;
+  if ((s = check_opts(ctx, &o, k, false)) != NMF_OK) return s;
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return update_impl<float>(ctx, algo, rows, k, (const float*)G, (const float*)P, (float*)X, &o,
+                              pivots);
+  if (dtype == NMF_F64)
+    return update_impl<double>(ctx, algo, rows, k, (const double*)G, (const double*)P,
+                               (double*)X, &o, pivots);
+  return fail(ctx, NMF_EINVAL, "unknown dtype");
+}
+
+nmf_status nmf_hals_normalize(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, int k,
+                              void* W, void* Ht, void* S, void* norms) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if (!W || !Ht) return fail(ctx, NMF_EINVAL, "null W or Ht");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return normalize_impl<float>(ctx, m, n, k, (float*)W, (float*)Ht, (float*)S, (float*)norms);
+  if (dtype == NMF_F64)
+    return normalize_impl<double>(ctx, m, n, k, (double*)W, (double*)Ht, (double*)S,
+                                  (double*)norms);
+  return fail(ctx, NMF_EINVAL, "unknown dtype");
+}
+
+nmf_status nmf_dense_relerr(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const void* A,
+                            int64_t lda, int k, const void* W, const void* Ht, double* out) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if (!A || !W || !Ht || !out) return fail(ctx, NMF_EINVAL, "null argument");
+  if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32) {
+    Prob<float> pb;
+    pb.A = (const float*)A;
+    pb.lda = lda;
+    return relerr_impl<float>(ctx, pb, m, n, k, (const float*)W, (const float*)Ht, out);
+  }
+  if (dtype == NMF_F64) {
+    Prob<double> pb;
+    pb.A = (const double*)A;
+    pb.lda = lda;
+    return relerr_impl<double>(ctx, pb, m, n, k, (const double*)W, (const double*)Ht, out);
+  }
+  return fail(ctx, NMF_EINVAL, "unknown dtype");
+}
+
+nmf_status nmf_csr_relerr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
+                          const int32_t* colidx, const float* vals, int k, const float* W,
+                          const float* Ht, double* out) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if (!rowptr || !W || !Ht || !out || (nnz > 0 && (!colidx || !vals)))
+    return fail(ctx, NMF_EINVAL, "null argument");
+  if (nnz < 0) return fail(ctx, NMF_EINVAL, "bad nnz");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  Prob<float> pb;
+  pb.sparse = true;
+  pb.rp = rowptr;
+  pb.ci = colidx;
+  pb.cv = vals;
+  pb.nnz = nnz;
+  return relerr_impl<float>(ctx, pb, m, n, k, W, Ht, out);
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Host-side interface between the C ABI (api.hip) and the kernel files.
+// Every function enqueues work on the given stream and returns the launch
+// status; none of them allocates memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nmfk {
+
+enum class GemmKind { NN, TN, TN_GRAM };
+
+// D (M x N) = X * Y (NN, X is M x K) or X^T * Y (TN, X is K x M); Y is K x N.
+// N must be a multiple of 16 between 16 and 128.
+template <typename T> struct GemmArgs {
+  const T* X; int64_t ldx;
+  const T* Y; int64_t ldy;
+  T* D; int64_t ldd;
+  int64_t M, N, K;
+};
+
+// `part` must hold splits * M * N elements when splits > 1.
+template <typename T>
+hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a, int64_t splits, T* part,
+                    hipStream_t st);
+
+// Local updates on rows x KP row-major factors (leading dimension KP); k is
+// the true rank, entries k..KP-1 are zero padding and stay zero.
+template <typename T>
+hipError_t mu_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, T eps,
+                   hipStream_t st);
+template <typename T>
+hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
+                     hipStream_t st);
+
+// HALS normalisation: s_i = sqrt(S[i][i]); W[:, i] /= s_i, Ht[:, i] *= s_i and
+// S[i][j] /= s_i s_j for s_i > 0. norms (nullable) receives s.
+template <typename T>
+hipError_t hals_normalize(T* W, int64_t m, T* Ht, int64_t n, T* S, T* norms, int k, int KP,
+                          hipStream_t st);
+
+// Copies between the caller's layouts (ld = k) and the padded row layout.
+template <typename T>
+hipError_t pad_rows(const T* src, int64_t rows, int k, T* dst, int KP, hipStream_t st);
+template <typename T>
+hipError_t unpad_rows(const T* src, int64_t rows, int k, int KP, T* dst, hipStream_t st);
+// H (k x n, ld n) -> Ht (n x KP) and back.
+template <typename T>
+hipError_t transpose_in(const T* H, int k, int64_t n, T* Ht, int KP, hipStream_t st);
+template <typename T>
+hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_t st);
+
+// Objective pieces. Each writes one double partial per block into `partial`
+// (capacity given by *_partials) and a final reduce sums them in order.
+template <typename T>
+int64_t residual_partials(int64_t m, int64_t n);
+template <typename T>
+hipError_t residual_sq(const T* A, int64_t lda, int64_t m, int64_t n, const T* W, const T* Ht,
+                       int KP, double* partial, hipStream_t st);
+template <typename T>
+int64_t sumsq_partials(int64_t m, int64_t n);
+template <typename T>
+hipError_t sumsq(const T* A, int64_t lda, int64_t m, int64_t n, double* partial,
+                 hipStream_t st);
+// out[slot] = sqrt(max(0, sum(partial[0..np)) + add) / ref) where add is the
+// <G1, G2> Frobenius product of two KP x KP matrices (nullable) and ref the
+// double at *ref_sq (nullable: out = the sum itself, no sqrt).
+template <typename T>
+hipError_t finish_relerr(const double* partial, int64_t np, const T* G1, const T* G2, int KP,
+                         const double* ref_sq, double* out, hipStream_t st);
+
+// Sparse (CSR, float32 values).
+hipError_t csr_spmm(const int64_t* rowptr, const int32_t* colidx, const float* vals, int64_t m,
+                    const float* F, int KP, float* P, hipStream_t st);
+// `work` holds csr_transpose_work_bytes(m, n, nnz) bytes of scratch.
+hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                         int64_t m, int64_t n, int64_t nnz, int64_t* rowptr_t,
+                         int32_t* colidx_t, float* vals_t, void* work, hipStream_t st);
+size_t csr_transpose_work_bytes(int64_t m, int64_t n, int64_t nnz);
+int64_t csr_residual_partials(int64_t m);
+hipError_t csr_residual_sq(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                           int64_t m, const float* W, const float* Ht, int KP, double* partial,
+                           hipStream_t st);
+hipError_t csr_sumsq(const float* vals, int64_t nnz, double* partial, int64_t np,
+                     hipStream_t st);
+// Input checks: sets *flag (device int) nonzero on a bad entry.
+template <typename T>
+hipError_t check_dense(const T* A, int64_t lda, int64_t m, int64_t n, int* flag,
+                       hipStream_t st);
+// flag bit 1: bad value; bit 2: bad structure (row bounds, column range or order).
+hipError_t check_csr(const int64_t* rowptr, const int32_t* colidx, const float* vals, int64_t m,
+                     int64_t n, int64_t nnz, int* flag, hipStream_t st);
+
+// Batched NNLS by block principal pivoting: each row x of X (rows x KP)
+// becomes argmin_{x>=0} 1/2 x^T G x - p^T x. status (device int) is set to
+// 1 on a singular passive-set system, 2 on pivot-cap exhaustion; pivots
+// (device long long) accumulates the passive-set solves.
+template <typename T>
+hipError_t bpp_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, int max_pivots,
+                    int* status, unsigned long long* pivots, hipStream_t st);
+
+}  // namespace nmfk

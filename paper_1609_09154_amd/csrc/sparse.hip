@@ -1,0 +1,358 @@
+// Sparse A (CSR, float32): the large products A H^T and (W^T A)^T = A^T W of
+// Algorithm 1 as row-wise SpMM, the one-time CSR transpose that gives A^T,
+// and the sparse forms of the objective and input checks.
+//
+// SpMM layout: one wavefront per output row. The wave splits into groups of
+// KP/4 lanes; each group takes one stored entry (j, a_ij) at a time and
+// gathers the 16-byte slices of row j of the dense operand (n x KP, row
+// major), so a group reads one whole dense row with one instruction and the
+// wave keeps 64/(KP/4) gathers in flight per step. Group partial sums are
+// combined with cross-lane shuffles at the end of the row, in a fixed order.
+#include "common.h"
+#include "kernels.h"
+
+namespace nmfk {
+
+template <int KP>
+__global__ __launch_bounds__(256) void csr_spmm_kernel(const int64_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ colidx,
+                                                       const float* __restrict__ vals,
+                                                       int64_t m, const float* __restrict__ F,
+                                                       float* __restrict__ P) {
+  constexpr int LPN = KP / 4;     // lanes per stored entry
+  constexpr int GPW = 64 / LPN;   // entries in flight per wave step
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / LPN, sub = lane % LPN;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= m) return;
+  const int64_t b = rowptr[row], e = rowptr[row + 1];
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  int64_t p = b + grp;
+  // unrolled by 4 entries per group
+  for (; p + 3 * GPW < e; p += 4 * GPW) {
+    int32_t j[4];
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = __builtin_nontemporal_load(colidx + p + u * GPW);
+      v[u] = __builtin_nontemporal_load(vals + p + u * GPW);
+    }
+    float4 f[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) f[u] = *reinterpret_cast<const float4*>(F + (int64_t)j[u] * KP + 4 * sub);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc.x = fmaf(v[u], f[u].x, acc.x);
+      acc.y = fmaf(v[u], f[u].y, acc.y);
+      acc.z = fmaf(v[u], f[u].z, acc.z);
+      acc.w = fmaf(v[u], f[u].w, acc.w);
+    }
+  }
+  for (; p < e; p += GPW) {
+    const int32_t j = colidx[p];
+    const float v = vals[p];
+    const float4 f = *reinterpret_cast<const float4*>(F + (int64_t)j * KP + 4 * sub);
+    acc.x = fmaf(v, f.x, acc.x);
+    acc.y = fmaf(v, f.y, acc.y);
+    acc.z = fmaf(v, f.z, acc.z);
+    acc.w = fmaf(v, f.w, acc.w);
+  }
+#pragma unroll
+  for (int off = LPN; off < 64; off <<= 1) {
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+    acc.z += __shfl_xor(acc.z, off, 64);
+    acc.w += __shfl_xor(acc.w, off, 64);
+  }
+  if (grp == 0) *reinterpret_cast<float4*>(P + row * KP + 4 * sub) = acc;
+}
+
+hipError_t csr_spmm(const int64_t* rowptr, const int32_t* colidx, const float* vals, int64_t m,
+                    const float* F, int KP, float* P, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)cdiv(m, 4);
+  switch (KP) {
+    case 16: csr_spmm_kernel<16><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
+    case 32: csr_spmm_kernel<32><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
+    case 64: csr_spmm_kernel<64><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
+    case 128: csr_spmm_kernel<128><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return NMF_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// CSR transpose: count entries per column, exclusive scan into the new row
+// pointers, scatter (slot order within a column is arbitrary), then put each
+// new row in increasing column order by ranking its entries. Keys within a
+// row are distinct, so the result is unique and the same on every run.
+// ---------------------------------------------------------------------------
+__global__ void count_cols_kernel(const int32_t* __restrict__ colidx, int64_t nnz,
+                                  int32_t* __restrict__ counts) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nnz) atomicAdd(&counts[colidx[p]], 1);
+}
+
+constexpr int SCAN_BLOCK = 1024;  // elements per block (256 threads x 4)
+
+// Exclusive scan of 1024 int64 values held 4 per thread; returns block total.
+__device__ int64_t block_exclusive_scan4(int64_t (&v)[4]) {
+  __shared__ int64_t sh[256];
+  const int t = threadIdx.x;
+  int64_t s = v[0] + v[1] + v[2] + v[3];
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int64_t incl = sh[t];
+  const int64_t total = sh[255];
+  int64_t run = incl - s;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t x = v[q];
+    v[q] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
+__global__ __launch_bounds__(256) void scan_block_sums_kernel(const int32_t* __restrict__ counts,
+                                                              int64_t n,
+                                                              int64_t* __restrict__ bsum) {
+  int64_t v[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + 4 * threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = base + q < n ? counts[base + q] : 0;
+  const int64_t tot = block_exclusive_scan4(v);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of nb block sums, in place.
+__global__ __launch_bounds__(256) void scan_top_kernel(int64_t* __restrict__ bsum, int64_t nb) {
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nb; c0 += SCAN_BLOCK) {
+    int64_t v[4];
+    const int64_t base = c0 + 4 * threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = base + q < nb ? bsum[base + q] : 0;
+    const int64_t tot = block_exclusive_scan4(v);
+    const int64_t cy = carry;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (base + q < nb) bsum[base + q] = v[q] + cy;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = cy + tot;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restrict__ counts,
+                                                         int64_t n,
+                                                         const int64_t* __restrict__ bsum,
+                                                         int64_t nnz,
+                                                         int64_t* __restrict__ out) {
+  int64_t v[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + 4 * threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = base + q < n ? counts[base + q] : 0;
+  block_exclusive_scan4(v);
+  const int64_t off = bsum[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (base + q < n) out[base + q] = v[q] + off;
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = nnz;
+}
+
+// One thread per source row: scatter its entries into their new rows.
+__global__ void scatter_kernel(const int64_t* __restrict__ rowptr,
+                               const int32_t* __restrict__ colidx,
+                               const float* __restrict__ vals, int64_t m,
+                               const int64_t* __restrict__ rowptr_t,
+                               int32_t* __restrict__ cursor, int32_t* __restrict__ tmp_key,
+                               float* __restrict__ tmp_val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    const int32_t j = colidx[p];
+    const int64_t pos = rowptr_t[j] + atomicAdd(&cursor[j], 1);
+    tmp_key[pos] = (int32_t)i;
+    tmp_val[pos] = vals[p];
+  }
+}
+
+// One wave per new row: rank each entry among the row's keys and write it
+// to its sorted slot.
+__global__ __launch_bounds__(256) void rank_sort_kernel(const int64_t* __restrict__ rowptr_t,
+                                                        int64_t n,
+                                                        const int32_t* __restrict__ tmp_key,
+                                                        const float* __restrict__ tmp_val,
+                                                        int32_t* __restrict__ colidx_t,
+                                                        float* __restrict__ vals_t) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const int64_t b = rowptr_t[j], e = rowptr_t[j + 1];
+  for (int64_t p = b + lane; p < e; p += 64) {
+    const int32_t key = tmp_key[p];
+    int64_t rank = 0;
+    for (int64_t q = b; q < e; ++q) rank += tmp_key[q] < key ? 1 : 0;
+    colidx_t[b + rank] = key;
+    vals_t[b + rank] = tmp_val[p];
+  }
+}
+
+size_t csr_transpose_work_bytes(int64_t m, int64_t n, int64_t nnz) {
+  (void)m;
+  const size_t nb = (size_t)cdiv(n, SCAN_BLOCK);
+  return round_up((size_t)n * 4, 256) + round_up(nb * 8, 256) + round_up((size_t)nnz * 4, 256) * 2;
+}
+
+hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                         int64_t m, int64_t n, int64_t nnz, int64_t* rowptr_t,
+                         int32_t* colidx_t, float* vals_t, void* work, hipStream_t st) {
+  char* w = (char*)work;
+  int32_t* counts = (int32_t*)w;
+  w += round_up((size_t)n * 4, 256);
+  const int64_t nb = cdiv(n, SCAN_BLOCK);
+  int64_t* bsum = (int64_t*)w;
+  w += round_up((size_t)nb * 8, 256);
+  int32_t* tmp_key = (int32_t*)w;
+  w += round_up((size_t)nnz * 4, 256);
+  float* tmp_val = (float*)w;
+  hipError_t e = hipMemsetAsync(counts, 0, (size_t)n * 4, st);
+  if (e != hipSuccess) return e;
+  if (nnz > 0) count_cols_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(colidx, nnz, counts);
+  scan_block_sums_kernel<<<(unsigned)nb, 256, 0, st>>>(counts, n, bsum);
+  scan_top_kernel<<<1, 256, 0, st>>>(bsum, nb);
+  scan_apply_kernel<<<(unsigned)nb, 256, 0, st>>>(counts, n, bsum, nnz, rowptr_t);
+  if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
+  if (nnz == 0) return hipSuccess;
+  if ((e = hipMemsetAsync(counts, 0, (size_t)n * 4, st)) != hipSuccess) return e;
+  scatter_kernel<<<(unsigned)cdiv(m, 256), 256, 0, st>>>(rowptr, colidx, vals, m, rowptr_t,
+                                                         counts, tmp_key, tmp_val);
+  rank_sort_kernel<<<(unsigned)cdiv(n, 4), 256, 0, st>>>(rowptr_t, n, tmp_key, tmp_val,
+                                                         colidx_t, vals_t);
+  return NMF_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Objective for sparse A: per stored entry (a - wh)^2 - wh^2, one lane per
+// entry, the row of W read with wave-uniform loads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+constexpr int RES_ROWS_PER_BLOCK = 64;
+
+template <int KP>
+__global__ __launch_bounds__(256) void csr_residual_kernel(const int64_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ colidx,
+                                                           const float* __restrict__ vals,
+                                                           int64_t m, const float* __restrict__ W,
+                                                           const float* __restrict__ Ht,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double local = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * RES_ROWS_PER_BLOCK;
+  for (int64_t i = r0 + wave; i < r0 + RES_ROWS_PER_BLOCK && i < m; i += 4) {
+    const float* wr = W + i * KP;
+    const int64_t b = rowptr[i], e = rowptr[i + 1];
+    for (int64_t p = b + lane; p < e; p += 64) {
+      const float* hr = Ht + (int64_t)colidx[p] * KP;
+      float wh = 0.f;
+#pragma unroll
+      for (int q = 0; q < KP; q += 4) {
+        const float4 h = *reinterpret_cast<const float4*>(hr + q);
+        wh = fmaf(wr[q], h.x, wh);
+        wh = fmaf(wr[q + 1], h.y, wh);
+        wh = fmaf(wr[q + 2], h.z, wh);
+        wh = fmaf(wr[q + 3], h.w, wh);
+      }
+      const double a = (double)vals[p], d = a - (double)wh;
+      local += d * d - (double)wh * (double)wh;
+    }
+  }
+  local = wave_sum_d(local);
+  if (lane == 0) sh[wave] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+int64_t csr_residual_partials(int64_t m) { return cdiv(m, RES_ROWS_PER_BLOCK); }
+
+hipError_t csr_residual_sq(const int64_t* rowptr, const int32_t* colidx, const float* vals,
+                           int64_t m, const float* W, const float* Ht, int KP, double* partial,
+                           hipStream_t st) {
+  const unsigned blocks = (unsigned)cdiv(m, RES_ROWS_PER_BLOCK);
+  switch (KP) {
+#define C(K) case K: csr_residual_kernel<K><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, W, Ht, partial); break;
+    C(16) C(32) C(48) C(64) C(80) C(96) C(112) C(128)
+#undef C
+    default: return hipErrorInvalidValue;
+  }
+  return NMF_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void csr_sumsq_kernel(const float* __restrict__ vals,
+                                                        int64_t nnz, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double local = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const double a = vals[p];
+    local += a * a;
+  }
+  local = wave_sum_d(local);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+hipError_t csr_sumsq(const float* vals, int64_t nnz, double* partial, int64_t np,
+                     hipStream_t st) {
+  csr_sumsq_kernel<<<(unsigned)np, 256, 0, st>>>(vals, nnz, partial);
+  return NMF_LAUNCH_CHECK();
+}
+
+// CSR validity: rowptr nondecreasing from 0 to nnz, columns in range and
+// strictly increasing within a row, values finite and >= 0.
+__global__ void check_csr_kernel(const int64_t* __restrict__ rowptr,
+                                 const int32_t* __restrict__ colidx,
+                                 const float* __restrict__ vals, int64_t m, int64_t n,
+                                 int64_t nnz, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int64_t b = rowptr[i], e = rowptr[i + 1];
+  // Row bounds are checked before any entry is read.
+  int bad = (b < 0 || e < b || e > nnz || (i == 0 && b != 0) || (i == m - 1 && e != nnz)) ? 2 : 0;
+  if (!bad) {
+    int32_t prev = -1;
+    for (int64_t p = b; p < e; ++p) {
+      const int32_t j = colidx[p];
+      const float v = vals[p];
+      if (j < 0 || j >= n || j <= prev) { bad = 2; break; }
+      if (!(v >= 0.f) || v == INFINITY) bad = bad ? bad : 1;
+      prev = j;
+    }
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+hipError_t check_csr(const int64_t* rowptr, const int32_t* colidx, const float* vals, int64_t m,
+                     int64_t n, int64_t nnz, int* flag, hipStream_t st) {
+  check_csr_kernel<<<(unsigned)cdiv(m, 256), 256, 0, st>>>(rowptr, colidx, vals, m, n, nnz, flag);
+  return NMF_LAUNCH_CHECK();
+}
+
+}  // namespace nmfk

@@ -1,0 +1,330 @@
+// Local update computations (LUC) of Algorithm 1 on the row layout: one
+// thread owns one row x of the factor being updated (a row of W, or a row of
+// H^T, i.e. a column of H) and keeps it in registers; the k x k Gram G of the
+// fixed factor is read with wave-uniform (scalar) loads. Rows are independent
+// (Section 5: rows of W and columns of H can be updated in parallel), so the
+// grid is simply one thread per row.
+//
+//   MU   (Section 4.1, Eq. (3)):  x_i <- x_i p_i / ((x G)_i + eps), all i at once
+//   HALS (Section 4.2, Eq. (5)):  i = 1..k in order, newest values:
+//        x_i <- max(0, x_i + (p_i - (x G)_i) / G_ii)   (skipped if G_ii = 0)
+//
+// Padding entries k..KP-1 of x are zero on entry and stay zero.
+#include "common.h"
+#include "kernels.h"
+
+namespace nmfk {
+
+template <typename T, int KP>
+__device__ __forceinline__ void load_row(const T* __restrict__ src, T (&x)[KP]) {
+  constexpr int VEC = Tr<T>::VEC;
+#pragma unroll
+  for (int q = 0; q < KP / VEC; ++q) {
+    V16<T> t = load16<T>(src + q * VEC);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) x[q * VEC + v] = t.v[v];
+  }
+}
+
+template <typename T, int KP>
+__device__ __forceinline__ void store_row(T* __restrict__ dst, const T (&x)[KP]) {
+  constexpr int VEC = Tr<T>::VEC;
+#pragma unroll
+  for (int q = 0; q < KP / VEC; ++q) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4*>(dst + q * 4) =
+          make_float4(x[q * 4], x[q * 4 + 1], x[q * 4 + 2], x[q * 4 + 3]);
+    } else {
+      *reinterpret_cast<double2*>(dst + q * 2) = make_double2(x[q * 2], x[q * 2 + 1]);
+    }
+  }
+}
+
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void mu_rows_kernel(T* __restrict__ X, const T* __restrict__ P,
+                                                      const T* __restrict__ G, int64_t rows,
+                                                      int k, T eps) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  T x[KP];
+  load_row<T, KP>(X + r * KP, x);
+  const T* pr = P + r * KP;
+  T* xr = X + r * KP;
+  constexpr int CH = 16;
+#pragma unroll
+  for (int i0 = 0; i0 < KP; i0 += CH) {
+    if (i0 < k) {
+      T d[CH];
+#pragma unroll
+      for (int ii = 0; ii < CH; ++ii) d[ii] = T(0);
+#pragma unroll
+      for (int j = 0; j < KP; ++j)
+#pragma unroll
+        for (int ii = 0; ii < CH; ++ii) d[ii] = fma(x[j], G[j * KP + i0 + ii], d[ii]);
+#pragma unroll
+      for (int ii = 0; ii < CH; ++ii) {
+        const int i = i0 + ii;
+        if (i < k) xr[i] = x[i] * pr[i] / (d[ii] + eps);
+      }
+    }
+  }
+}
+
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void hals_rows_kernel(T* __restrict__ X,
+                                                        const T* __restrict__ P,
+                                                        const T* __restrict__ G, int64_t rows,
+                                                        int k) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  T x[KP];
+  load_row<T, KP>(X + r * KP, x);
+  const T* pr = P + r * KP;
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    if (i < k) {
+      const T gii = G[i * KP + i];
+      if (gii > T(0)) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < KP; ++j) s = fma(x[j], G[j * KP + i], s);
+        const T t = x[i] + (pr[i] - s) / gii;
+        x[i] = t > T(0) ? t : T(0);
+      }
+    }
+  }
+  store_row<T, KP>(X + r * KP, x);
+}
+
+// Ranks above 64: the same updates with each thread's row kept in LDS
+// (column tid of a [KP][64] array, so accesses are bank-conflict free) and
+// runtime loops, instead of fully unrolled register code. G is symmetric, so
+// G[i*KP + j] is read along j with uniform loads.
+constexpr int LDS_ROWS = 64;
+template <typename T>
+__global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(T* __restrict__ X,
+                                                               const T* __restrict__ P,
+                                                               const T* __restrict__ G,
+                                                               int64_t rows, int k, int KP,
+                                                               T eps) {
+  __shared__ T xs[NMF_MAX_K * LDS_ROWS];
+  const int t = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * LDS_ROWS + t;
+  if (r >= rows) return;  // no barriers below: each thread touches only its column
+  for (int j = 0; j < KP; ++j) xs[j * LDS_ROWS + t] = X[r * KP + j];
+  for (int i = 0; i < k; ++i) {
+    T d = T(0);
+    for (int j = 0; j < k; ++j) d = fma(xs[j * LDS_ROWS + t], G[i * KP + j], d);
+    X[r * KP + i] = xs[i * LDS_ROWS + t] * P[r * KP + i] / (d + eps);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(LDS_ROWS) void hals_rows_lds_kernel(T* __restrict__ X,
+                                                                 const T* __restrict__ P,
+                                                                 const T* __restrict__ G,
+                                                                 int64_t rows, int k, int KP) {
+  __shared__ T xs[NMF_MAX_K * LDS_ROWS];
+  const int t = threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * LDS_ROWS + t;
+  if (r >= rows) return;
+  for (int j = 0; j < KP; ++j) xs[j * LDS_ROWS + t] = X[r * KP + j];
+  for (int i = 0; i < k; ++i) {
+    const T gii = G[i * KP + i];
+    if (gii > T(0)) {
+      T s = T(0);
+      for (int j = 0; j < k; ++j) s = fma(xs[j * LDS_ROWS + t], G[i * KP + j], s);
+      const T v = xs[i * LDS_ROWS + t] + (P[r * KP + i] - s) / gii;
+      xs[i * LDS_ROWS + t] = v > T(0) ? v : T(0);
+    }
+  }
+  for (int j = 0; j < KP; ++j) X[r * KP + j] = xs[j * LDS_ROWS + t];
+}
+
+#define KP_SWITCH(KPV, CALL, FALLBACK)                         \
+  switch (KPV) {                                               \
+    case 16: { constexpr int KPc = 16; CALL; } break;          \
+    case 32: { constexpr int KPc = 32; CALL; } break;          \
+    case 48: { constexpr int KPc = 48; CALL; } break;          \
+    case 64: { constexpr int KPc = 64; CALL; } break;          \
+    default:                                                   \
+      if (KPV > NMF_MAX_K || KPV % 16) return hipErrorInvalidValue; \
+      FALLBACK;                                                \
+  }
+
+template <typename T>
+hipError_t mu_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, T eps,
+                   hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)cdiv(rows, 256);
+  KP_SWITCH(KP, (mu_rows_kernel<T, KPc><<<blocks, 256, 0, st>>>(X, P, G, rows, k, eps)),
+            (mu_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
+                X, P, G, rows, k, KP, eps)));
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
+                     hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)cdiv(rows, 256);
+  KP_SWITCH(KP, (hals_rows_kernel<T, KPc><<<blocks, 256, 0, st>>>(X, P, G, rows, k)),
+            (hals_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
+                X, P, G, rows, k, KP)));
+  return NMF_LAUNCH_CHECK();
+}
+
+// --- HALS normalisation ----------------------------------------------------
+// One block: norms s_i = sqrt(S_ii) (0 if S_ii <= 0), then S <- D^-1 S D^-1
+// on the entries whose norms are positive.
+template <typename T>
+__global__ void hals_norms_kernel(T* __restrict__ S, T* __restrict__ norms, int k, int KP) {
+  __shared__ double s_sh[NMF_MAX_K];
+  for (int i = threadIdx.x; i < KP; i += blockDim.x) {
+    const T d = S[i * KP + i];
+    const double s = (i < k && d > T(0)) ? sqrt((double)d) : 0.0;
+    s_sh[i] = s;
+    norms[i] = (T)s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) {
+    const int i = e / KP, j = e - i * KP;
+    const double si = s_sh[i], sj = s_sh[j];
+    if (si > 0.0 && sj > 0.0) S[e] = (T)((double)S[e] / (si * sj));
+  }
+}
+
+// W[:, i] /= s_i (rows 0..m-1), Ht[:, i] *= s_i (rows m..m+n-1 of the grid).
+template <typename T>
+__global__ void hals_scale_kernel(T* __restrict__ W, int64_t m, T* __restrict__ Ht, int64_t n,
+                                  const T* __restrict__ norms, int k, int KP) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (m + n) * KP;
+  if (e >= total) return;
+  const int64_t r = e / KP;
+  const int i = (int)(e - r * KP);
+  if (i >= k) return;
+  const T s = norms[i];
+  if (!(s > T(0))) return;
+  if (r < m) W[r * KP + i] = W[r * KP + i] / s;
+  else Ht[(r - m) * KP + i] = Ht[(r - m) * KP + i] * s;
+}
+
+template <typename T>
+hipError_t hals_normalize(T* W, int64_t m, T* Ht, int64_t n, T* S, T* norms, int k, int KP,
+                          hipStream_t st) {
+  hals_norms_kernel<T><<<1, 256, 0, st>>>(S, norms, k, KP);
+  hipError_t e = NMF_LAUNCH_CHECK();
+  if (e != hipSuccess) return e;
+  const int64_t total = (m + n) * KP;
+  if (total == 0) return hipSuccess;
+  hals_scale_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(W, m, Ht, n, norms, k, KP);
+  return NMF_LAUNCH_CHECK();
+}
+
+// --- layout copies ---------------------------------------------------------
+template <typename T>
+__global__ void pad_rows_kernel(const T* __restrict__ src, int64_t rows, int k,
+                                T* __restrict__ dst, int KP) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * KP) return;
+  const int64_t r = e / KP;
+  const int i = (int)(e - r * KP);
+  dst[e] = i < k ? src[r * k + i] : T(0);
+}
+
+template <typename T>
+__global__ void unpad_rows_kernel(const T* __restrict__ src, int64_t rows, int k, int KP,
+                                  T* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * k) return;
+  const int64_t r = e / k;
+  const int i = (int)(e - r * k);
+  dst[e] = src[r * KP + i];
+}
+
+// Ht[j][i] = H[i][j] (i < k), 0 for k <= i < KP. Tiled through LDS.
+template <typename T>
+__global__ void transpose_in_kernel(const T* __restrict__ H, int k, int64_t n,
+                                    T* __restrict__ Ht, int KP) {
+  __shared__ T tile[32][33];
+  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  const int i0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int i = i0 + yy;
+    const int64_t j = j0 + tx;
+    tile[yy][tx] = (i < k && j < n) ? H[(int64_t)i * n + j] : T(0);
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t j = j0 + yy;
+    const int i = i0 + tx;
+    if (j < n && i < KP) Ht[j * KP + i] = tile[tx][yy];
+  }
+}
+
+template <typename T>
+__global__ void transpose_out_kernel(const T* __restrict__ Ht, int k, int64_t n, int KP,
+                                     T* __restrict__ H) {
+  __shared__ T tile[32][33];
+  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  const int i0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t j = j0 + yy;
+    const int i = i0 + tx;
+    tile[tx][yy] = (j < n && i < k) ? Ht[j * KP + i] : T(0);
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int i = i0 + yy;
+    const int64_t j = j0 + tx;
+    if (i < k && j < n) H[(int64_t)i * n + j] = tile[yy][tx];
+  }
+}
+
+template <typename T>
+hipError_t pad_rows(const T* src, int64_t rows, int k, T* dst, int KP, hipStream_t st) {
+  const int64_t total = rows * KP;
+  if (total == 0) return hipSuccess;
+  pad_rows_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(src, rows, k, dst, KP);
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t unpad_rows(const T* src, int64_t rows, int k, int KP, T* dst, hipStream_t st) {
+  const int64_t total = rows * k;
+  if (total == 0) return hipSuccess;
+  unpad_rows_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(src, rows, k, KP, dst);
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t transpose_in(const T* H, int k, int64_t n, T* Ht, int KP, hipStream_t st) {
+  dim3 grid((unsigned)cdiv(n, 32), (unsigned)cdiv(KP, 32));
+  transpose_in_kernel<T><<<grid, 256, 0, st>>>(H, k, n, Ht, KP);
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_t st) {
+  dim3 grid((unsigned)cdiv(n, 32), (unsigned)cdiv(k, 32));
+  transpose_out_kernel<T><<<grid, 256, 0, st>>>(Ht, k, n, KP, H);
+  return NMF_LAUNCH_CHECK();
+}
+
+#define INST(T)                                                                             \
+  template hipError_t mu_rows<T>(T*, const T*, const T*, int64_t, int, int, T, hipStream_t); \
+  template hipError_t hals_rows<T>(T*, const T*, const T*, int64_t, int, int, hipStream_t);  \
+  template hipError_t hals_normalize<T>(T*, int64_t, T*, int64_t, T*, T*, int, int,         \
+                                        hipStream_t);                                       \
+  template hipError_t pad_rows<T>(const T*, int64_t, int, T*, int, hipStream_t);            \
+  template hipError_t unpad_rows<T>(const T*, int64_t, int, int, T*, hipStream_t);          \
+  template hipError_t transpose_in<T>(const T*, int, int64_t, T*, int, hipStream_t);        \
+  template hipError_t transpose_out<T>(const T*, int, int64_t, int, T*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace nmfk

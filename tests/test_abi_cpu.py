@@ -1,0 +1,123 @@
+"""The C-ABI library loads, exports every function include/nmf.h declares,
+and rejects bad arguments on the host before touching a device (checked on a
+context bound to no device, so no GPU is needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1609_09154_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nmf.h")
+
+EINVAL, EDEVICE = _lib.NMF_EINVAL, _lib.NMF_EDEVICE
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nmf_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    names = declared_functions()
+    assert len(names) >= 15
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_defaults():
+    L = _lib.lib()
+    assert L.nmf_status_str(0) == b"NMF_OK"
+    assert L.nmf_status_str(5) == b"NMF_ENOTCONV"
+    o = _lib.default_opts()
+    assert o.algo == _lib.NMF_MU and o.iters == 0 and o.eps_mu == 1e-16
+    assert o.max_pivots == 0 and o.objective == 0
+
+
+@pytest.fixture
+def hctx():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.nmf_create(ctypes.byref(h), -1, None) == 0
+    yield h
+    L.nmf_destroy(h)
+
+
+P = ctypes.c_void_p(4096)  # never dereferenced: checks fail or the context has no device
+
+
+def dense(h, m=10, n=8, lda=8, k=3, dtype=_lib.NMF_F32, opts=None, A=P, W=P, H=P, relerr=None):
+    o = opts or _lib.default_opts(algo="hals", iters=2)
+    return _lib.lib().nmf_dense(h, dtype, m, n, A, lda, k, ctypes.byref(o), W, H, relerr, None)
+
+
+def test_valid_dense_call_reaches_device_stage(hctx):
+    assert dense(hctx) == EDEVICE
+
+
+@pytest.mark.parametrize("kw", [dict(m=0), dict(n=0), dict(k=0), dict(k=129), dict(lda=7),
+                                dict(dtype=7), dict(A=None), dict(W=None), dict(H=None),
+                                dict(m=1 << 41)])
+def test_dense_argument_errors(hctx, kw):
+    assert dense(hctx, **kw) == EINVAL
+    assert _lib.lib().nmf_last_error(hctx)
+
+
+def test_dense_bad_options(hctx):
+    assert dense(hctx, opts=_lib.default_opts(algo=3)) == EINVAL
+    assert dense(hctx, opts=_lib.default_opts(iters=-1)) == EINVAL
+    assert dense(hctx, opts=_lib.default_opts(objective=9)) == EINVAL
+    assert dense(hctx, opts=_lib.default_opts(eps_mu=-1.0)) == EINVAL
+    assert dense(hctx, k=65, opts=_lib.default_opts(algo="abpp")) == EINVAL
+    # rel_err requested without an objective
+    errs = (ctypes.c_double * 3)()
+    assert dense(hctx, relerr=errs) == EINVAL
+
+
+def test_null_context_and_opts():
+    L = _lib.lib()
+    assert L.nmf_dense(None, 1, 4, 4, P, 4, 2, None, P, P, None, None) == EINVAL
+    h = ctypes.c_void_p()
+    assert L.nmf_create(ctypes.byref(h), -1, None) == 0
+    assert L.nmf_dense(h, 1, 4, 4, P, 4, 2, None, P, P, None, None) == EINVAL
+    L.nmf_destroy(h)
+    assert L.nmf_create(None, 0, None) == EINVAL
+
+
+def test_csr_argument_errors(hctx):
+    L = _lib.lib()
+    o = _lib.default_opts(algo="abpp", iters=1)
+    ok = L.nmf_csr(hctx, 10, 10, 5, P, P, P, 3, ctypes.byref(o), P, P, None, None)
+    assert ok == EDEVICE
+    assert L.nmf_csr(hctx, 10, 10, -1, P, P, P, 3, ctypes.byref(o), P, P, None, None) == EINVAL
+    assert L.nmf_csr(hctx, 10, 10, 5, None, P, P, 3, ctypes.byref(o), P, P, None, None) == EINVAL
+    assert L.nmf_csr(hctx, 10, 10, 5, P, None, P, 3, ctypes.byref(o), P, P, None, None) == EINVAL
+    assert L.nmf_csr(hctx, 10, 1 << 32, 5, P, P, P, 3, ctypes.byref(o), P, P, None, None) == EINVAL
+
+
+def test_step_argument_errors(hctx):
+    L = _lib.lib()
+    assert L.nmf_gram(hctx, 1, 10, 3, P, 2, P) == EINVAL          # ldx < k
+    assert L.nmf_gram(hctx, 1, 10, 3, P, 3, P) == EDEVICE
+    assert L.nmf_dense_AF(hctx, 1, 10, 8, P, 8, 3, P, 2, P) == EINVAL
+    assert L.nmf_dense_AtF(hctx, 1, 10, 8, P, 7, 3, P, 3, P) == EINVAL
+    assert L.nmf_dense_AF(hctx, 1, 10, 8, P, 8, 3, P, 3, P) == EDEVICE
+    o = _lib.default_opts()
+    piv = ctypes.c_longlong()
+    assert L.nmf_update(hctx, 9, 1, 10, 3, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
+    assert L.nmf_update(hctx, 2, 1, 10, 80, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
+    assert L.nmf_update(hctx, 1, 1, 10, 3, None, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
+    assert L.nmf_update(hctx, 1, 1, 10, 3, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EDEVICE
+    out = ctypes.c_double()
+    assert L.nmf_dense_relerr(hctx, 1, 10, 8, P, 8, 3, P, P, None) == EINVAL
+    assert L.nmf_dense_relerr(hctx, 1, 10, 8, P, 8, 3, P, P, ctypes.byref(out)) == EDEVICE
+    assert L.nmf_csr_transpose(hctx, 10, 8, -2, P, P, P, P, P, P) == EINVAL
+    assert L.nmf_hals_normalize(hctx, 1, 10, 8, 0, P, P, None, None) == EINVAL

@@ -1,0 +1,194 @@
+"""Whole-iteration parity: Algorithm 1 on the GPU (nmf_dense / nmf_csr)
+against the FP64 oracle, relative error after every iteration.
+
+Bars: FP64 runs match to 1e-10 relative per iteration; FP32 runs to 1e-5
+relative per iteration (the stated FP32 objective tolerance). Inputs are the
+planted workloads of the benchmark at sizes the oracle finishes in seconds.
+"""
+import numpy as np
+import pytest
+import scipy.sparse
+
+import oracle
+import paper_1609_09154_amd as nmf
+from synth import erdos_renyi_csr, init_factors, planted_dense
+from tests.gpu_util import host, rel_diff, step, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def run_dense(A, W0, H0, algo, iters, npdt, **kw):
+    Ad, Wd, Hd = to_dev(A, npdt), to_dev(W0, npdt), to_dev(H0, npdt)
+    errs, stats = nmf.nmf_dense(Ad, Wd, Hd, algo=algo, iters=iters, objective=True, **kw)
+    return host(Wd), host(Hd), np.array(errs), stats
+
+
+def dense_case(m, n, k, k_true, seed, npdt):
+    A = planted_dense(m, n, k_true, sigma=0.01, seed=seed).astype(npdt)
+    W0, H0 = init_factors(m, n, k, seed=seed + 7545)
+    return A, W0.astype(npdt), H0.astype(npdt)
+
+
+def test_mu_f64_2000x1000_k10_20_iterations():
+    """The small FP64 workload: A = W0 H0 + |N(0, 0.01)|, MU, 20 iterations."""
+    A, W0, H0 = dense_case(2000, 1000, 10, 10, 1609, np.float64)
+    step("mu f64 2000x1000 k=10")
+    W, H, e, _ = run_dense(A, W0, H0, "mu", 20, np.float64)
+    Wr, Hr, er = oracle.run(A, 10, "mu", 20, W0, H0)
+    assert rel_diff(e, er) <= 1e-10, (e, er)
+    assert rel_diff(W, Wr) <= 1e-8 and rel_diff(H, Hr) <= 1e-8
+
+
+@pytest.mark.parametrize("algo", ["hals", "abpp"])
+@pytest.mark.parametrize("m,n,k", [(700, 500, 12), (333, 257, 50)])
+def test_f64_runs(algo, m, n, k):
+    A, W0, H0 = dense_case(m, n, k, k, 11 + k, np.float64)
+    step("%s f64 %dx%d k=%d" % (algo, m, n, k))
+    W, H, e, _ = run_dense(A, W0, H0, algo, 8, np.float64)
+    Wr, Hr, er = oracle.run(A, k, algo, 8, W0, H0)
+    assert rel_diff(e, er) <= 1e-10, (e, er)
+
+
+@pytest.mark.parametrize("algo,m,n,k,iters", [
+    ("hals", 3000, 2500, 50, 10),   # the FP32 HALS workload's shape family, scaled
+    ("mu", 2049, 1537, 50, 10),
+    ("abpp", 1500, 1100, 50, 5),
+    ("hals", 1200, 1000, 100, 5),
+])
+def test_f32_runs(algo, m, n, k, iters):
+    A, W0, H0 = dense_case(m, n, k, k, 101 + k, np.float32)
+    step("%s f32 %dx%d k=%d" % (algo, m, n, k))
+    W, H, e, _ = run_dense(A, W0, H0, algo, iters, np.float32)
+    _, _, er = oracle.run(A.astype(np.float64), k, algo, iters, W0.astype(np.float64),
+                          H0.astype(np.float64))
+    d = rel_diff(e, er)
+    print("f32 %s %dx%d k=%d max rel objective diff %.3e; e_T gpu %.6e oracle %.6e"
+          % (algo, m, n, k, d, e[-1], er[-1]))
+    assert d <= 1e-5, (e, er)
+    assert (W >= 0).all() and (H >= 0).all()
+
+
+def test_hals_objective_monotone_and_normalised():
+    A, W0, H0 = dense_case(2500, 2000, 50, 50, 5, np.float32)
+    step("hals f32 monotone")
+    W, H, e, _ = run_dense(A, W0, H0, "hals", 15, np.float32)
+    assert all(b <= a * (1 + 1e-5) for a, b in zip(e, e[1:]))
+    np.testing.assert_allclose(np.linalg.norm(W.astype(np.float64), axis=0), 1.0, rtol=1e-5)
+
+
+def test_deterministic_and_resumable():
+    A, W0, H0 = dense_case(1500, 1300, 50, 50, 9, np.float32)
+    step("determinism")
+    W1, H1, e1, _ = run_dense(A, W0, H0, "hals", 6, np.float32)
+    W2, H2, e2, _ = run_dense(A, W0, H0, "hals", 6, np.float32)
+    np.testing.assert_array_equal(W1, W2)
+    np.testing.assert_array_equal(H1, H2)
+    np.testing.assert_array_equal(e1, e2)
+    step("resume")
+    Wa, Ha, ea, _ = run_dense(A, W0, H0, "hals", 4, np.float32)
+    Wb, Hb, eb, _ = run_dense(A, Wa, Ha, "hals", 2, np.float32)
+    np.testing.assert_array_equal(Wb, W1)
+    np.testing.assert_array_equal(Hb, H1)
+
+
+def test_stats_and_zero_iterations():
+    A, W0, H0 = dense_case(600, 400, 10, 10, 3, np.float32)
+    step("stats")
+    W, H, e, st = run_dense(A, W0, H0, "abpp", 3, np.float32, timers=True)
+    assert st["ms_total"] > 0 and st["ms_mm"] > 0 and st["ms_luc"] > 0 and st["ms_gram"] > 0
+    assert st["bpp_pivots"] >= 3 * (600 + 400)
+    W, H, e, _ = run_dense(A, W0, H0, "mu", 0, np.float32)
+    np.testing.assert_array_equal(W, W0)
+    np.testing.assert_array_equal(H, H0)
+    assert len(e) == 1
+
+
+def test_check_input_flags_bad_values():
+    A, W0, H0 = dense_case(200, 100, 5, 5, 4, np.float32)
+    A[17, 3] = np.nan
+    step("check_input nan")
+    with pytest.raises(nmf.NMFError) as ei:
+        run_dense(A, W0, H0, "mu", 1, np.float32, check_input=True)
+    assert ei.value.status == 4
+    A[17, 3] = -1.0
+    with pytest.raises(nmf.NMFError):
+        run_dense(A, W0, H0, "mu", 1, np.float32, check_input=True)
+
+
+def test_pivot_cap_reports_not_converged():
+    A, W0, H0 = dense_case(300, 200, 20, 20, 8, np.float64)
+    step("abpp pivot cap")
+    with pytest.raises(nmf.NMFError) as ei:
+        run_dense(A, W0, H0, "abpp", 1, np.float64, max_pivots=1)
+    assert ei.value.status == 5
+
+
+# --- sparse --------------------------------------------------------------
+
+def csr_dev(csr):
+    import torch
+
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(csr.rowptr).to(dev), torch.from_numpy(csr.colidx).to(dev),
+            torch.from_numpy(csr.vals.astype(np.float32)).to(dev))
+
+
+def scipy_csr(csr):
+    return scipy.sparse.csr_matrix((csr.vals.astype(np.float64), csr.colidx, csr.rowptr),
+                                   shape=(csr.m, csr.n))
+
+
+@pytest.mark.parametrize("m,n,d", [(1, 1, 1.0), (3000, 2000, 0.01), (1025, 4097, 0.05),
+                                   (500, 300, 0.0)])
+def test_csr_transpose_bit_exact(m, n, d):
+    csr = erdos_renyi_csr(m, n, d, seed=m + n)
+    step("csr transpose %dx%d d=%g" % (m, n, d))
+    rpt, cit, cvt = nmf.nmf_csr_transpose(*csr_dev(csr), n)
+    T = scipy.sparse.csr_matrix((csr.vals, csr.colidx, csr.rowptr), shape=(m, n)).T.tocsr()
+    T.sort_indices()
+    np.testing.assert_array_equal(host(rpt), T.indptr.astype(np.int64))
+    np.testing.assert_array_equal(host(cit), T.indices.astype(np.int32))
+    np.testing.assert_array_equal(host(cvt), T.data.astype(np.float32))
+
+
+@pytest.mark.parametrize("m,n,d,k", [(2000, 1500, 0.02, 50), (777, 999, 0.05, 10),
+                                     (300, 5000, 0.01, 64), (1000, 800, 0.03, 100), (50, 40, 0.0, 16)])
+def test_csr_spmm(m, n, d, k):
+    from tests.gpu_util import U32, assert_gemm_bound
+    csr = erdos_renyi_csr(m, n, d, seed=2 * m + n)
+    F = np.random.default_rng(k).random((n, k)).astype(np.float32)
+    step("csr spmm %dx%d k=%d" % (m, n, k))
+    P = host(nmf.nmf_csr_AF(*csr_dev(csr), n, to_dev(F, np.float32)))
+    ref = oracle.product_AHt(scipy_csr(csr), F.T.astype(np.float64))
+    rowlen = int(np.diff(csr.rowptr).max()) if m else 0
+    assert_gemm_bound(P, ref, ref, max(rowlen, 1), U32, what="spmm")
+
+
+@pytest.mark.parametrize("algo,iters", [("abpp", 6), ("hals", 8), ("mu", 8)])
+def test_csr_runs(algo, iters):
+    """Sparse ER data with ~100 stored entries per row (the sparse workload's
+    row density), k = 50."""
+    m, n, k = 3000, 2600, 50
+    csr = erdos_renyi_csr(m, n, 100.0 / n, seed=7)
+    W0, H0 = init_factors(m, n, k, seed=77)
+    W0 = W0.astype(np.float32)
+    H0 = H0.astype(np.float32)
+    rp, ci, cv = csr_dev(csr)
+    Wd, Hd = to_dev(W0, np.float32), to_dev(H0, np.float32)
+    step("csr %s %dx%d k=%d" % (algo, m, n, k))
+    errs, st = nmf.nmf_csr(rp, ci, cv, n, Wd, Hd, algo=algo, iters=iters, objective=True)
+    _, _, er = oracle.run(scipy_csr(csr), k, algo, iters, W0.astype(np.float64),
+                          H0.astype(np.float64))
+    d = rel_diff(errs, er)
+    print("csr %s max rel objective diff %.3e; e_T %.6f" % (algo, d, errs[-1]))
+    assert d <= 1e-5, (errs, er)
+
+
+def test_csr_relerr_matches_oracle():
+    csr = erdos_renyi_csr(900, 700, 0.03, seed=5)
+    W, H = init_factors(900, 700, 20, seed=6)
+    step("csr relerr")
+    got = nmf.nmf_csr_relerr(*csr_dev(csr), 700, to_dev(W, np.float32), to_dev(H.T, np.float32))
+    ref = oracle.relative_error(scipy_csr(csr), W.astype(np.float32).astype(np.float64),
+                                H.astype(np.float32).astype(np.float64))
+    assert abs(got - ref) <= 1e-5 * ref
