@@ -1,0 +1,184 @@
+"""Benchmark: AU-NMF iterations per second on one MI355X.
+
+Workload (default): dense float32 A = W0 H0 + |N(0, 0.01)| with m = n = 65536
+(17.2 GB), W0 and H0 U(0,1) of rank 50, factorised at k = 50 by HALS. One
+step is one full iteration of Algorithm 1: H H^T, A H^T, the W sweep, W^T W,
+the normalisation, W^T A and the H sweep, all in the library's HIP kernels,
+with A resident in HBM. Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
+                  [--no-cpu-baseline] [--sample-rows R]
+
+roofline: the dominant kernels are the two large products (A H^T and W^T A,
+2 m n k algorithmic flops per launch, k unpadded). Their average launch time
+comes from the library's hipEvents on the stream the kernels run on;
+achieved = 2 m n k / that time, against the FP32 matrix peak. traffic is the
+HBM byte count per launch from the committed rocprofv3 counter summary,
+reported only while the product kernel source is unchanged since the counters
+were taken.
+
+cpu_baseline: the FP64 oracle (tests only, never the product path) timed on
+the host for a few iterations of the same algorithm on a square sample of
+the same planted matrix family, scaled by (m n) / (sample rows)^2 to the
+full workload's iterations per second.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dense_65536x65536_k50.json")
+
+WORKLOADS = {
+    "dense-65536x65536-k50-hals-f32": dict(m=65536, n=65536, k=50, k_true=50, algo="hals",
+                                           dtype="f32"),
+    "dense-2000x1000-k10-mu-f64": dict(m=2000, n=1000, k=10, k_true=10, algo="mu", dtype="f64"),
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1609_09154_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(src_hash):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != src_hash:
+        return None
+    return t
+
+
+def cpu_baseline(wl, sample_rows, iters=6):
+    """Time the FP64 oracle on the host: `iters` iterations of the same
+    algorithm on a sample_rows x sample_rows planted matrix of rank k_true."""
+    import numpy as np
+
+    import oracle
+    from synth import init_factors, planted_dense
+
+    cores = len(os.sched_getaffinity(0))
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ.setdefault(var, str(cores))
+    s = sample_rows
+    A = planted_dense(s, s, wl["k_true"], sigma=0.01, seed=1609).astype(np.float32).astype(np.float64)
+    W0, H0 = init_factors(s, s, wl["k"], seed=9154)
+    oracle.run(A, wl["k"], wl["algo"], 1, W0, H0, track_error=False)  # warm-up
+    t0 = time.perf_counter()
+    oracle.run(A, wl["k"], wl["algo"], iters, W0, H0, track_error=False)
+    dt = (time.perf_counter() - t0) / iters
+    scale = (wl["m"] * wl["n"]) / float(s * s)
+    try:
+        from threadpoolctl import threadpool_info
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        used = cores
+    return {"value": 1.0 / (dt * scale), "unit": "iters/s", "cores": int(used), "kind": "oracle",
+            "sample": "%d iterations of FP64 %s on a %dx%d planted matrix (k=%d), %.3f s/iter, "
+                      "scaled by %.1f to %dx%d" % (iters, wl["algo"].upper(), s, s, wl["k"], dt,
+                                                   scale, wl["m"], wl["n"])}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="dense-65536x65536-k50-hals-f32", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sample-rows", type=int, default=16384)
+    ap.add_argument("--check", action="store_true", help="also report the final relative error")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1609_09154_amd as nmf
+    from synth import init_factors, planted_dense_torch
+
+    wl = WORKLOADS[args.workload]
+    m, n, k = wl["m"], wl["n"], wl["k"]
+    tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
+    dev = torch.device("cuda:0")
+    print("[bench] generating %s" % args.workload, file=sys.stderr, flush=True)
+    A = planted_dense_torch(m, n, wl["k_true"], sigma=0.01, seed=1609, device=dev, dtype=tdt)
+    W0n, H0n = init_factors(m, n, k, seed=9154)
+    W0 = torch.from_numpy(W0n).to(dev, tdt)
+    H0 = torch.from_numpy(H0n).to(dev, tdt)
+    torch.cuda.synchronize()
+
+    print("[bench] warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    W, H = W0.clone(), H0.clone()
+    nmf.nmf_dense(A, W, H, algo=wl["algo"], iters=args.warmup, objective=False)
+    W.copy_(W0)
+    H.copy_(H0)
+    torch.cuda.synchronize()
+
+    print("[bench] timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    _, stats = nmf.nmf_dense(A, W, H, algo=wl["algo"], iters=args.steps, objective=False,
+                             timers=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = args.steps / elapsed
+
+    flops_per_launch = 2.0 * m * n * k
+    ms_launch = 0.5 * (stats["ms_mm_aht"] + stats["ms_mm_wta"]) / args.steps
+    peak = PEAK_FP32_TFLOPS if wl["dtype"] == "f32" else PEAK_FP64_TFLOPS
+    achieved = flops_per_launch / (ms_launch * 1e-3) / 1e12
+    src_hash = kernel_source_hash()
+    tr = load_traffic(src_hash)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
+                "traffic": (tr["hbm_bytes_per_launch"] if tr else None),
+                "kernel": "dense products A H^T and W^T A (MFMA 16x16x4 f32)",
+                "ms_per_launch": round(ms_launch, 4),
+                "ms_aht": round(stats["ms_mm_aht"] / args.steps, 4),
+                "ms_wta": round(stats["ms_mm_wta"] / args.steps, 4),
+                "algorithmic_flops_per_launch": flops_per_launch}
+    iter_flops = 4.0 * m * n * k
+    out = {
+        "metric": "NMF iterations/s (dense HALS, A 65536x65536 fp32, k=50)"
+                  if args.workload.startswith("dense-65536") else "NMF iterations/s",
+        "value": round(value, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": wl["dtype"], "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "algorithm": wl["algo"],
+                   "parallelism": "single-gpu"},
+        "tflops_products": round(iter_flops / (ms_per_step * 1e-3) / 1e12, 2),
+        "phase_ms_per_step": {p: round(stats[f] / args.steps, 4) for p, f in
+                              (("mm", "ms_mm"), ("luc", "ms_luc"), ("gram", "ms_gram"))},
+        "roofline": roofline,
+    }
+    if args.check:
+        rel = nmf.nmf_dense_relerr(A, W, H.t().contiguous())
+        out["final_rel_err"] = rel
+    del A
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, min(args.sample_rows, m))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

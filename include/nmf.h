@@ -90,6 +90,8 @@ typedef struct {
   double ms_obj;     /* objective evaluations                                */
   double ms_setup;   /* layout copies, CSR transpose                         */
   long long bpp_pivots; /* ABPP: total passive-set solves over all RHS       */
+  double ms_mm_aht;  /* the A H^T part of ms_mm (one launch group per iter.) */
+  double ms_mm_wta;  /* the W^T A part of ms_mm                              */
 } nmf_stats;
 
 typedef struct nmf_ctx nmf_ctx;

@@ -35,7 +35,8 @@ class NmfStats(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_double), ("ms_mm", ctypes.c_double),
                 ("ms_luc", ctypes.c_double), ("ms_gram", ctypes.c_double),
                 ("ms_obj", ctypes.c_double), ("ms_setup", ctypes.c_double),
-                ("bpp_pivots", ctypes.c_longlong)]
+                ("bpp_pivots", ctypes.c_longlong), ("ms_mm_aht", ctypes.c_double),
+                ("ms_mm_wta", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -150,7 +150,9 @@ struct Timers {
       hipEventElapsedTime(&ms, marks[i].first, marks[i + 1].first);
       if (marks[i].second >= 0) acc[marks[i].second] += ms;
     }
-    s->ms_mm += acc[0];
+    s->ms_mm_aht += acc[0];
+    s->ms_mm_wta += acc[5];
+    s->ms_mm += acc[0] + acc[5];
     s->ms_luc += acc[1];
     s->ms_gram += acc[2];
     s->ms_obj += acc[3];
@@ -162,7 +164,7 @@ struct Timers {
     for (auto& m : marks) hipEventDestroy(m.first);
   }
 };
-enum { PH_MM = 0, PH_LUC = 1, PH_GRAM = 2, PH_OBJ = 3, PH_SETUP = 4, PH_END = -1 };
+enum { PH_MM = 0, PH_LUC = 1, PH_GRAM = 2, PH_OBJ = 3, PH_SETUP = 4, PH_MM_T = 5, PH_END = -1 };
 
 template <typename T> nmf_dtype dtype_of();
 template <> nmf_dtype dtype_of<float>() { return NMF_F32; }
@@ -374,7 +376,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
       tm.mark(PH_LUC);
       HIP_TRY(nmfk::hals_normalize<T>(w.W, m, w.Ht, n, w.S, w.norms, k, KP, st));
     }
-    tm.mark(PH_MM);
+    tm.mark(PH_MM_T);
     RUN(product_AtF<T>(ctx, pb, m, n, w.W, KP, w.R, w.part));
     tm.mark(PH_LUC);
     RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots));

@@ -13,19 +13,23 @@
 //     matrix D G D + (I - D), D = diag(F), by Cholesky: lane i keeps row i
 //     in registers, each column of the factor is broadcast through LDS, and
 //     the factor's rows go to LDS once for the backward solve.
-// A non-positive pivot (G_FF not numerically positive definite) sets
-// status |= 1; reaching the pivot cap sets status |= 2.
+// The factorisation, the solves and the sign tests run in double for every
+// storage type: with float arithmetic, rounding noise on entries whose exact
+// value is zero flips their sign from one pivot to the next and the pivoting
+// can cycle. A non-positive pivot (G_FF not numerically positive definite)
+// sets status |= 1; reaching the pivot cap sets status |= 2.
 #include "common.h"
 #include "kernels.h"
 
 namespace nmfk {
 
-template <typename T, int KP>
-__global__ __launch_bounds__(64) void bpp_kernel(T* __restrict__ X, const T* __restrict__ P,
-                                                 const T* __restrict__ G, int64_t rows, int k,
+template <typename TS, int KP>
+__global__ __launch_bounds__(64) void bpp_kernel(TS* __restrict__ X, const TS* __restrict__ P,
+                                                 const TS* __restrict__ G, int64_t rows, int k,
                                                  int max_pivots, int* __restrict__ status,
                                                  unsigned long long* __restrict__ pivots) {
   static_assert(KP <= 64, "one lane per index");
+  typedef double T;  // compute type
   constexpr int LD = KP + 1;
   __shared__ T Gs[KP * LD];
   __shared__ T Ls[KP * LD];
@@ -34,13 +38,13 @@ __global__ __launch_bounds__(64) void bpp_kernel(T* __restrict__ X, const T* __r
   const int i = threadIdx.x;
   const bool lanei = i < KP;
   const bool act = i < k;
-  for (int e = i; e < KP * KP; e += 64) Gs[(e / KP) * LD + (e % KP)] = G[e];
+  for (int e = i; e < KP * KP; e += 64) Gs[(e / KP) * LD + (e % KP)] = (T)G[e];
   __syncthreads();
 
   unsigned long long my_pivots = 0;
   int my_status = 0;
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-    const T p = act ? P[r * KP + i] : T(0);
+    const T p = act ? (T)P[r * KP + i] : T(0);
     T x = T(0), y = -p;
     uint64_t F = 0;
     int budget = 3, best = k + 1, npiv = 0;
@@ -123,7 +127,7 @@ __global__ __launch_bounds__(64) void bpp_kernel(T* __restrict__ X, const T* __r
       __syncthreads();
     }
     my_pivots += (unsigned long long)npiv;
-    if (lanei) X[r * KP + i] = act ? (x > T(0) ? x : T(0)) : T(0);
+    if (lanei) X[r * KP + i] = act ? (TS)(x > T(0) ? x : T(0)) : TS(0);
   }
   if (i == 0) {
     atomicAdd(pivots, my_pivots);

@@ -137,7 +137,7 @@ def erdos_renyi_csr(m: int, n: int, density: float, seed: int = DATA_SEED,
     total = m * n
     pieces = []
     pos = -1
-    while True:
+    while density > 0:
         gaps = rng.geometric(density, size=chunk).astype(np.int64)
         p = pos + np.cumsum(gaps)
         cut = np.searchsorted(p, total)
