@@ -80,6 +80,9 @@ typedef struct {
   int timers;        /* nonzero: fill the per-phase times in nmf_stats       */
   int check_input;   /* nonzero: scan A for NaN/Inf/negative entries and the */
                      /* CSR arrays for out-of-range or unsorted columns      */
+  int transpose_a;   /* dense A: 0 (default) keeps a transposed copy of A in */
+                     /* device memory for the call when it fits (both large  */
+                     /* products then stream A row by row); -1 never does    */
 } nmf_opts;
 
 typedef struct {
@@ -97,7 +100,8 @@ typedef struct {
 typedef struct nmf_ctx nmf_ctx;
 
 /* Fills *opts with the defaults: MU, 0 iterations, eps_mu 1e-16,
- * max_pivots 0 (= 50 k), no objective, no timers, no input check. */
+ * max_pivots 0 (= 50 k), no objective, no timers, no input check,
+ * transpose_a 0. */
 void nmf_default_opts(nmf_opts* opts);
 
 /* Creates a context bound to HIP device `device` and the HIP stream

@@ -104,9 +104,10 @@ def _ctx(ctx, device) -> Context:
 
 
 def nmf_dense(A, W, H, algo="hals", iters=10, objective=True, eps_mu=1e-16, max_pivots=0,
-              timers=False, check_input=False, ctx=None):
+              timers=False, check_input=False, transpose_a=True, ctx=None):
     """Algorithm 1 on dense A (m x n); W (m x k) and H (k x n) are updated in
-    place. Returns (rel_err list or None, stats dict)."""
+    place. transpose_a=False keeps the library from holding a transposed
+    copy of A. Returns (rel_err list or None, stats dict)."""
     torch = _torch()
     m, n = A.shape
     k = W.shape[1]
@@ -117,7 +118,8 @@ def nmf_dense(A, W, H, algo="hals", iters=10, objective=True, eps_mu=1e-16, max_
     c = _ctx(ctx, A.device.index or 0)
     o = default_opts(algo=algo, iters=iters, eps_mu=eps_mu, max_pivots=max_pivots,
                      objective=NMF_OBJ_DIRECT if objective else NMF_OBJ_NONE,
-                     timers=1 if timers else 0, check_input=1 if check_input else 0)
+                     timers=1 if timers else 0, check_input=1 if check_input else 0,
+                     transpose_a=0 if transpose_a else -1)
     errs = (ctypes.c_double * (iters + 1))() if objective else None
     stats = NmfStats()
     rc = _lib.lib().nmf_dense(c.handle, _dtype_code(A), m, n, pa, A.stride(0), k, ctypes.byref(o),

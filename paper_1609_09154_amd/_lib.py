@@ -28,7 +28,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class NmfOpts(ctypes.Structure):
     _fields_ = [("algo", _int), ("iters", _int), ("eps_mu", ctypes.c_double),
                 ("max_pivots", _int), ("objective", _int), ("timers", _int),
-                ("check_input", _int)]
+                ("check_input", _int), ("transpose_a", _int)]
 
 
 class NmfStats(ctypes.Structure):

@@ -28,6 +28,8 @@ struct nmf_ctx {
   std::string err;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  void* at = nullptr;    // transposed copy of a dense A (see nmf_opts.transpose_a)
+  size_t at_bytes = 0;
 };
 
 namespace {
@@ -89,13 +91,6 @@ int kp_sparse(int k) {
   return kp;
 }
 
-// Splits of the reduction index for the large products: enough workgroups to
-// give every CU at least two, each split still long.
-int64_t product_splits(int64_t wgs, int64_t K) {
-  int64_t s = 1;
-  while (wgs * s < 512 && K / (2 * s) >= 4096 && s < 16) s *= 2;
-  return s;
-}
 int64_t gram_splits(int64_t rows) {
   int64_t s = cdiv(rows, 256);
   return s < 1 ? 1 : (s > 1024 ? 1024 : s);
@@ -173,6 +168,7 @@ template <> nmf_dtype dtype_of<double>() { return NMF_F64; }
 // Everything one AU-NMF call needs on the device.
 template <typename T> struct Work {
   T *W, *Ht, *P, *R, *Q, *S, *norms, *part;
+  T *Wt, *Hk;  // W^T (KP x m) and H (KP x n): the rank side of the dense products
   double *obj_part, *relerr, *normA;
   int* status;
   unsigned long long* pivots;
@@ -195,20 +191,19 @@ nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, i
 
 template <typename T>
 nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part) {
-  nmfk::GemmArgs<T> a{X, KP, X, KP, G, KP, KP, KP, rows};
+  nmfk::GemmArgs<T> a{X, KP, X, KP, G, KP, KP, KP, rows, false, 0};
   HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(rows), part, ctx->stream));
   return NMF_OK;
 }
 
-template <typename T>
-int64_t mw_rows() { return 16 * 4 * 4; }  // rows per workgroup of the product kernels
 
 // Workspace offsets for an AU-NMF call on an m x n problem.
 template <typename T>
 size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_t extra_part,
-                 Carve& cv, size_t off[12]) {
-  const int64_t ps_p = product_splits(cdiv(m, mw_rows<T>()), n);
-  const int64_t ps_r = product_splits(cdiv(n, mw_rows<T>()), m);
+                 Carve& cv, size_t off[14]) {
+  const int64_t ps_p = std::max(nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
+                                nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n));
+  const int64_t ps_r = nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m);
   int64_t part = ps_p > 1 ? ps_p * m * KP : 0;
   part = std::max<int64_t>(part, ps_r > 1 ? ps_r * n * KP : 0);
   part = std::max<int64_t>(part, gram_splits(std::max(m, n)) * KP * KP);
@@ -225,11 +220,13 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[9] = cv.take<double>(iters + 2);
   off[10] = cv.take<int>(4);
   off[11] = cv.take<unsigned long long>(2);
+  off[12] = cv.take<T>(m * KP);
+  off[13] = cv.take<T>(n * KP);
   return cv.off;
 }
 
 template <typename T>
-Work<T> bind_work(nmf_ctx* ctx, const size_t off[12], int64_t obj_np) {
+Work<T> bind_work(nmf_ctx* ctx, const size_t off[14], int64_t obj_np) {
   Work<T> w;
   w.W = at<T>(ctx, off[0]);
   w.Ht = at<T>(ctx, off[1]);
@@ -244,6 +241,8 @@ Work<T> bind_work(nmf_ctx* ctx, const size_t off[12], int64_t obj_np) {
   w.relerr = at<double>(ctx, off[9]);
   w.status = at<int>(ctx, off[10]);
   w.pivots = at<unsigned long long>(ctx, off[11]);
+  w.Wt = at<T>(ctx, off[12]);
+  w.Hk = at<T>(ctx, off[13]);
   w.obj_np = obj_np;
   return w;
 }
@@ -266,14 +265,17 @@ nmf_status read_status(nmf_ctx* ctx, const int* dstatus, const unsigned long lon
 template <typename T> struct Prob {
   bool sparse = false;
   const T* A = nullptr; int64_t lda = 0;                 // dense
+  const T* At = nullptr;                                 // dense A^T (n x m, ld m) or null
   const int64_t* rp = nullptr; const int32_t* ci = nullptr; const float* cv = nullptr;  // CSR A
   const int64_t* rpt = nullptr; const int32_t* cit = nullptr; const float* cvt = nullptr; // CSR A^T
   int64_t nnz = 0;
 };
 
+// Ft (nullable) is F transposed (KP x rows of F); the dense kernels then read
+// the rank-side operand with 16-byte loads.
 template <typename T>
-nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int KP,
-                      T* Pout, T* part) {
+nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F,
+                      const T* Ft, int k, int KP, T* Pout, T* part) {
   if (pb.sparse) {
     if constexpr (sizeof(T) == 4) {
       HIP_TRY(nmfk::csr_spmm(pb.rp, pb.ci, pb.cv, m, F, KP, Pout, ctx->stream));
@@ -281,15 +283,22 @@ nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, con
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
   }
-  nmfk::GemmArgs<T> a{pb.A, pb.lda, F, KP, Pout, KP, m, KP, n};
-  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::NN, a, product_splits(cdiv(m, mw_rows<T>()), n), part,
-                            ctx->stream));
+  if (pb.At) {
+    // A H^T = (A^T)^T H^T: the TN kernel streaming A^T row by row.
+    nmfk::GemmArgs<T> a{pb.At, m, Ft ? Ft : F, Ft ? n : (int64_t)KP, Pout, KP, m, KP, n,
+                        Ft != nullptr, k};
+    HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, 0, part, ctx->stream));
+    return NMF_OK;
+  }
+  nmfk::GemmArgs<T> a{pb.A, pb.lda, Ft ? Ft : F, Ft ? n : (int64_t)KP, Pout, KP, m, KP, n,
+                      Ft != nullptr, k};
+  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::NN, a, 0, part, ctx->stream));
   return NMF_OK;
 }
 
 template <typename T>
-nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int KP,
-                       T* Rout, T* part) {
+nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F,
+                       const T* Ft, int k, int KP, T* Rout, T* part) {
   if (pb.sparse) {
     if constexpr (sizeof(T) == 4) {
       HIP_TRY(nmfk::csr_spmm(pb.rpt, pb.cit, pb.cvt, n, F, KP, Rout, ctx->stream));
@@ -297,9 +306,9 @@ nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, co
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
   }
-  nmfk::GemmArgs<T> a{pb.A, pb.lda, F, KP, Rout, KP, n, KP, m};
-  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, product_splits(cdiv(n, mw_rows<T>()), m), part,
-                            ctx->stream));
+  nmfk::GemmArgs<T> a{pb.A, pb.lda, Ft ? Ft : F, Ft ? m : (int64_t)KP, Rout, KP, n, KP, m,
+                      Ft != nullptr, k};
+  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, 0, part, ctx->stream));
   return NMF_OK;
 }
 
@@ -361,12 +370,17 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     RUN(norm_sq_A<T>(ctx, pb, m, n, w));
     RUN(objective<T>(ctx, pb, m, n, k, KP, w, 0));
   }
+  // Transposed factor copies for the dense products (read with 16-byte loads,
+  // so their rows must stay 16-byte aligned).
+  const bool tH = !pb.sparse && (n * (int64_t)sizeof(T)) % 16 == 0;
+  const bool tW = !pb.sparse && (m * (int64_t)sizeof(T)) % 16 == 0;
+  if (tH && o->iters > 0) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
     tm.mark(PH_GRAM);
     RUN(gram<T>(ctx, w.Ht, n, KP, w.Q, w.part));
     tm.mark(PH_MM);
-    RUN(product_AF<T>(ctx, pb, m, n, w.Ht, KP, w.P, w.part));
+    RUN(product_AF<T>(ctx, pb, m, n, w.Ht, tH ? w.Hk : nullptr, k, KP, w.P, w.part));
     tm.mark(PH_LUC);
     RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots));
     // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
@@ -376,10 +390,12 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
       tm.mark(PH_LUC);
       HIP_TRY(nmfk::hals_normalize<T>(w.W, m, w.Ht, n, w.S, w.norms, k, KP, st));
     }
+    if (tW) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
     tm.mark(PH_MM_T);
-    RUN(product_AtF<T>(ctx, pb, m, n, w.W, KP, w.R, w.part));
+    RUN(product_AtF<T>(ctx, pb, m, n, w.W, tW ? w.Wt : nullptr, k, KP, w.R, w.part));
     tm.mark(PH_LUC);
     RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots));
+    if (tH && t + 1 < o->iters) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
     if (want_obj) {
       tm.mark(PH_OBJ);
       RUN(objective<T>(ctx, pb, m, n, k, KP, w, t + 1));
@@ -417,6 +433,37 @@ nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_ob
   return NMF_OK;
 }
 
+// A^T into the context's second buffer, when it fits next to everything else
+// with a quarter of the device memory to spare; *out stays null otherwise.
+template <typename T>
+nmf_status transposed_copy(nmf_ctx* ctx, const T* A, int64_t lda, int64_t m, int64_t n,
+                           const T** out) {
+  *out = nullptr;
+  const size_t need = (size_t)m * (size_t)n * sizeof(T);
+  if (ctx->at_bytes < need) {
+    size_t freeb = 0, total = 0;
+    HIP_TRY(hipMemGetInfo(&freeb, &total));
+    const size_t reuse = ctx->at_bytes;
+    if (freeb + reuse < need + total / 4) return NMF_OK;
+    if (ctx->at) {
+      HIP_TRY(hipStreamSynchronize(ctx->stream));
+      HIP_TRY(hipFree(ctx->at));
+      ctx->at = nullptr;
+      ctx->at_bytes = 0;
+    }
+    if (hipMalloc(&ctx->at, need) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->at = nullptr;
+      return NMF_OK;
+    }
+    ctx->at_bytes = need;
+  }
+  T* At = (T*)ctx->at;
+  HIP_TRY(nmfk::transpose_full<T>(A, lda, m, n, At, ctx->stream));
+  *out = At;
+  return NMF_OK;
+}
+
 template <typename T>
 nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t lda, int k,
                       const nmf_opts* o, T* W, T* H, double* rel_err, nmf_stats* stats) {
@@ -424,7 +471,7 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t ld
   const bool want_obj = o->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max(nmfk::residual_partials<T>(m, n), nmfk::sumsq_partials<T>(m, n));
   Carve cv;
-  size_t off[12];
+  size_t off[14];
   plan_work<T>(m, n, KP, o->iters, obj_np, 0, cv, off);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
@@ -448,6 +495,9 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t ld
   Prob<T> pb;
   pb.A = A;
   pb.lda = lda;
+  if (o->iters > 0 && o->transpose_a == 0) {
+    if ((s = transposed_copy<T>(ctx, A, lda, m, n, &pb.At)) != NMF_OK) return s;
+  }
   s = run_au_nmf<T>(ctx, pb, m, n, k, KP, o, w, want_obj, tm);
   if (stats) HIP_TRY(hipEventRecord(t1, st));
   if (s == NMF_OK) {
@@ -476,6 +526,7 @@ void nmf_default_opts(nmf_opts* o) {
   o->objective = NMF_OBJ_NONE;
   o->timers = 0;
   o->check_input = 0;
+  o->transpose_a = 0;
 }
 
 const char* nmf_status_str(nmf_status s) {
@@ -514,10 +565,11 @@ nmf_status nmf_create(nmf_ctx** out, int device, void* hip_stream) {
 
 void nmf_destroy(nmf_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->ws && ctx->device >= 0) {
+  if ((ctx->ws || ctx->at) && ctx->device >= 0) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(ctx->ws);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->at) (void)hipFree(ctx->at);
   }
   delete ctx;
 }
@@ -561,7 +613,7 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   const bool want_obj = opts->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max<int64_t>(nmfk::csr_residual_partials(m), 1024);
   Carve cv;
-  size_t off[12];
+  size_t off[14];
   plan_work<T>(m, n, KP, opts->iters, obj_np, 0, cv, off);
   const size_t o_rpt = cv.take<int64_t>(n + 1);
   const size_t o_cit = cv.take<int32_t>(nnz);
@@ -660,22 +712,27 @@ nmf_status dense_prod_impl(nmf_ctx* ctx, bool transA, int64_t m, int64_t n, cons
                            int64_t lda, int k, const T* F, int64_t ldf, T* Out) {
   const int KP = kp_dense(k);
   const int64_t frows = transA ? m : n, orows = transA ? n : m;
-  const int64_t splits = transA ? product_splits(cdiv(n, mw_rows<T>()), m)
-                                : product_splits(cdiv(m, mw_rows<T>()), n);
+  const int64_t splits = transA ? nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m)
+                                : nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n);
   Carve cv;
   const size_t oF = cv.take<T>(frows * KP);
+  const size_t oFt = cv.take<T>(frows * KP);
   const size_t oO = cv.take<T>(orows * KP);
   const size_t oP = cv.take<T>(splits > 1 ? splits * orows * KP : 1);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   T* Fp = at<T>(ctx, oF);
+  T* Ft = at<T>(ctx, oFt);
   T* Op = at<T>(ctx, oO);
   if ((s = pad_any<T>(ctx, F, frows, k, ldf, Fp, KP)) != NMF_OK) return s;
+  // The transposed copy is read with 16-byte loads: rows must stay aligned.
+  const bool use_t = (frows * (int64_t)sizeof(T)) % 16 == 0;
+  if (use_t) HIP_TRY(nmfk::transpose_rows<T>(Fp, frows, KP, Ft, ctx->stream));
   Prob<T> pb;
   pb.A = A;
   pb.lda = lda;
-  s = transA ? product_AtF<T>(ctx, pb, m, n, Fp, KP, Op, at<T>(ctx, oP))
-             : product_AF<T>(ctx, pb, m, n, Fp, KP, Op, at<T>(ctx, oP));
+  s = transA ? product_AtF<T>(ctx, pb, m, n, Fp, use_t ? Ft : nullptr, k, KP, Op, at<T>(ctx, oP))
+             : product_AF<T>(ctx, pb, m, n, Fp, use_t ? Ft : nullptr, k, KP, Op, at<T>(ctx, oP));
   if (s != NMF_OK) return s;
   HIP_TRY(nmfk::unpad_rows<T>(Op, orows, k, KP, Out, ctx->stream));
   return NMF_OK;
@@ -747,7 +804,7 @@ nmf_status relerr_impl(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, in
                                    : std::max(nmfk::residual_partials<T>(m, n),
                                               nmfk::sumsq_partials<T>(m, n));
   Carve cv;
-  size_t off[12];
+  size_t off[14];
   plan_work<T>(m, n, KP, 0, obj_np, 0, cv, off);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;

@@ -32,6 +32,12 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// 16 independent 4x4 blocks, k = 1: block b = l / 4 takes A_b[i] from lane
+// 4b + i and B_b[j] from lane 4b + j; lane 4b + j holds D_b[r][j] in element r.
+__device__ __forceinline__ f32x4 mfma4x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
 // Row of the 16x16 output held by lane `lane` in accumulator element `r`.
 // f32: lane l holds rows 4*(l/16) + r; f64: rows 4*r + l/16. Column is l % 16.
 template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);

@@ -10,19 +10,28 @@ namespace nmfk {
 
 enum class GemmKind { NN, TN, TN_GRAM };
 
-// D (M x N) = X * Y (NN, X is M x K) or X^T * Y (TN, X is K x M); Y is K x N.
-// N must be a multiple of 16 between 16 and 128.
+// D (M x N) = X * Y (NN, X is M x K) or X^T * Y (TN, X is K x M). Y is
+// K x N, or, with yt set, its transpose N x K (ldy between its N rows; then
+// Y must be 16-byte aligned with ldy a multiple of 16 bytes). N must be a
+// multiple of 16 between 16 and 128.
 template <typename T> struct GemmArgs {
   const T* X; int64_t ldx;
   const T* Y; int64_t ldy;
   T* D; int64_t ldd;
   int64_t M, N, K;
+  bool yt;
+  int nvalid;  // output columns that matter (0: all N); columns >= nvalid may be 0
 };
 
-// `part` must hold splits * M * N elements when splits > 1.
+// `part` must hold splits * M * N elements when splits > 1. splits <= 0 picks
+// the split count automatically (gemm_auto_splits, at most
+// MAX_PRODUCT_SPLITS for the products).
+constexpr int64_t MAX_PRODUCT_SPLITS = 4;
 template <typename T>
 hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a, int64_t splits, T* part,
                     hipStream_t st);
+template <typename T>
+int64_t gemm_auto_splits(GemmKind kind, int64_t M, int64_t N, int64_t K);
 
 // Local updates on rows x KP row-major factors (leading dimension KP); k is
 // the true rank, entries k..KP-1 are zero padding and stay zero.
@@ -44,6 +53,12 @@ template <typename T>
 hipError_t pad_rows(const T* src, int64_t rows, int k, T* dst, int KP, hipStream_t st);
 template <typename T>
 hipError_t unpad_rows(const T* src, int64_t rows, int k, int KP, T* dst, hipStream_t st);
+// At (n x m, ld m) = A^T for A (m x n, lda).
+template <typename T>
+hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, hipStream_t st);
+// src (rows x KP, row major) -> dst (KP x rows, row major), all KP rows.
+template <typename T>
+hipError_t transpose_rows(const T* src, int64_t rows, int KP, T* dst, hipStream_t st);
 // H (k x n, ld n) -> Ht (n x KP) and back.
 template <typename T>
 hipError_t transpose_in(const T* H, int k, int64_t n, T* Ht, int KP, hipStream_t st);

@@ -284,6 +284,41 @@ __global__ void transpose_out_kernel(const T* __restrict__ Ht, int k, int64_t n,
   }
 }
 
+// Full transpose of a dense matrix (A, m x n, lda) into At (n x m, ld m),
+// 64 x 64 tiles through LDS so both the reads and the writes are 256-byte
+// row segments.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_full_kernel(const T* __restrict__ A,
+                                                             int64_t lda, int64_t m, int64_t n,
+                                                             T* __restrict__ At) {
+  __shared__ T tile[64][65];
+  const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    tile[i][tx] = (r < m && c < n) ? __builtin_nontemporal_load(A + r * lda + c) : T(0);
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < n && r < m) At[c * m + r] = tile[tx][i];
+  }
+}
+
+template <typename T>
+hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, hipStream_t st) {
+  dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
+  transpose_full_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, At);
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t transpose_rows(const T* src, int64_t rows, int KP, T* dst, hipStream_t st) {
+  dim3 grid((unsigned)cdiv(rows, 32), (unsigned)cdiv(KP, 32));
+  transpose_out_kernel<T><<<grid, 256, 0, st>>>(src, KP, rows, KP, dst);
+  return NMF_LAUNCH_CHECK();
+}
+
 template <typename T>
 hipError_t pad_rows(const T* src, int64_t rows, int k, T* dst, int KP, hipStream_t st) {
   const int64_t total = rows * KP;
@@ -322,7 +357,9 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
   template hipError_t pad_rows<T>(const T*, int64_t, int, T*, int, hipStream_t);            \
   template hipError_t unpad_rows<T>(const T*, int64_t, int, int, T*, hipStream_t);          \
   template hipError_t transpose_in<T>(const T*, int, int64_t, T*, int, hipStream_t);        \
-  template hipError_t transpose_out<T>(const T*, int, int64_t, int, T*, hipStream_t);
+  template hipError_t transpose_out<T>(const T*, int, int64_t, int, T*, hipStream_t);         \
+  template hipError_t transpose_rows<T>(const T*, int64_t, int, T*, hipStream_t);            \
+  template hipError_t transpose_full<T>(const T*, int64_t, int64_t, int64_t, T*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

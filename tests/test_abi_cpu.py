@@ -39,7 +39,9 @@ def test_status_strings_and_defaults():
     assert L.nmf_status_str(5) == b"NMF_ENOTCONV"
     o = _lib.default_opts()
     assert o.algo == _lib.NMF_MU and o.iters == 0 and o.eps_mu == 1e-16
-    assert o.max_pivots == 0 and o.objective == 0
+    assert o.max_pivots == 0 and o.objective == 0 and o.transpose_a == 0
+    # the ctypes mirrors must be at least as large as the C structs they stand for
+    assert ctypes.sizeof(_lib.NmfOpts) == 8 * 5 and ctypes.sizeof(_lib.NmfStats) == 8 * 9
 
 
 @pytest.fixture

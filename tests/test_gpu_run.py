@@ -72,6 +72,19 @@ def test_f32_runs(algo, m, n, k, iters):
     assert (W >= 0).all() and (H >= 0).all()
 
 
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_without_transposed_copy(dt):
+    """transpose_a=False keeps A H^T on the NN kernel; same bar as above."""
+    A, W0, H0 = dense_case(1030, 777, 50, 50, 21, dt)
+    step("hals no transposed copy %s" % dt.__name__)
+    W, H, e, _ = run_dense(A, W0, H0, "hals", 6, dt, transpose_a=False)
+    W2, H2, e2, _ = run_dense(A, W0, H0, "hals", 6, dt)
+    _, _, er = oracle.run(A.astype(np.float64), 50, "hals", 6, W0.astype(np.float64),
+                          H0.astype(np.float64))
+    bar = 1e-5 if dt == np.float32 else 1e-10
+    assert rel_diff(e, er) <= bar and rel_diff(e2, er) <= bar
+
+
 def test_hals_objective_monotone_and_normalised():
     A, W0, H0 = dense_case(2500, 2000, 50, 50, 5, np.float32)
     step("hals f32 monotone")
