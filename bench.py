@@ -42,6 +42,8 @@ WORKLOADS = {
     "dense-65536x65536-k50-hals-f32": dict(m=65536, n=65536, k=50, k_true=50, algo="hals",
                                            dtype="f32"),
     "dense-2000x1000-k10-mu-f64": dict(m=2000, n=1000, k=10, k_true=10, algo="mu", dtype="f64"),
+    "csr-1048576x1048576-d1e-4-k50-abpp-f32": dict(m=1 << 20, n=1 << 20, k=50, density=1e-4,
+                                                   algo="abpp", dtype="f32", sparse=True),
 }
 
 
@@ -94,6 +96,66 @@ def cpu_baseline(wl, sample_rows, iters=6):
                                                    scale, wl["m"], wl["n"])}
 
 
+def run_sparse(args, wl):
+    """Sparse workload: ER CSR A, ABPP. roofline: the SpMM on HBM, with its
+    compulsory bytes (values and column ids once, row pointers, the dense
+    operand once, the output once) per launch."""
+    import numpy as np
+    import torch
+
+    import paper_1609_09154_amd as nmf
+    from synth import erdos_renyi_csr, init_factors
+
+    m, n, k = wl["m"], wl["n"], wl["k"]
+    dev = torch.device("cuda:0")
+    print("[bench] generating %s" % args.workload, file=sys.stderr, flush=True)
+    csr = erdos_renyi_csr(m, n, wl["density"], seed=1609)
+    nnz = csr.nnz
+    rp = torch.from_numpy(csr.rowptr).to(dev)
+    ci = torch.from_numpy(csr.colidx).to(dev)
+    cv = torch.from_numpy(csr.vals.astype(np.float32)).to(dev)
+    W0n, H0n = init_factors(m, n, k, seed=9154)
+    W0 = torch.from_numpy(W0n.astype(np.float32)).to(dev)
+    H0 = torch.from_numpy(H0n.astype(np.float32)).to(dev)
+    del csr
+    torch.cuda.synchronize()
+    print("[bench] warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    W, H = W0.clone(), H0.clone()
+    nmf.nmf_csr(rp, ci, cv, n, W, H, algo=wl["algo"], iters=args.warmup, objective=False)
+    W.copy_(W0)
+    H.copy_(H0)
+    torch.cuda.synchronize()
+    print("[bench] timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    _, st = nmf.nmf_csr(rp, ci, cv, n, W, H, algo=wl["algo"], iters=args.steps, objective=False,
+                        timers=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1000.0 * elapsed / args.steps
+    comp_bytes = 8.0 * nnz + 8.0 * (m + 1) + 4.0 * n * k + 4.0 * m * k
+    ms_spmm = 0.5 * (st["ms_mm_aht"] + st["ms_mm_wta"]) / args.steps
+    achieved = comp_bytes / (ms_spmm * 1e-3) / 1e9
+    out = {
+        "metric": "NMF iterations/s (sparse ABPP, ER CSR 2^20 x 2^20, d=1e-4, k=50)",
+        "value": round(args.steps / elapsed, 3), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "nnz": nnz,
+                   "algorithm": wl["algo"], "parallelism": "single-gpu"},
+        "phase_ms_per_step": {p: round(st[f] / args.steps, 4) for p, f in
+                              (("mm", "ms_mm"), ("luc", "ms_luc"), ("gram", "ms_gram"))},
+        "setup_ms": round(st["ms_setup"], 3),
+        "bpp_pivots_per_rhs": round(st["bpp_pivots"] / float(args.steps * (m + n)), 3),
+        "nnls_solves_per_s": round(args.steps * (m + n) / (st["ms_luc"] * 1e-3), 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "csr_spmm (A H^T and A^T W)", "ms_per_launch": round(ms_spmm, 4),
+                     "algorithmic_bytes_per_launch": comp_bytes},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +180,8 @@ def main():
     from synth import init_factors, planted_dense_torch
 
     wl = WORKLOADS[args.workload]
+    if wl.get("sparse"):
+        return run_sparse(args, wl)
     m, n, k = wl["m"], wl["n"], wl["k"]
     tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
     dev = torch.device("cuda:0")

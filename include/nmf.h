@@ -120,8 +120,8 @@ const char* nmf_last_error(const nmf_ctx* ctx);
 /* Full AU-NMF on a dense A (Algorithm 1).
  *   A       m x n, leading dimension lda >= n, element type a_dtype.
  *   W       m x k (leading dimension k), same element type: the initial W on
- *           entry (read by MU and HALS, ignored by ABPP, whose W step is an
- *           exact solve), the final W on return.
+ *           entry (read by MU and HALS; ABPP's W step is an exact solve that
+ *           only takes its starting passive sets from it), the final W.
  *   H       k x n (leading dimension n): initial H on entry, final H on return.
  *   rel_err host array of iters+1 doubles or NULL; requires opts->objective.
  *   stats   host pointer or NULL.
@@ -186,7 +186,9 @@ nmf_status nmf_csr_transpose(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
  *             x_i <- max(0, x_i + (p_i - x G_:i) / G_ii)        (Eq. (5))
  *             (no normalisation here; see nmf_hals_normalize)
  *   NMF_ABPP: x <- argmin_{x >= 0} 1/2 x^T G x - p^T x          (Eqs. (6)-(7))
- *             by block principal pivoting; the incoming X is ignored.
+ *             by block principal pivoting. The support of the incoming row
+ *             of X is only the starting passive set; the result is the
+ *             unique minimiser whatever X holds (G positive definite).
  *             pivots (host, nullable) receives the total number of
  *             passive-set solves. */
 nmf_status nmf_update(nmf_ctx* ctx, nmf_algo algo, nmf_dtype dtype,

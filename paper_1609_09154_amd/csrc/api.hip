@@ -169,22 +169,27 @@ template <> nmf_dtype dtype_of<double>() { return NMF_F64; }
 template <typename T> struct Work {
   T *W, *Ht, *P, *R, *Q, *S, *norms, *part;
   T *Wt, *Hk;  // W^T (KP x m) and H (KP x n): the rank side of the dense products
+  double* ginv;  // KP x KP, ABPP
   double *obj_part, *relerr, *normA;
   int* status;
   unsigned long long* pivots;
   int64_t obj_np;
 };
 
+// status points at 4 device ints: [0] ABPP flags, [1] input check, [2] G^-1 ok.
+// ginv: KP*KP doubles of scratch for ABPP.
 template <typename T>
 nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, int64_t rows,
                         int k, int KP, const nmf_opts* o, int* status,
-                        unsigned long long* pivots) {
+                        unsigned long long* pivots, double* ginv) {
   hipStream_t st = ctx->stream;
   if (algo == NMF_MU) HIP_TRY(nmfk::mu_rows<T>(X, Pm, G, rows, k, KP, (T)o->eps_mu, st));
   else if (algo == NMF_HALS) HIP_TRY(nmfk::hals_rows<T>(X, Pm, G, rows, k, KP, st));
   else {
     const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
-    HIP_TRY(nmfk::bpp_rows<T>(X, Pm, G, rows, k, KP, cap, status, pivots, st));
+    // the incoming X (the current iterate) starts each right-hand side's pivoting
+    HIP_TRY(nmfk::bpp_rows_compact<T>(X, Pm, G, rows, k, KP, cap, 1, ginv, status + 2, status,
+                                      pivots, st));
   }
   return NMF_OK;
 }
@@ -200,7 +205,7 @@ nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part) {
 // Workspace offsets for an AU-NMF call on an m x n problem.
 template <typename T>
 size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_t extra_part,
-                 Carve& cv, size_t off[14]) {
+                 Carve& cv, size_t off[15]) {
   const int64_t ps_p = std::max(nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
                                 nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n));
   const int64_t ps_r = nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m);
@@ -222,11 +227,12 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[11] = cv.take<unsigned long long>(2);
   off[12] = cv.take<T>(m * KP);
   off[13] = cv.take<T>(n * KP);
+  off[14] = cv.take<double>(KP * KP);
   return cv.off;
 }
 
 template <typename T>
-Work<T> bind_work(nmf_ctx* ctx, const size_t off[14], int64_t obj_np) {
+Work<T> bind_work(nmf_ctx* ctx, const size_t off[15], int64_t obj_np) {
   Work<T> w;
   w.W = at<T>(ctx, off[0]);
   w.Ht = at<T>(ctx, off[1]);
@@ -243,6 +249,7 @@ Work<T> bind_work(nmf_ctx* ctx, const size_t off[14], int64_t obj_np) {
   w.pivots = at<unsigned long long>(ctx, off[11]);
   w.Wt = at<T>(ctx, off[12]);
   w.Hk = at<T>(ctx, off[13]);
+  w.ginv = at<double>(ctx, off[14]);
   w.obj_np = obj_np;
   return w;
 }
@@ -382,7 +389,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     tm.mark(PH_MM);
     RUN(product_AF<T>(ctx, pb, m, n, w.Ht, tH ? w.Hk : nullptr, k, KP, w.P, w.part));
     tm.mark(PH_LUC);
-    RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots));
+    RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv));
     // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
     tm.mark(PH_GRAM);
     RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
@@ -394,7 +401,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     tm.mark(PH_MM_T);
     RUN(product_AtF<T>(ctx, pb, m, n, w.W, tW ? w.Wt : nullptr, k, KP, w.R, w.part));
     tm.mark(PH_LUC);
-    RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots));
+    RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots, w.ginv));
     if (tH && t + 1 < o->iters) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
     if (want_obj) {
       tm.mark(PH_OBJ);
@@ -471,7 +478,7 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t ld
   const bool want_obj = o->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max(nmfk::residual_partials<T>(m, n), nmfk::sumsq_partials<T>(m, n));
   Carve cv;
-  size_t off[14];
+  size_t off[15];
   plan_work<T>(m, n, KP, o->iters, obj_np, 0, cv, off);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
@@ -613,7 +620,7 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   const bool want_obj = opts->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max<int64_t>(nmfk::csr_residual_partials(m), 1024);
   Carve cv;
-  size_t off[14];
+  size_t off[15];
   plan_work<T>(m, n, KP, opts->iters, obj_np, 0, cv, off);
   const size_t o_rpt = cv.take<int64_t>(n + 1);
   const size_t o_cit = cv.take<int32_t>(nnz);
@@ -748,6 +755,7 @@ nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, 
   const size_t oX = cv.take<T>(rows * KP);
   const size_t oS = cv.take<int>(4);
   const size_t oV = cv.take<unsigned long long>(2);
+  const size_t oI = cv.take<double>(KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   T* Gp = at<T>(ctx, oG);
@@ -762,7 +770,9 @@ nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, 
   if (KP > k) HIP_TRY(hipMemsetAsync(Gp + (size_t)k * KP, 0, sizeof(T) * (KP - k) * KP, st));
   HIP_TRY(nmfk::pad_rows<T>(Pm, rows, k, Pp, KP, st));
   HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
-  if ((s = local_update<T>(ctx, algo, Xp, Pp, Gp, rows, k, KP, o, dst, dpv)) != NMF_OK) return s;
+  if ((s = local_update<T>(ctx, algo, Xp, Pp, Gp, rows, k, KP, o, dst, dpv, at<double>(ctx, oI))) !=
+      NMF_OK)
+    return s;
   HIP_TRY(nmfk::unpad_rows<T>(Xp, rows, k, KP, X, st));
   if (algo == NMF_ABPP) return read_status(ctx, dst, dpv, pivots);
   return NMF_OK;
@@ -804,7 +814,7 @@ nmf_status relerr_impl(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, in
                                    : std::max(nmfk::residual_partials<T>(m, n),
                                               nmfk::sumsq_partials<T>(m, n));
   Carve cv;
-  size_t off[14];
+  size_t off[15];
   plan_work<T>(m, n, KP, 0, obj_np, 0, cv, off);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;

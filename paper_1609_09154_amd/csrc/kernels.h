@@ -107,11 +107,13 @@ hipError_t check_csr(const int64_t* rowptr, const int32_t* colidx, const float* 
                      int64_t n, int64_t nnz, int* flag, hipStream_t st);
 
 // Batched NNLS by block principal pivoting: each row x of X (rows x KP)
-// becomes argmin_{x>=0} 1/2 x^T G x - p^T x. status (device int) is set to
-// 1 on a singular passive-set system, 2 on pivot-cap exhaustion; pivots
-// (device long long) accumulates the passive-set solves.
+// becomes argmin_{x>=0} 1/2 x^T G x - p^T x. With warm set, the support of
+// the incoming row starts the pivoting. Ginv: KP*KP doubles of scratch,
+// ginv_ok: one device int. status (device int) |= 1 on a singular system,
+// |= 2 on pivot-cap exhaustion; pivots (device) accumulates the solves.
 template <typename T>
-hipError_t bpp_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, int max_pivots,
-                    int* status, unsigned long long* pivots, hipStream_t st);
+hipError_t bpp_rows_compact(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
+                            int max_pivots, int warm, double* Ginv, int* ginv_ok, int* status,
+                            unsigned long long* pivots, hipStream_t st);
 
 }  // namespace nmfk
