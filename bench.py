@@ -36,6 +36,8 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dense_65536x65536_k50.json")
+TRAFFIC_FILE_CSR = os.path.join(ROOT, "profiles", "traffic_csr_spmm_1048576_d1e-4_k50.json")
+SPARSE_SOURCES = ("sparse.hip", "common.h")
 COPY_CAL_BYTES = 3 << 30
 
 WORKLOADS = {
@@ -47,17 +49,17 @@ WORKLOADS = {
 }
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=("gemm.hip", "common.h")):
     h = hashlib.sha256()
-    for f in ("gemm.hip", "common.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1609_09154_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(src_hash):
+def load_traffic(src_hash, path=TRAFFIC_FILE):
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -94,6 +96,19 @@ def cpu_baseline(wl, sample_rows, iters=6):
             "sample": "%d iterations of FP64 %s on a %dx%d planted matrix (k=%d), %.3f s/iter, "
                       "scaled by %.1f to %dx%d" % (iters, wl["algo"].upper(), s, s, wl["k"], dt,
                                                    scale, wl["m"], wl["n"])}
+
+
+def copy_calibration(dev):
+    """One device copy of COPY_CAL_BYTES: a dispatch of known traffic that
+    scales the HBM counters of the other dispatches in a counter run."""
+    import torch
+
+    src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def run_sparse(args, wl):
@@ -135,6 +150,8 @@ def run_sparse(args, wl):
     comp_bytes = 8.0 * nnz + 8.0 * (m + 1) + 4.0 * n * k + 4.0 * m * k
     ms_spmm = 0.5 * (st["ms_mm_aht"] + st["ms_mm_wta"]) / args.steps
     achieved = comp_bytes / (ms_spmm * 1e-3) / 1e9
+    tr = load_traffic(kernel_source_hash(SPARSE_SOURCES), TRAFFIC_FILE_CSR)
+    traffic = tr["hbm_bytes_per_launch"] if tr else None
     out = {
         "metric": "NMF iterations/s (sparse ABPP, ER CSR 2^20 x 2^20, d=1e-4, k=50)",
         "value": round(args.steps / elapsed, 3), "unit": "iters/s", "n_gpus": 1,
@@ -149,10 +166,16 @@ def run_sparse(args, wl):
         "bpp_pivots_per_rhs": round(st["bpp_pivots"] / float(args.steps * (m + n)), 3),
         "nnls_solves_per_s": round(args.steps * (m + n) / (st["ms_luc"] * 1e-3), 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "csr_spmm (A H^T and A^T W)", "ms_per_launch": round(ms_spmm, 4),
-                     "algorithmic_bytes_per_launch": comp_bytes},
+                     "algorithmic_bytes_per_launch": comp_bytes,
+                     "traffic_gbs": (round(traffic / (ms_spmm * 1e-3) / 1e9, 1) if traffic
+                                     else None),
+                     "traffic_frac": (round(traffic / (ms_spmm * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+                                      if traffic else None)},
     }
+    if args.copy_calibration:
+        copy_calibration(dev)
     print(json.dumps(out), flush=True)
 
 
@@ -241,12 +264,7 @@ def main():
         rel = nmf.nmf_dense_relerr(A, W, H.t().contiguous())
         out["final_rel_err"] = rel
     if args.copy_calibration:
-        src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(dev)
     del A
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

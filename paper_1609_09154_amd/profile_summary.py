@@ -1,6 +1,9 @@
 """Writes a short Markdown summary of a rocprofv3 kernel-trace database.
 
-    python -m paper_1609_09154_amd.profile_summary DB OUT.md "TITLE" "COMMAND"
+    python -m paper_1609_09154_amd.profile_summary DB OUT.md "TITLE" "COMMAND" [PATTERNS]
+
+PATTERNS: comma-separated kernel-name fragments whose dispatches are listed
+split at 1 ms (default: the dense product kernels).
 
 Reads the `top_kernels` view (name, calls, total and average duration in
 microseconds) and the per-dispatch `kernels` view of a rocpd SQLite file.
@@ -9,7 +12,7 @@ import sqlite3
 import sys
 
 
-def summarize(db, out, title, command, top=14):
+def summarize(db, out, title, command, top=14, patterns=("gemm_tn_kernel", "gemm_nn_kernel")):
     con = sqlite3.connect(db)
     cur = con.cursor()
     rows = list(cur.execute("select name, total_calls, total_duration, average, percentage "
@@ -23,14 +26,14 @@ def summarize(db, out, title, command, top=14):
             f.write("| `%s` | %d | %.1f | %.1f | %.2f |\n"
                     % (name[:120].replace("|", "/"), calls, tot, avg, pct))
         # dispatches of the product kernels, split by duration (products vs Grams)
-        for pat in ("gemm_tn_kernel", "gemm_nn_kernel"):
+        for pat in patterns:
             d = [r[0] / 1000.0 for r in cur.execute(
                 "select (end - start) from kernels where name like ? order by start", ("%" + pat + "%",))]
             big = [x for x in d if x > 1000.0]
             small = [x for x in d if x <= 1000.0]
             if d:
-                f.write("\n`%s`: %d launches; %d above 1 ms averaging %.1f us (the large products), "
-                        "%d at or below averaging %.1f us (Grams and small launches).\n"
+                f.write("\n`%s`: %d launches; %d above 1 ms averaging %.1f us, "
+                        "%d at or below averaging %.1f us.\n"
                         % (pat, len(d), len(big), sum(big) / max(len(big), 1), len(small),
                            sum(small) / max(len(small), 1)))
 
@@ -78,4 +81,6 @@ if __name__ == "__main__":
         print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6],
                       int(sys.argv[7]), sys.argv[8]))
     else:
-        summarize(*sys.argv[1:5])
+        pats = tuple(sys.argv[5].split(",")) if len(sys.argv) > 5 else ("gemm_tn_kernel",
+                                                                         "gemm_nn_kernel")
+        summarize(*sys.argv[1:5], patterns=pats)
