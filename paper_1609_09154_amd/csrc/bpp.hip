@@ -22,18 +22,24 @@
 // and the KKT conditions give an equivalent system on the active set A:
 //     y = G x - p,  x_A = 0,  y_F = 0   =>   x = G^-1 (p + y),
 //     (G^-1)_AA y_A = -(G^-1 p)_A,       x_F = (G^-1 p)_F + (G^-1)_FA y_A.
-// With k <= 64 one of |F|, |A| is at most 32, so every factorisation here is
-// at most 32 x 32: lane c holds compact row c in double registers, pivots are
-// broadcast with readlane, each factor column goes through LDS once, and L is
-// transposed through LDS for the backward solve. Each right-hand side starts
-// from the support of the incoming X (warm start); the solution is unique, so
-// the start only changes how many exchanges are needed.
+// With k <= 64 one of |F|, |A| is at most 32, so each solve eliminates at
+// most 32 pivots. The solved set S (F, or A) is moved to lanes 0..|S|-1 and
+// the other indices to the lanes after it (one cross-lane permute); every
+// lane c holds row c of [M_{.,S} | rhs] in double registers, and Gauss-Jordan
+// elimination over the pivots of S (pivot rows broadcast with readlane)
+// leaves the solution on S in lanes c < |S| and, in the other lanes, the
+// right-hand side with S eliminated: p - G_{.F} x_F = -y for the passive
+// system; for the active one, with right-hand side G^-1 p, the solution on
+// A is -y_A and the other lanes hold x_F. So one elimination gives both halves of
+// the KKT pair, with no LDS traffic and no waits inside the solve. Each
+// right-hand side starts from the support of the incoming X (warm start);
+// the solution is unique, so the start only changes how many exchanges are
+// needed.
 // ===========================================================================
 namespace nmfk {
 
 constexpr int BPP_WAVES = 4;   // right-hand sides in flight per workgroup
-constexpr int CNF = 32;        // largest compact system
-constexpr int CLD = CNF + 1;
+constexpr int CNF = 32;        // largest eliminated set
 
 __device__ __forceinline__ double rdl(double v, int q) {
   const unsigned long long b = __double_as_longlong(v);
@@ -42,66 +48,36 @@ __device__ __forceinline__ double rdl(double v, int q) {
   return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
-// Orders this wave's LDS writes before its later reads (lanes read what
-// other lanes of the same wave wrote).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// v from lane `src` (any lane, per-lane source).
+__device__ __forceinline__ double pull(double v, int src) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(b & 0xffffffffu));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(b >> 32));
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// Solves M s = b for the ns x ns SPD matrix whose row `lane` is in a[]
-// (lanes >= ns and columns >= ns are ignored). Returns s in lane c < ns and
-// sets *bad on a non-positive pivot. bw: 64 doubles of LDS, Lw: CNF x CLD.
-__device__ __forceinline__ double chol_solve(double (&a)[CNF], double b, int ns, int lane,
-                                             double* bw, double* Lw, bool* bad) {
-  double dd = 1.0;
+// Gauss-Jordan elimination of the first ns <= NS columns (lane c holds row c
+// of the matrix in a[] and its right-hand side b): returns the solution in
+// lanes c < ns and the eliminated right-hand side in the other lanes; a
+// non-positive pivot sets bad. Columns ns..NS-1 hold zeros, so the column
+// loops need no bounds tests.
+template <int NS>
+__device__ __forceinline__ double gj_eliminate(double (&a)[CNF], double b, int ns, int lane,
+                                               bool& bad) {
+  double dq = 1.0;
 #pragma unroll
-  for (int q = 0; q < CNF; ++q) {
+  for (int q = 0; q < NS; ++q) {
     if (q < ns) {
-      double d = rdl(a[q], q);
-      if (!(d > 0.0)) { *bad = true; d = 1.0; }
-      const double inv = 1.0 / sqrt(d);
-      const double l = a[q] * inv;
-      a[q] = lane >= q ? l : 0.0;
-      if (lane == q) dd = inv;
-      const double lq = (lane > q && lane < ns) ? l : 0.0;
-      bw[lane] = lq;
-      wave_sync();
+      double pv = rdl(a[q], q);
+      if (!(pv > 0.0)) { bad = true; pv = 1.0; }
+      const double f = (lane == q) ? 0.0 : a[q] / pv;
+      if (lane == q) dq = pv;
+      b = fma(-f, rdl(b, q), b);
 #pragma unroll
-      for (int j = q + 1; j < CNF; ++j)
-        if (j < ns) a[j] = fma(-lq, bw[j], a[j]);
-      wave_sync();
+      for (int j = q + 1; j < NS; ++j) a[j] = fma(-f, rdl(a[j], q), a[j]);
     }
   }
-  if (lane < CNF) {
-#pragma unroll
-    for (int j = 0; j < CNF; ++j) Lw[lane * CLD + j] = a[j];
-  }
-  wave_sync();
-  // forward: L z = b
-  double rz = b, z = 0.0;
-#pragma unroll
-  for (int q = 0; q < CNF; ++q) {
-    if (q < ns) {
-      const double zq = rdl(rz, q) * rdl(dd, q);
-      if (lane == q) z = zq;
-      rz = fma(-a[q], zq, rz);
-    }
-  }
-  // backward: L^T s = z (lane c reads column c of L from LDS)
-  double rs = z, s = 0.0;
-#pragma unroll
-  for (int q = CNF - 1; q >= 0; --q) {
-    if (q < ns) {
-      const double sq = rdl(rs, q) * rdl(dd, q);
-      if (lane == q) s = sq;
-      const double lqc = lane < CNF ? Lw[q * CLD + lane] : 0.0;
-      rs = fma(-lqc, sq, rs);
-    }
-  }
-  wave_sync();
-  return s;
+  return lane < ns ? b / dq : b;
 }
 
 // Ginv (KP x KP, double) = inverse of G restricted to the indices i < k with
@@ -164,21 +140,14 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_compact_kernel(
   static_assert(KP <= 64, "one lane per index");
   constexpr int LD = KP + 1;
   __shared__ TS Gs[KP * LD];
-  __shared__ double Ls[BPP_WAVES][CNF * CLD];
-  __shared__ double Bs[BPP_WAVES][64];
-  __shared__ double Xs[BPP_WAVES][64];
-  __shared__ int Is[BPP_WAVES][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) Gs[(e / KP) * LD + (e % KP)] = G[e];
   __syncthreads();
-  double* bw = Bs[wv];
-  double* xw = Xs[wv];
-  double* Lw = Ls[wv];
-  int* iw = Is[wv];
   // live: index in range with a nonzero Gram diagonal (see gram_inverse_kernel)
   const bool act = lane < k && Gs[lane * LD + lane] > TS(0);
   const uint64_t all = __ballot(act);
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const bool have_ginv = k > CNF && *ginv_ok != 0;
   unsigned long long my_pivots = 0;
   int my_status = 0;
 
@@ -212,80 +181,62 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_compact_kernel(
       const bool fi = (F >> lane) & 1ull;
       if (nf == 0) { x = 0.0; y = -p; continue; }
       const bool passive = nf <= CNF;
-      if (!passive && !*ginv_ok) { bad = true; break; }  // G^-1 unavailable (G singular)
+      if (!passive && !have_ginv) { bad = true; break; }  // G^-1 unavailable (G singular)
       if (!passive && !have_cp) {
         // cp = G^-1 p, once per right-hand side
-        xw[lane] = p;
-        wave_sync();
         double s = 0.0;
-        if (act)
-          for (int j = 0; j < k; ++j) s = fma(Ginv[j * KP + lane], xw[j], s);
-        cp = s;
+        const int grow = act ? lane : 0;
+        for (int j = 0; j < k; ++j) s = fma(Ginv[grow * KP + j], rdl(p, j), s);
+        cp = act ? s : 0.0;
         have_cp = true;
-        wave_sync();
       }
-      const uint64_t Sset = passive ? F : (all & ~F);
-      const int ns = __popcll(Sset);
-      const bool si = (Sset >> lane) & 1ull;
-      const int rank = __popcll(Sset & below);
-      if (si) iw[rank] = lane;
-      xw[lane] = passive ? p : cp;
-      wave_sync();
-      const int ci = lane < ns ? iw[lane] : 0;
+      const uint64_t S = passive ? F : (all & ~F);
+      const int ns = __popcll(S);
+      const bool si = (S >> lane) & 1ull;
+      // compact position: S in increasing index order, then the other lanes
+      const int pos = si ? __popcll(S & below) : ns + __popcll(~S & below);
+      const int ci0 = __builtin_amdgcn_ds_permute(pos << 2, lane);  // index held by lane
+      const int ci = ci0 < k ? ci0 : 0;
+      const double bv = pull(passive ? p : cp, ci0);
+      const double b = bv;
       double a[CNF];
+      uint64_t bits = S;
 #pragma unroll
       for (int d = 0; d < CNF; ++d) {
-        double v = (lane == d) ? 1.0 : 0.0;
+        double v = 0.0;
         if (d < ns) {
-          const int j = iw[d];
-          if (lane < ns) v = passive ? (double)Gs[ci * LD + j] : Ginv[ci * KP + j];
+          const int j = __builtin_ctzll(bits);
+          bits &= bits - 1;
+          v = passive ? (double)Gs[ci * LD + j] : Ginv[ci * KP + j];
         }
         a[d] = v;
       }
-      const double b = lane < ns ? (passive ? xw[ci] : -xw[ci]) : 0.0;
-      wave_sync();
-      const double sol = chol_solve(a, b, ns, lane, bw, Lw, &bad);
+      double sol;
+      switch ((ns + 7) >> 3) {
+        case 1: sol = gj_eliminate<8>(a, b, ns, lane, bad); break;
+        case 2: sol = gj_eliminate<16>(a, b, ns, lane, bad); break;
+        case 3: sol = gj_eliminate<24>(a, b, ns, lane, bad); break;
+        default: sol = gj_eliminate<32>(a, b, ns, lane, bad); break;
+      }
       if (bad && npiv == 1 && from_warm) {
         // The warm-start set was not positive definite: start over from F = {}.
         bad = false;
         F = 0;
         x = 0.0;
         y = -p;
-        wave_sync();
         continue;
       }
       if (bad) break;
-      // scatter the compact solution back to original indices
-      bw[lane] = sol;
-      wave_sync();
-      const double mine = si ? bw[rank] : 0.0;
-      wave_sync();
+      const double val = pull(sol, pos);
       if (passive) {
-        x = fi ? mine : 0.0;
-        xw[lane] = x;
-        wave_sync();
-        double gx = 0.0;
-        const int grow = lane < k ? lane : 0;
-        for (int d = 0; d < ns; ++d) {
-          const int j = iw[d];
-          gx = fma((double)Gs[grow * LD + j], xw[j], gx);
-        }
-        y = fi ? 0.0 : gx - p;
+        x = fi ? val : 0.0;
+        y = (fi || !act) ? 0.0 : -val;
       } else {
-        // mine = y on A; x_F = cp_F + Ginv_FA y_A
-        y = si ? mine : 0.0;
-        xw[lane] = y;
-        wave_sync();
-        double gy = 0.0;
-        const int grow = lane < k ? lane : 0;
-        for (int d = 0; d < ns; ++d) {
-          const int j = iw[d];
-          gy = fma(Ginv[grow * KP + j], xw[j], gy);
-        }
-        x = fi ? cp + gy : 0.0;
-        y = fi ? 0.0 : y;
+        // (G^-1)_AA z = (G^-1 p)_A gives z = -y_A; the other lanes hold
+        // (G^-1 p)_F - (G^-1)_FA z = x_F
+        y = si ? -val : 0.0;
+        x = fi ? val : 0.0;
       }
-      wave_sync();
     }
     if (bad) my_status |= 1;
     my_pivots += (unsigned long long)npiv;

@@ -174,6 +174,40 @@ def spd_gram(k: int, rows: int, seed: int, dtype=np.float64):
     return (X.T @ X).astype(dtype), X
 
 
+def planted_nnls(rows: int, k: int, seed: int, gram_cols: int = 0):
+    """Nonnegative least-squares instances with a known answer.
+
+    G = B B^T for a k x gram_cols U(0,1) matrix B (default 4k columns),
+    rounded to float32 values so both storage types hold it exactly. Row r
+    gets a support F_r whose size is drawn uniformly from 0..k (so every
+    size, the empty and the full set included, occurs), values xs on F_r and
+    slacks ys off F_r both U(0.5, 1.5) x the size of G's entries, and
+    right-hand side p_r = G xs_r - ys_r (float64). Then xs_r >= 0, ys_r >= 0,
+    xs_r * ys_r = 0 and G xs_r - p_r = ys_r: the optimality conditions of
+    min_{x >= 0} 1/2 x^T G x - p_r^T x hold at xs_r, which is therefore the
+    unique solution (G is positive definite almost surely).
+
+    Returns (G, P, XS), P and XS of shape rows x k."""
+    rng = _rng(seed)
+    c = gram_cols or 4 * k
+    B = rng.random((k, c))
+    G = (B @ B.T).astype(np.float32).astype(np.float64)
+    scale = float(np.abs(G).max())
+    sizes = rng.integers(0, k + 1, size=rows)
+    if rows >= 2:
+        sizes[0], sizes[1] = 0, k
+    XS = np.zeros((rows, k))
+    YS = np.zeros((rows, k))
+    for r in range(rows):
+        sup = rng.permutation(k)[: sizes[r]]
+        on = np.zeros(k, dtype=bool)
+        on[sup] = True
+        XS[r, on] = rng.uniform(0.5, 1.5, size=int(on.sum()))
+        YS[r, ~on] = rng.uniform(0.5, 1.5, size=int((~on).sum())) * scale
+    P = XS @ G - YS
+    return G, P, XS
+
+
 # Workloads of the benchmark and parity suite, named by shape. Each entry:
 # (kind, m, n, k, algorithm, iterations, dtype, extra)
 WORKLOADS = {

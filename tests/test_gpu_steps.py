@@ -141,6 +141,37 @@ def test_update_abpp(dt, rows, k):
     assert piv >= rows  # at least one passive-set solve per row (x = 0 is infeasible here)
 
 
+@pytest.mark.parametrize("start", ["zeros", "ones", "random"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("k", [10, 33, 50, 64])
+def test_update_abpp_planted(dt, k, start):
+    """Instances whose unique solution is known by construction (optimality
+    conditions planted at a point with every support size 0..k), from three
+    starting supports: the empty set, the full set and a random one. Covers
+    both solved systems (the passive set when |F| <= 32, the active set
+    otherwise)."""
+    from synth import planted_nnls
+
+    npdt, u = DT[dt]
+    rows = 600
+    G, P, XS = planted_nnls(rows, k, seed=40 + k)
+    if start == "zeros":
+        X0 = np.zeros((rows, k))
+    elif start == "ones":
+        X0 = np.ones((rows, k))
+    else:
+        X0 = (uniform((rows, k), seed=k) > 0.5).astype(np.float64)
+    Xd = to_dev(X0.astype(npdt), npdt)
+    step("update abpp planted %s k=%d start=%s" % (dt, k, start))
+    nmf.nmf_update("abpp", to_dev(G.astype(npdt), npdt), to_dev(P.astype(npdt), npdt), Xd)
+    got = host(Xd).astype(np.float64)
+    cond = np.linalg.cond(G)
+    tol = 1e-9 if dt == "f64" else min(1e-2, 50 * cond * u)
+    err = np.max(np.abs(got - XS)) / np.abs(XS).max()
+    assert err <= tol, (err, tol, cond)
+    assert ((got > 0) == (XS > 0)).all()
+
+
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (300, 200, 10), (1000, 1500, 50), (129, 4100, 64)])
 def test_dense_relerr(dt, m, n, k):

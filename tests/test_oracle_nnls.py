@@ -118,3 +118,15 @@ def test_pivot_cap_raises():
     G, R = _random_problem(8, 10, seed=1)
     with pytest.raises(RuntimeError):
         oracle.bpp_nnls(G, np.abs(R) + 0.1, max_pivots=0)
+
+
+@pytest.mark.parametrize("k", [1, 7, 33, 50])
+def test_planted_kkt_solutions_recovered(k):
+    """Instances built to satisfy the optimality conditions at a chosen point
+    (every support size from empty to full): the oracle must return that
+    point, which no property of the oracle itself decides."""
+    from synth import planted_nnls
+
+    G, P, XS = planted_nnls(120, k, seed=300 + k)
+    X = oracle.abpp_update_W(G, P)
+    assert np.max(np.abs(X - XS)) <= 1e-9 * np.abs(XS).max()
