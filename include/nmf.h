@@ -33,6 +33,14 @@
  * - Element types: NMF_F64 runs everything in double; NMF_F32 stores A, W, H
  *   in float and accumulates the large products in float on the matrix
  *   cores, with the Gram split-sums and the objective accumulated in double.
+ *   NMF_BF16 (dense A only) stores A as bfloat16 (each element the 16 bits
+ *   of the value, row pitch lda a multiple of 8 elements, rows 16-byte
+ *   aligned) with W, H and every other array in float: the two large
+ *   products run on the BF16 matrix cores with float accumulation, the
+ *   factor operand rounded to bfloat16 (nearest even) for each product;
+ *   Grams, updates and the objective are as for NMF_F32. This is the
+ *   reduced-precision variant of the products the paper's Section 6.3.1
+ *   breakdown calls MM.
  * - 1 <= k <= NMF_MAX_K and k <= min(m, n) is not required, but k must not
  *   exceed NMF_MAX_K. m, n >= 1.
  * - Calls on one context must not overlap (one stream, shared workspace).
@@ -60,7 +68,7 @@ typedef enum {
 
 typedef enum { NMF_MU = 0, NMF_HALS = 1, NMF_ABPP = 2 } nmf_algo;
 
-typedef enum { NMF_F64 = 0, NMF_F32 = 1 } nmf_dtype;
+typedef enum { NMF_F64 = 0, NMF_F32 = 1, NMF_BF16 = 2 } nmf_dtype;
 
 typedef enum {
   NMF_OBJ_NONE = 0,    /* do not evaluate the objective                    */
@@ -82,7 +90,9 @@ typedef struct {
                      /* CSR arrays for out-of-range or unsorted columns      */
   int transpose_a;   /* dense A: 0 (default) keeps a transposed copy of A in */
                      /* device memory for the call when it fits (both large  */
-                     /* products then stream A row by row); -1 never does    */
+                     /* products then stream A row by row); -1 never does.   */
+                     /* NMF_BF16 A always needs the copy: -1 is rejected and */
+                     /* a copy that does not fit returns NMF_ENOMEM          */
 } nmf_opts;
 
 typedef struct {
@@ -118,8 +128,9 @@ const char* nmf_status_str(nmf_status s);
 const char* nmf_last_error(const nmf_ctx* ctx);
 
 /* Full AU-NMF on a dense A (Algorithm 1).
- *   A       m x n, leading dimension lda >= n, element type a_dtype.
- *   W       m x k (leading dimension k), same element type: the initial W on
+ *   A       m x n, leading dimension lda >= n, element type dtype.
+ *   W       m x k (leading dimension k), element type dtype (float for
+ *           NMF_BF16): the initial W on
  *           entry (read by MU and HALS; ABPP's W step is an exact solve that
  *           only takes its starting passive sets from it), the final W.
  *   H       k x n (leading dimension n): initial H on entry, final H on return.
@@ -153,13 +164,16 @@ nmf_status nmf_gram(nmf_ctx* ctx, nmf_dtype dtype, int64_t rows, int k,
                     const void* X, int64_t ldx, void* G);
 
 /* P = A F for dense A (m x n, lda) and F (n x k, ldf): with F = H^T this is
- * the A H^T of the W update. Output P is m x k (leading dimension k). */
+ * the A H^T of the W update. Output P is m x k (leading dimension k).
+ * NMF_BF16: A bfloat16 (lda a multiple of 8), F and P float; F is rounded
+ * to bfloat16 for the product, as in nmf_dense. */
 nmf_status nmf_dense_AF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
                         const void* A, int64_t lda, int k, const void* F,
                         int64_t ldf, void* P);
 
 /* R = A^T F for dense A (m x n, lda) and F (m x k, ldf): with F = W this is
- * (W^T A)^T of the H update. Output R is n x k (leading dimension k). */
+ * (W^T A)^T of the H update. Output R is n x k (leading dimension k).
+ * NMF_BF16 as for nmf_dense_AF (the call makes a transposed copy of A). */
 nmf_status nmf_dense_AtF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
                          const void* A, int64_t lda, int k, const void* F,
                          int64_t ldf, void* R);
@@ -206,7 +220,8 @@ nmf_status nmf_hals_normalize(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
 
 /* Relative error ||A - W H||_F / ||A||_F of Section 6.2 for dense A, with W
  * (m x k) and Ht = H^T (n x k). Residual formed explicitly, squares summed
- * in double. Result written to the host double *out (synchronises). */
+ * in double. Result written to the host double *out (synchronises).
+ * NMF_BF16: A bfloat16, W and Ht float. */
 nmf_status nmf_dense_relerr(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
                             int64_t n, const void* A, int64_t lda, int k,
                             const void* W, const void* Ht, double* out);

@@ -26,6 +26,6 @@ from .nmf import (  # noqa: F401
     gram_fixed_H, gram_fixed_W, product_AHt, product_WtA,
     mu_update_W, mu_update_H, hals_update_W, hals_update_H,
     abpp_update_W, abpp_update_H, relative_error, objective_sq, run,
-    MU_EPS,
+    round_bf16, MU_EPS,
 )
 from .bpp import bpp_nnls, passive_solve  # noqa: F401

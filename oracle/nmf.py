@@ -26,6 +26,25 @@ def _is_sparse(A) -> bool:
     return hasattr(A, "tocsr") and not isinstance(A, np.ndarray)
 
 
+# --- bfloat16 rounding of a product operand --------------------------------
+
+def round_bf16(X):
+    """Values of X rounded to bfloat16 (8 significant bits, float32's
+    exponent range), round to nearest with ties to even, returned as float64.
+
+    Written from the format's definition: a float32 whose low 16 bits are
+    dropped keeps its sign, exponent and 7 stored fraction bits, so rounding
+    adds half a unit of the kept last place (0x8000 in the low half), minus
+    one when the kept last bit is 0 so that exact ties go to the even
+    neighbour, and then clears the low half. Values are first rounded to
+    float32, the type the GPU factors are stored in. NaN is not expected."""
+    x32 = np.ascontiguousarray(np.asarray(X, dtype=np.float64).astype(np.float32))
+    u = x32.view(np.uint32).astype(np.uint64)
+    keep_lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + keep_lsb) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 # --- the four products of Algorithm 1 ------------------------------------
 
 def gram_fixed_H(H):
@@ -210,7 +229,7 @@ def relative_error(A, W, H, normA_sq: float | None = None) -> float:
 # --- Algorithm 1 ---------------------------------------------------------
 
 def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
-        max_pivots=None, track_error: bool = True):
+        max_pivots=None, track_error: bool = True, bf16_products: bool = False):
     """AU-NMF (Algorithm 1) for ``iters`` iterations from (W0, H0).
 
     One iteration: Q = H H^T, P = A H^T, update W; S = W^T W, R = W^T A,
@@ -218,7 +237,14 @@ def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
     (W, H, rel_err) with rel_err[t] the relative error after t iterations
     (rel_err[0] at the initial factors), or an empty list when
     ``track_error`` is False.
+
+    bf16_products: the reduced-precision variant of the two large products
+    (A stored in bfloat16 is passed in as its float64 values): the factor
+    operand of A H^T and W^T A is rounded to bfloat16 first (round_bf16);
+    the products are then exact in float64, and the Grams, updates and the
+    error use the unrounded factors as before.
     """
+    fr = round_bf16 if bf16_products else (lambda X: X)
     algo = algo.lower()
     if algo not in ("mu", "hals", "abpp"):
         raise ValueError("unknown algorithm %r" % algo)
@@ -231,7 +257,7 @@ def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
         errs.append(relative_error(A, W, H, normA_sq))
     for _ in range(iters):
         Q = gram_fixed_H(H)
-        P = product_AHt(A, H)
+        P = product_AHt(A, fr(H))
         if algo == "mu":
             W = mu_update_W(W, Q, P, eps)
         elif algo == "hals":
@@ -239,7 +265,7 @@ def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
         else:
             W = abpp_update_W(Q, P, max_pivots)
         S = gram_fixed_W(W)
-        R = product_WtA(A, W)
+        R = product_WtA(A, fr(W))
         if algo == "mu":
             H = mu_update_H(H, S, R, eps)
         elif algo == "hals":

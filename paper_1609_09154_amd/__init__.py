@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (NMF_ABPP, NMF_F32, NMF_F64, NMF_HALS, NMF_MU, NMF_OBJ_DIRECT,  # noqa: F401
+from ._lib import (NMF_ABPP, NMF_BF16, NMF_F32, NMF_F64, NMF_HALS, NMF_MU, NMF_OBJ_DIRECT,  # noqa: F401
                    NMF_OBJ_NONE, NMFError, NmfStats, default_opts)
 
 __all__ = ["Context", "NMFError", "nmf_dense", "nmf_csr", "nmf_gram", "nmf_dense_AF",
@@ -35,7 +35,17 @@ def _dtype_code(t) -> int:
         return NMF_F32
     if t.dtype == torch.float64:
         return NMF_F64
-    raise TypeError("only float32 and float64 tensors are supported, got %s" % t.dtype)
+    if t.dtype == torch.bfloat16:
+        return NMF_BF16
+    raise TypeError("only float32, float64 and bfloat16 (A) tensors are supported, got %s"
+                    % t.dtype)
+
+
+def _factor_dtype(A):
+    """Element type of W, H and the products for a dense A: float32 when A
+    is bfloat16, A's own type otherwise."""
+    torch = _torch()
+    return torch.float32 if A.dtype == torch.bfloat16 else A.dtype
 
 
 def _dev(t, name, dtype=None, shape=None):
@@ -107,12 +117,13 @@ def nmf_dense(A, W, H, algo="hals", iters=10, objective=True, eps_mu=1e-16, max_
               timers=False, check_input=False, transpose_a=True, ctx=None):
     """Algorithm 1 on dense A (m x n); W (m x k) and H (k x n) are updated in
     place. transpose_a=False keeps the library from holding a transposed
-    copy of A. Returns (rel_err list or None, stats dict)."""
+    copy of A. A may be bfloat16 (then W and H are float32, the products run
+    on the BF16 matrix cores). Returns (rel_err list or None, stats dict)."""
     torch = _torch()
     m, n = A.shape
     k = W.shape[1]
-    dt = A.dtype
-    pa = _dev(A, "A", dtype=dt)
+    dt = _factor_dtype(A)
+    pa = _dev(A, "A")
     pw = _dev(W, "W", dtype=dt, shape=(m, k))
     ph = _dev(H, "H", dtype=dt, shape=(k, n))
     c = _ctx(ctx, A.device.index or 0)
@@ -164,12 +175,13 @@ def nmf_gram(X, ctx=None):
 
 
 def nmf_dense_AF(A, F, ctx=None):
-    """P = A F for dense A (m x n) and F (n x k)."""
+    """P = A F for dense A (m x n) and F (n x k); A may be bfloat16 (F and P
+    float32)."""
     torch = _torch()
     m, n = A.shape
     k = F.shape[1]
-    _dev(F, "F", dtype=A.dtype, shape=(n, k))
-    P = torch.empty((m, k), dtype=A.dtype, device=A.device)
+    _dev(F, "F", dtype=_factor_dtype(A), shape=(n, k))
+    P = torch.empty((m, k), dtype=_factor_dtype(A), device=A.device)
     c = _ctx(ctx, A.device.index or 0)
     c.check(_lib.lib().nmf_dense_AF(c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0), k,
                                   _dev(F, "F"), F.stride(0), _dev(P, "P")))
@@ -177,12 +189,13 @@ def nmf_dense_AF(A, F, ctx=None):
 
 
 def nmf_dense_AtF(A, F, ctx=None):
-    """R = A^T F for dense A (m x n) and F (m x k)."""
+    """R = A^T F for dense A (m x n) and F (m x k); A may be bfloat16 (F and R
+    float32)."""
     torch = _torch()
     m, n = A.shape
     k = F.shape[1]
-    _dev(F, "F", dtype=A.dtype, shape=(m, k))
-    R = torch.empty((n, k), dtype=A.dtype, device=A.device)
+    _dev(F, "F", dtype=_factor_dtype(A), shape=(m, k))
+    R = torch.empty((n, k), dtype=_factor_dtype(A), device=A.device)
     c = _ctx(ctx, A.device.index or 0)
     c.check(_lib.lib().nmf_dense_AtF(c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0), k,
                                    _dev(F, "F"), F.stride(0), _dev(R, "R")))
@@ -259,8 +272,8 @@ def nmf_dense_relerr(A, W, Ht, ctx=None):
     """||A - W Ht^T||_F / ||A||_F for dense A."""
     m, n = A.shape
     k = W.shape[1]
-    _dev(W, "W", dtype=A.dtype, shape=(m, k))
-    _dev(Ht, "Ht", dtype=A.dtype, shape=(n, k))
+    _dev(W, "W", dtype=_factor_dtype(A), shape=(m, k))
+    _dev(Ht, "Ht", dtype=_factor_dtype(A), shape=(n, k))
     out = ctypes.c_double(0.0)
     c = _ctx(ctx, A.device.index or 0)
     c.check(_lib.lib().nmf_dense_relerr(c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0),

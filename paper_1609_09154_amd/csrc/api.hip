@@ -273,6 +273,12 @@ template <typename T> struct Prob {
   bool sparse = false;
   const T* A = nullptr; int64_t lda = 0;                 // dense
   const T* At = nullptr;                                 // dense A^T (n x m, ld m) or null
+  // bfloat16 A (bits, T = float): A m x n (lda), its transposed copy n x m
+  // (row pitch ldat) and scratch for the packed bfloat16 factor.
+  const uint16_t* Ab = nullptr;
+  const uint16_t* Abt = nullptr;
+  int64_t ldat = 0;
+  uint16_t* fb = nullptr;
   const int64_t* rp = nullptr; const int32_t* ci = nullptr; const float* cv = nullptr;  // CSR A
   const int64_t* rpt = nullptr; const int32_t* cit = nullptr; const float* cvt = nullptr; // CSR A^T
   int64_t nnz = 0;
@@ -289,6 +295,17 @@ nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, con
       return NMF_OK;
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
+  }
+  if (pb.Ab) {
+    if constexpr (sizeof(T) == 4) {
+      // P = A (H^T): H packed as bfloat16 rows (KP x n), K = n contiguous
+      const int64_t ldf = round_up(n, 8);
+      HIP_TRY(nmfk::pack_bf16_t(F, n, KP, pb.fb, ldf, ctx->stream));
+      HIP_TRY(nmfk::gemm_bf16_nt(pb.Ab, pb.lda, pb.fb, ldf, Pout, KP, m, KP, n, part,
+                                 ctx->stream));
+      return NMF_OK;
+    }
+    return fail(ctx, NMF_EINVAL, "bfloat16 A takes float factors");
   }
   if (pb.At) {
     // A H^T = (A^T)^T H^T: the TN kernel streaming A^T row by row.
@@ -312,6 +329,18 @@ nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, co
       return NMF_OK;
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
+  }
+  if (pb.Ab) {
+    if constexpr (sizeof(T) == 4) {
+      // R = A^T W on the transposed copy: W packed as bfloat16 rows (KP x m)
+      if (!pb.Abt) return fail(ctx, NMF_EINVAL, "bfloat16 A^T W needs the transposed copy");
+      const int64_t ldf = round_up(m, 8);
+      HIP_TRY(nmfk::pack_bf16_t(F, m, KP, pb.fb, ldf, ctx->stream));
+      HIP_TRY(nmfk::gemm_bf16_nt(pb.Abt, pb.ldat, pb.fb, ldf, Rout, KP, n, KP, m, part,
+                                 ctx->stream));
+      return NMF_OK;
+    }
+    return fail(ctx, NMF_EINVAL, "bfloat16 A takes float factors");
   }
   nmfk::GemmArgs<T> a{pb.A, pb.lda, Ft ? Ft : F, Ft ? m : (int64_t)KP, Rout, KP, n, KP, m,
                       Ft != nullptr, k};
@@ -339,7 +368,13 @@ nmf_status objective(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int 
     }
     return NMF_EINVAL;
   }
-  HIP_TRY(nmfk::residual_sq<T>(pb.A, pb.lda, m, n, w.W, w.Ht, KP, w.obj_part, st));
+  if (pb.Ab) {
+    if constexpr (sizeof(T) == 4)
+      HIP_TRY((nmfk::residual_sq<float, uint16_t>(pb.Ab, pb.lda, m, n, w.W, w.Ht, KP, w.obj_part,
+                                                  st)));
+  } else {
+    HIP_TRY((nmfk::residual_sq<T, T>(pb.A, pb.lda, m, n, w.W, w.Ht, KP, w.obj_part, st)));
+  }
   HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, nmfk::residual_partials<T>(m, n), (const T*)nullptr,
                                  (const T*)nullptr, KP, w.normA, w.relerr + slot, st));
   (void)k;
@@ -359,7 +394,8 @@ nmf_status norm_sq_A(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, Work
     }
     return NMF_EINVAL;
   }
-  HIP_TRY(nmfk::sumsq<T>(pb.A, pb.lda, m, n, w.obj_part, st));
+  if (pb.Ab) HIP_TRY(nmfk::sumsq<uint16_t>(pb.Ab, pb.lda, m, n, w.obj_part, st));
+  else HIP_TRY(nmfk::sumsq<T>(pb.A, pb.lda, m, n, w.obj_part, st));
   HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, nmfk::sumsq_partials<T>(m, n), (const T*)nullptr,
                                  (const T*)nullptr, 0, (const double*)nullptr, w.normA, st));
   return NMF_OK;
@@ -379,8 +415,8 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   }
   // Transposed factor copies for the dense products (read with 16-byte loads,
   // so their rows must stay 16-byte aligned).
-  const bool tH = !pb.sparse && (n * (int64_t)sizeof(T)) % 16 == 0;
-  const bool tW = !pb.sparse && (m * (int64_t)sizeof(T)) % 16 == 0;
+  const bool tH = !pb.sparse && !pb.Ab && (n * (int64_t)sizeof(T)) % 16 == 0;
+  const bool tW = !pb.sparse && !pb.Ab && (m * (int64_t)sizeof(T)) % 16 == 0;
   if (tH && o->iters > 0) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
@@ -444,9 +480,9 @@ nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_ob
 // with a quarter of the device memory to spare; *out stays null otherwise.
 template <typename T>
 nmf_status transposed_copy(nmf_ctx* ctx, const T* A, int64_t lda, int64_t m, int64_t n,
-                           const T** out) {
+                           int64_t ldt, const T** out) {
   *out = nullptr;
-  const size_t need = (size_t)m * (size_t)n * sizeof(T);
+  const size_t need = (size_t)ldt * (size_t)n * sizeof(T);
   if (ctx->at_bytes < need) {
     size_t freeb = 0, total = 0;
     HIP_TRY(hipMemGetInfo(&freeb, &total));
@@ -466,27 +502,44 @@ nmf_status transposed_copy(nmf_ctx* ctx, const T* A, int64_t lda, int64_t m, int
     ctx->at_bytes = need;
   }
   T* At = (T*)ctx->at;
-  HIP_TRY(nmfk::transpose_full<T>(A, lda, m, n, At, ctx->stream));
+  HIP_TRY(nmfk::transpose_full<T>(A, lda, m, n, At, ldt, ctx->stream));
   *out = At;
   return NMF_OK;
 }
 
+// Scratch for bfloat16 products: the packed factor and the split partials.
+struct Bf16Plan { int64_t fb_elems, part_elems; };
+Bf16Plan bf16_plan(int64_t m, int64_t n, int KP) {
+  Bf16Plan p;
+  p.fb_elems = (int64_t)KP * round_up(std::max(m, n), 8);
+  const int64_t sp = nmfk::gemm_bf16_splits(m, n), sr = nmfk::gemm_bf16_splits(n, m);
+  p.part_elems = std::max<int64_t>(sp > 1 ? sp * m * KP : 0, sr > 1 ? sr * n * KP : 0);
+  return p;
+}
+
+// Ab (nullable): A as bfloat16 bits (then A is null and T is float).
 template <typename T>
-nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t lda, int k,
-                      const nmf_opts* o, T* W, T* H, double* rel_err, nmf_stats* stats) {
+nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, const uint16_t* Ab,
+                      int64_t lda, int k, const nmf_opts* o, T* W, T* H, double* rel_err,
+                      nmf_stats* stats) {
   const int KP = kp_dense(k);
   const bool want_obj = o->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max(nmfk::residual_partials<T>(m, n), nmfk::sumsq_partials<T>(m, n));
+  const Bf16Plan bp = Ab ? bf16_plan(m, n, KP) : Bf16Plan{0, 0};
   Carve cv;
   size_t off[15];
-  plan_work<T>(m, n, KP, o->iters, obj_np, 0, cv, off);
+  plan_work<T>(m, n, KP, o->iters, obj_np, bp.part_elems, cv, off);
+  const size_t ofb = cv.take<uint16_t>(Ab ? bp.fb_elems : 0);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   Work<T> w = bind_work<T>(ctx, off, obj_np);
   hipStream_t st = ctx->stream;
   HIP_TRY(hipMemsetAsync(w.status, 0, 4 * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(w.pivots, 0, 2 * sizeof(unsigned long long), st));
-  if (o->check_input) HIP_TRY(nmfk::check_dense<T>(A, lda, m, n, w.status + 1, st));
+  if (o->check_input) {
+    if (Ab) HIP_TRY(nmfk::check_dense<uint16_t>(Ab, lda, m, n, w.status + 1, st));
+    else HIP_TRY(nmfk::check_dense<T>(A, lda, m, n, w.status + 1, st));
+  }
   Timers tm;
   tm.on = stats && o->timers;
   tm.st = st;
@@ -502,8 +555,17 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t ld
   Prob<T> pb;
   pb.A = A;
   pb.lda = lda;
-  if (o->iters > 0 && o->transpose_a == 0) {
-    if ((s = transposed_copy<T>(ctx, A, lda, m, n, &pb.At)) != NMF_OK) return s;
+  if (Ab) {
+    pb.Ab = Ab;
+    pb.fb = at<uint16_t>(ctx, ofb);
+    pb.ldat = round_up(m, 8);
+    if (o->iters > 0) {
+      if ((s = transposed_copy<uint16_t>(ctx, Ab, lda, m, n, pb.ldat, &pb.Abt)) != NMF_OK)
+        return s;
+      if (!pb.Abt) return fail(ctx, NMF_ENOMEM, "no room for the transposed bfloat16 copy of A");
+    }
+  } else if (o->iters > 0 && o->transpose_a == 0) {
+    if ((s = transposed_copy<T>(ctx, A, lda, m, n, m, &pb.At)) != NMF_OK) return s;
   }
   s = run_au_nmf<T>(ctx, pb, m, n, k, KP, o, w, want_obj, tm);
   if (stats) HIP_TRY(hipEventRecord(t1, st));
@@ -595,13 +657,23 @@ nmf_status nmf_dense(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const 
   if ((s = check_opts(ctx, opts, k, rel_err != nullptr)) != NMF_OK) return s;
   if (!A || !W || !H) return fail(ctx, NMF_EINVAL, "null A, W or H");
   if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
-  if (dtype != NMF_F32 && dtype != NMF_F64) return fail(ctx, NMF_EINVAL, "unknown dtype");
+  if (dtype != NMF_F32 && dtype != NMF_F64 && dtype != NMF_BF16)
+    return fail(ctx, NMF_EINVAL, "unknown dtype");
+  if (dtype == NMF_BF16) {
+    if (lda % 8 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A: lda must be a multiple of 8");
+    if (((uintptr_t)A) % 16 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A must be 16-byte aligned");
+    if (opts->transpose_a != 0)
+      return fail(ctx, NMF_EINVAL, "bfloat16 A needs its transposed copy (transpose_a 0)");
+  }
   if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_BF16)
+    return dense_impl<float>(ctx, m, n, nullptr, (const uint16_t*)A, lda, k, opts, (float*)W,
+                             (float*)H, rel_err, stats);
   if (dtype == NMF_F32)
-    return dense_impl<float>(ctx, m, n, (const float*)A, lda, k, opts, (float*)W, (float*)H,
-                             rel_err, stats);
-  return dense_impl<double>(ctx, m, n, (const double*)A, lda, k, opts, (double*)W, (double*)H,
-                            rel_err, stats);
+    return dense_impl<float>(ctx, m, n, (const float*)A, nullptr, lda, k, opts, (float*)W,
+                             (float*)H, rel_err, stats);
+  return dense_impl<double>(ctx, m, n, (const double*)A, nullptr, lda, k, opts, (double*)W,
+                            (double*)H, rel_err, stats);
 }
 
 nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_t* rowptr,
@@ -745,6 +817,38 @@ nmf_status dense_prod_impl(nmf_ctx* ctx, bool transA, int64_t m, int64_t n, cons
   return NMF_OK;
 }
 
+nmf_status dense_prod_bf16_impl(nmf_ctx* ctx, bool transA, int64_t m, int64_t n,
+                                const uint16_t* Ab, int64_t lda, int k, const float* F,
+                                int64_t ldf, float* Out) {
+  const int KP = kp_dense(k);
+  const int64_t frows = transA ? m : n, orows = transA ? n : m;
+  const Bf16Plan bp = bf16_plan(m, n, KP);
+  Carve cv;
+  const size_t oF = cv.take<float>(frows * KP);
+  const size_t oO = cv.take<float>(orows * KP);
+  const size_t oP = cv.take<float>(std::max<int64_t>(bp.part_elems, 1));
+  const size_t oB = cv.take<uint16_t>(bp.fb_elems);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  float* Fp = at<float>(ctx, oF);
+  float* Op = at<float>(ctx, oO);
+  if ((s = pad_any<float>(ctx, F, frows, k, ldf, Fp, KP)) != NMF_OK) return s;
+  Prob<float> pb;
+  pb.Ab = Ab;
+  pb.lda = lda;
+  pb.fb = at<uint16_t>(ctx, oB);
+  if (transA) {
+    pb.ldat = round_up(m, 8);
+    if ((s = transposed_copy<uint16_t>(ctx, Ab, lda, m, n, pb.ldat, &pb.Abt)) != NMF_OK) return s;
+    if (!pb.Abt) return fail(ctx, NMF_ENOMEM, "no room for the transposed bfloat16 copy of A");
+  }
+  s = transA ? product_AtF<float>(ctx, pb, m, n, Fp, nullptr, k, KP, Op, at<float>(ctx, oP))
+             : product_AF<float>(ctx, pb, m, n, Fp, nullptr, k, KP, Op, at<float>(ctx, oP));
+  if (s != NMF_OK) return s;
+  HIP_TRY(nmfk::unpad_rows<float>(Op, orows, k, KP, Out, ctx->stream));
+  return NMF_OK;
+}
+
 template <typename T>
 nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, const T* Pm,
                        T* X, const nmf_opts* o, long long* pivots) {
@@ -853,7 +957,14 @@ static nmf_status dense_prod(nmf_ctx* ctx, bool transA, nmf_dtype dtype, int64_t
   if (!A || !F || !Out) return fail(ctx, NMF_EINVAL, "null A, F or output");
   if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
   if (ldf < k) return fail(ctx, NMF_EINVAL, "ldf < k");
+  if (dtype == NMF_BF16) {
+    if (lda % 8 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A: lda must be a multiple of 8");
+    if (((uintptr_t)A) % 16 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A must be 16-byte aligned");
+  }
   if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_BF16)
+    return dense_prod_bf16_impl(ctx, transA, m, n, (const uint16_t*)A, lda, k, (const float*)F,
+                                ldf, (float*)Out);
   if (dtype == NMF_F32)
     return dense_prod_impl<float>(ctx, transA, m, n, (const float*)A, lda, k, (const float*)F,
                                   ldf, (float*)Out);
@@ -966,6 +1077,12 @@ nmf_status nmf_dense_relerr(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
     pb.A = (const double*)A;
     pb.lda = lda;
     return relerr_impl<double>(ctx, pb, m, n, k, (const double*)W, (const double*)Ht, out);
+  }
+  if (dtype == NMF_BF16) {
+    Prob<float> pb;
+    pb.Ab = (const uint16_t*)A;
+    pb.lda = lda;
+    return relerr_impl<float>(ctx, pb, m, n, k, (const float*)W, (const float*)Ht, out);
   }
   return fail(ctx, NMF_EINVAL, "unknown dtype");
 }

@@ -85,6 +85,15 @@ __device__ __forceinline__ V16<T> load16_stream(const T* p) {
   return r;
 }
 
+// bfloat16 values are carried as their 16 bits (uint16_t) outside the
+// matrix-core operands. to_double widens any stored element type.
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) {
+  return __uint_as_float((unsigned)b << 16);
+}
+__device__ __forceinline__ double to_double(float x) { return (double)x; }
+__device__ __forceinline__ double to_double(double x) { return x; }
+__device__ __forceinline__ double to_double(uint16_t x) { return (double)bf16_bits_to_float(x); }
+
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 

@@ -384,6 +384,52 @@ __global__ void reduce_splits_kernel(const T* __restrict__ part, int splits, int
   out[r * ldo + cc] = (T)s;
 }
 
+// Same sums for few outputs and many splits (the k x k Grams): RS_SUB
+// threads per output each add every RS_SUB-th slab, then one thread adds the
+// RS_SUB partial sums in order. The order is fixed, so results stay bitwise
+// reproducible.
+constexpr int RS_OUT = 16, RS_SUB = 16;
+template <typename T>
+__global__ __launch_bounds__(RS_OUT * RS_SUB) void reduce_splits_wide_kernel(
+    const T* __restrict__ part, int splits, int64_t stride, int64_t rows, int cols, int64_t ldo,
+    T* __restrict__ out, int64_t ldp) {
+  __shared__ double sh[RS_SUB][RS_OUT];
+  const int o = threadIdx.x % RS_OUT, sub = threadIdx.x / RS_OUT;
+  const int64_t idx = (int64_t)blockIdx.x * RS_OUT + o;
+  const int64_t total = rows * cols;
+  const int64_t r = idx / cols, cc = idx - r * cols;
+  double s = 0.0;
+  if (idx < total) {
+    const T* src = part + r * ldp + cc;
+    for (int p = sub; p < splits; p += RS_SUB) s += (double)src[(int64_t)p * stride];
+  }
+  sh[sub][o] = s;
+  __syncthreads();
+  if (sub == 0 && idx < total) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < RS_SUB; ++q) t += sh[q][o];
+    out[r * ldo + cc] = (T)t;
+  }
+}
+
+template <typename T>
+hipError_t reduce_splits(const T* part, int splits, int64_t dsplit, int64_t M, int N,
+                         int64_t ldd, T* D, int64_t ldp, hipStream_t st) {
+  const int64_t total = M * N;
+  if (total < 65536 && splits > 16)
+    reduce_splits_wide_kernel<T><<<(unsigned)cdiv(total, RS_OUT), RS_OUT * RS_SUB, 0, st>>>(
+        part, splits, dsplit, M, N, ldd, D, ldp);
+  else
+    reduce_splits_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(part, splits, dsplit, M,
+                                                                         N, ldd, D, ldp);
+  return NMF_LAUNCH_CHECK();
+}
+template hipError_t reduce_splits<float>(const float*, int, int64_t, int64_t, int, int64_t, float*,
+                                         int64_t, hipStream_t);
+template hipError_t reduce_splits<double>(const double*, int, int64_t, int64_t, int, int64_t,
+                                          double*, int64_t, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -528,10 +574,7 @@ hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a_in, int64_t splits, T* p
   }
 #undef NT_CASE
   if (e != hipSuccess || splits == 1) return e;
-  const int64_t total = a.M * a.N;
-  reduce_splits_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(
-      part, (int)splits, dsplit, a.M, (int)a.N, a.ldd, a.D, a.N);
-  return NMF_LAUNCH_CHECK();
+  return reduce_splits<T>(part, (int)splits, dsplit, a.M, (int)a.N, a.ldd, a.D, a.N, st);
 }
 
 template int64_t gemm_auto_splits<float>(GemmKind, int64_t, int64_t, int64_t);

@@ -32,6 +32,23 @@ hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a, int64_t splits, T* part
                     hipStream_t st);
 template <typename T>
 int64_t gemm_auto_splits(GemmKind kind, int64_t M, int64_t N, int64_t K);
+// D[i][j] (ld ldd) = sum over s of part[s * dsplit + i * ldp + j], in the
+// order s = 0, 1, ... with double sums, for i < M, j < N.
+template <typename T>
+hipError_t reduce_splits(const T* part, int splits, int64_t dsplit, int64_t M, int N,
+                         int64_t ldd, T* D, int64_t ldp, hipStream_t st);
+
+// BF16 products: D (M x N float, ld ldd) = X Y^T for X (M x K) and Y (N x K)
+// bfloat16 bits, K contiguous in both (ldx, ldy multiples of 8, rows 16-byte
+// aligned), N a multiple of 16 up to 128, float accumulation. `part` must
+// hold gemm_bf16_splits(M, K) * M * N floats when that count exceeds 1.
+hipError_t gemm_bf16_nt(const uint16_t* X, int64_t ldx, const uint16_t* Y, int64_t ldy, float* D,
+                        int64_t ldd, int64_t M, int N, int64_t K, float* part, hipStream_t st);
+int64_t gemm_bf16_splits(int64_t M, int64_t K);
+// Ft (KP x rows, row pitch ldt) = F^T rounded to bfloat16 (nearest even), for
+// F rows x KP float.
+hipError_t pack_bf16_t(const float* F, int64_t rows, int KP, uint16_t* Ft, int64_t ldt,
+                       hipStream_t st);
 
 // Local updates on rows x KP row-major factors (leading dimension KP); k is
 // the true rank, entries k..KP-1 are zero padding and stay zero.
@@ -53,9 +70,11 @@ template <typename T>
 hipError_t pad_rows(const T* src, int64_t rows, int k, T* dst, int KP, hipStream_t st);
 template <typename T>
 hipError_t unpad_rows(const T* src, int64_t rows, int k, int KP, T* dst, hipStream_t st);
-// At (n x m, ld m) = A^T for A (m x n, lda).
+// At (n x m, row pitch ldt >= m) = A^T for A (m x n, lda). T is float,
+// double or uint16_t (bfloat16 bits).
 template <typename T>
-hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, hipStream_t st);
+hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, int64_t ldt,
+                          hipStream_t st);
 // src (rows x KP, row major) -> dst (KP x rows, row major), all KP rows.
 template <typename T>
 hipError_t transpose_rows(const T* src, int64_t rows, int KP, T* dst, hipStream_t st);
@@ -69,8 +88,10 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
 // (capacity given by *_partials) and a final reduce sums them in order.
 template <typename T>
 int64_t residual_partials(int64_t m, int64_t n);
-template <typename T>
-hipError_t residual_sq(const T* A, int64_t lda, int64_t m, int64_t n, const T* W, const T* Ht,
+// residual_sq: A is stored as TA (T, or uint16_t bfloat16 bits with float
+// factors). sumsq and check_dense take float, double or uint16_t A.
+template <typename T, typename TA = T>
+hipError_t residual_sq(const TA* A, int64_t lda, int64_t m, int64_t n, const T* W, const T* Ht,
                        int KP, double* partial, hipStream_t st);
 template <typename T>
 int64_t sumsq_partials(int64_t m, int64_t n);

@@ -30,8 +30,8 @@ __device__ __forceinline__ double block_sum(double v) {
 // Each wave: 64 rows x 64 columns of the residual; block = 4 waves stacked in
 // columns (64 x 256).
 constexpr int RT = 64;
-template <typename T>
-__global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ A, int64_t lda,
+template <typename T, typename TA>
+__global__ __launch_bounds__(256) void residual_kernel(const TA* __restrict__ A, int64_t lda,
                                                        int64_t m, int64_t n,
                                                        const T* __restrict__ W,
                                                        const T* __restrict__ Ht, int KP,
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ A, 
           for (int b = 0; b < 4; ++b) {
             const int64_t col = c0 + 16 * b + c;
             if (col < n) {
-              const double d = (double)A[row * lda + col] - (double)acc[a][b][r];
+              const double d = to_double(A[row * lda + col]) - (double)acc[a][b][r];
               local += d * d;
             }
           }
@@ -100,11 +100,11 @@ int64_t residual_partials(int64_t m, int64_t n) {
   return cdiv(n, 4 * RT) * cdiv(m, RT);
 }
 
-template <typename T>
-hipError_t residual_sq(const T* A, int64_t lda, int64_t m, int64_t n, const T* W, const T* Ht,
+template <typename T, typename TA>
+hipError_t residual_sq(const TA* A, int64_t lda, int64_t m, int64_t n, const T* W, const T* Ht,
                        int KP, double* partial, hipStream_t st) {
   dim3 grid((unsigned)cdiv(n, 4 * RT), (unsigned)cdiv(m, RT));
-  residual_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, W, Ht, KP, partial);
+  residual_kernel<T, TA><<<grid, 256, 0, st>>>(A, lda, m, n, W, Ht, KP, partial);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const T* __restrict__ A, int
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   for (int64_t r = r0; r < r0 + 64 && r < m; ++r)
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-      const double a = (double)A[r * lda + j];
+      const double a = to_double(A[r * lda + j]);
       local += a * a;
     }
   const double s = block_sum(local);
@@ -173,8 +173,8 @@ __global__ void check_dense_kernel(const T* __restrict__ A, int64_t lda, int64_t
   int bad = 0;
   for (int64_t r = r0; r < r0 + 16 && r < m; ++r)
     for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-      const T a = A[r * lda + j];
-      if (!(a >= T(0)) || a == (T)INFINITY) bad = 1;
+      const double a = to_double(A[r * lda + j]);
+      if (!(a >= 0.0) || a == (double)INFINITY) bad = 1;
     }
   if (bad) atomicOr(flag, 1);
 }
@@ -188,8 +188,8 @@ hipError_t check_dense(const T* A, int64_t lda, int64_t m, int64_t n, int* flag,
 
 #define INST(T)                                                                               \
   template int64_t residual_partials<T>(int64_t, int64_t);                                    \
-  template hipError_t residual_sq<T>(const T*, int64_t, int64_t, int64_t, const T*, const T*, \
-                                     int, double*, hipStream_t);                              \
+  template hipError_t residual_sq<T, T>(const T*, int64_t, int64_t, int64_t, const T*,        \
+                                        const T*, int, double*, hipStream_t);                 \
   template int64_t sumsq_partials<T>(int64_t, int64_t);                                       \
   template hipError_t sumsq<T>(const T*, int64_t, int64_t, int64_t, double*, hipStream_t);    \
   template hipError_t finish_relerr<T>(const double*, int64_t, const T*, const T*, int,       \
@@ -198,5 +198,13 @@ hipError_t check_dense(const T* A, int64_t lda, int64_t m, int64_t n, int* flag,
 INST(float)
 INST(double)
 #undef INST
+template hipError_t residual_sq<float, uint16_t>(const uint16_t*, int64_t, int64_t, int64_t,
+                                                 const float*, const float*, int, double*,
+                                                 hipStream_t);
+template int64_t sumsq_partials<uint16_t>(int64_t, int64_t);
+template hipError_t sumsq<uint16_t>(const uint16_t*, int64_t, int64_t, int64_t, double*,
+                                    hipStream_t);
+template hipError_t check_dense<uint16_t>(const uint16_t*, int64_t, int64_t, int64_t, int*,
+                                          hipStream_t);
 
 }  // namespace nmfk

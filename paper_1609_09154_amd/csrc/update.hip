@@ -290,7 +290,7 @@ __global__ void transpose_out_kernel(const T* __restrict__ Ht, int k, int64_t n,
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_full_kernel(const T* __restrict__ A,
                                                              int64_t lda, int64_t m, int64_t n,
-                                                             T* __restrict__ At) {
+                                                             T* __restrict__ At, int64_t ldt) {
   __shared__ T tile[64][65];
   const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -301,14 +301,15 @@ __global__ __launch_bounds__(256) void transpose_full_kernel(const T* __restrict
   __syncthreads();
   for (int i = ty; i < 64; i += 4) {
     const int64_t c = c0 + i, r = r0 + tx;
-    if (c < n && r < m) At[c * m + r] = tile[tx][i];
+    if (c < n && r < m) At[c * ldt + r] = tile[tx][i];
   }
 }
 
 template <typename T>
-hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, hipStream_t st) {
+hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, int64_t ldt,
+                          hipStream_t st) {
   dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
-  transpose_full_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, At);
+  transpose_full_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, At, ldt);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -359,9 +360,12 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
   template hipError_t transpose_in<T>(const T*, int, int64_t, T*, int, hipStream_t);        \
   template hipError_t transpose_out<T>(const T*, int, int64_t, int, T*, hipStream_t);         \
   template hipError_t transpose_rows<T>(const T*, int64_t, int, T*, hipStream_t);            \
-  template hipError_t transpose_full<T>(const T*, int64_t, int64_t, int64_t, T*, hipStream_t);
+  template hipError_t transpose_full<T>(const T*, int64_t, int64_t, int64_t, T*, int64_t,      \
+                                        hipStream_t);
 INST(float)
 INST(double)
 #undef INST
+template hipError_t transpose_full<uint16_t>(const uint16_t*, int64_t, int64_t, int64_t,
+                                             uint16_t*, int64_t, hipStream_t);
 
 }  // namespace nmfk
