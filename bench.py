@@ -46,6 +46,8 @@ WORKLOADS = {
     "dense-2000x1000-k10-mu-f64": dict(m=2000, n=1000, k=10, k_true=10, algo="mu", dtype="f64"),
     "csr-1048576x1048576-d1e-4-k50-abpp-f32": dict(m=1 << 20, n=1 << 20, k=50, density=1e-4,
                                                    algo="abpp", dtype="f32", sparse=True),
+    "dense-131072x65536-k100-hals-bf16": dict(m=131072, n=65536, k=100, k_true=100, algo="hals",
+                                              dtype="bf16"),
 }
 
 
@@ -179,6 +181,81 @@ def run_sparse(args, wl):
     print(json.dumps(out), flush=True)
 
 
+def run_bf16(args, wl):
+    """Precision workload: the same planted matrix stored in bfloat16 (the
+    two large products on the BF16 matrix cores, everything else float32)
+    and in float32, factorised from the same initial factors. value is the
+    BF16 rate; the FP32 rate and both final relative errors (direct residual
+    against the float32 A, double accumulation) are reported beside it.
+    roofline: the BF16 products stream A (2 bytes per entry) once per launch:
+    HBM-bound at k flops per byte."""
+    import torch
+
+    import paper_1609_09154_amd as nmf
+    from synth import init_factors, planted_dense_torch
+
+    m, n, k = wl["m"], wl["n"], wl["k"]
+    dev = torch.device("cuda:0")
+    print("[bench] generating %s" % args.workload, file=sys.stderr, flush=True)
+    A32 = planted_dense_torch(m, n, wl["k_true"], sigma=0.01, seed=1609, device=dev,
+                              dtype=torch.float32)
+    Ab = A32.to(torch.bfloat16)
+    W0n, H0n = init_factors(m, n, k, seed=9154)
+    W0 = torch.from_numpy(W0n).to(dev, torch.float32)
+    H0 = torch.from_numpy(H0n).to(dev, torch.float32)
+    torch.cuda.synchronize()
+    res = {}
+    for tag, A in (("bf16", Ab), ("f32", A32)):
+        print("[bench] %s: warmup %d" % (tag, args.warmup), file=sys.stderr, flush=True)
+        W, H = W0.clone(), H0.clone()
+        nmf.nmf_dense(A, W, H, algo=wl["algo"], iters=args.warmup, objective=False)
+        W.copy_(W0)
+        H.copy_(H0)
+        torch.cuda.synchronize()
+        print("[bench] %s: timing %d steps" % (tag, args.steps), file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        _, st = nmf.nmf_dense(A, W, H, algo=wl["algo"], iters=args.steps, objective=False,
+                              timers=True)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        rel = nmf.nmf_dense_relerr(A32, W, H.t().contiguous())
+        res[tag] = dict(elapsed=elapsed, stats=st, rel_err=rel)
+    b = res["bf16"]
+    ms_launch = 0.5 * (b["stats"]["ms_mm_aht"] + b["stats"]["ms_mm_wta"]) / args.steps
+    bytes_launch = 2.0 * m * n
+    achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
+    f = res["f32"]
+    ms_launch32 = 0.5 * (f["stats"]["ms_mm_aht"] + f["stats"]["ms_mm_wta"]) / args.steps
+    out = {
+        "metric": "NMF iterations/s (dense HALS, A 131072x65536 bf16, k=100; BF16 products)",
+        "value": round(args.steps / b["elapsed"], 3), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * b["elapsed"] / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "algorithm": wl["algo"],
+                   "parallelism": "single-gpu"},
+        "phase_ms_per_step": {p: round(b["stats"][q] / args.steps, 4) for p, q in
+                              (("mm", "ms_mm"), ("luc", "ms_luc"), ("gram", "ms_gram"))},
+        "rel_err_after_steps": {"bf16": b["rel_err"], "f32": f["rel_err"],
+                                "bf16_minus_f32_relative": (b["rel_err"] - f["rel_err"])
+                                / f["rel_err"]},
+        "f32_same_problem": {"value": round(args.steps / f["elapsed"], 3), "unit": "iters/s",
+                             "ms_per_step": round(1000.0 * f["elapsed"] / args.steps, 3),
+                             "ms_per_product": round(ms_launch32, 4),
+                             "tflops_products": round(2.0 * m * n * k / (ms_launch32 * 1e-3)
+                                                      / 1e12, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "gemm_bf16_nt (A H^T and A^T W, BF16 MFMA 16x16x32)",
+                     "ms_per_launch": round(ms_launch, 4),
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "tflops": round(2.0 * m * n * k / (ms_launch * 1e-3) / 1e12, 2)},
+    }
+    if args.copy_calibration:
+        copy_calibration(dev)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +282,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl.get("sparse"):
         return run_sparse(args, wl)
+    if wl["dtype"] == "bf16":
+        return run_bf16(args, wl)
     m, n, k = wl["m"], wl["n"], wl["k"]
     tdt = torch.float32 if wl["dtype"] == "f32" else torch.float64
     dev = torch.device("cuda:0")

@@ -37,36 +37,40 @@ __device__ __forceinline__ uint16_t to_bf16_rne(float x) {
 }
 
 constexpr int BK = 64;         // K values per step (two MFMAs per tile)
-constexpr int BMT = 4;         // 16-row tiles per wave
 constexpr int BWAVES = 4;      // waves per workgroup
-constexpr int BROWS = 16 * BMT * BWAVES;  // rows of X per workgroup
 constexpr int YLD = BK + 8;    // LDS row pitch of the factor slice (bf16 units)
 
 // Lane (g = l / 16, c = l % 16) of a wave reads, for each of its row tiles,
 // the 32 bytes X[row][k0 + 16 g .. k0 + 16 g + 15]: elements 0..7 feed the
 // first MFMA of the step and 8..15 the second. The same K permutation is
 // applied to the factor operand, so the sum is unchanged.
-struct XFrag { u32x4 v[BMT][2]; };
+template <int MT> struct XFrag { u32x4 v[MT][2]; };
 
-template <int NT, int STAGES>
-__global__ __launch_bounds__(64 * BWAVES, 1) void gemm_bf16_nt_kernel(
+// NT 16-column tiles (N = 16 NT), MT 16-row tiles per wave, STAGES K steps
+// of X in registers (STAGES - 1 in flight while one is multiplied), WPE
+// waves per SIMD to leave room for (the register budget follows from it).
+template <int NT, int MT, int STAGES, int WPE>
+__global__ __launch_bounds__(64 * BWAVES, WPE) void gemm_bf16_nt_kernel(
     const uint16_t* __restrict__ X, int64_t ldx, const uint16_t* __restrict__ Y, int64_t ldy,
     float* __restrict__ D, int64_t ldd, int64_t dsplit, int64_t M, int64_t K, int64_t kchunk) {
   constexpr int NR = 16 * NT;               // factor rows (the padded rank)
   constexpr int YCH = BK / 8;               // 16-byte chunks per factor row per step
-  constexpr int YPASS = (NR * YCH + 255) / 256;
-  __shared__ __attribute__((aligned(16))) uint16_t Ys[2][NR * YLD];
+  constexpr int YRP = 256 / YCH;            // factor rows staged per pass
+  constexpr int YPASS = (NR + YRP - 1) / YRP;
+  // LDS rows NR..YPASS*YRP-1 take the copies of the last pass past the
+  // factor's end (their global row is clamped): no branch in the staging.
+  __shared__ __attribute__((aligned(16))) uint16_t Ys[2][YPASS * YRP * YLD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c = lane & 15;
-  const int64_t m0 = (int64_t)blockIdx.x * BROWS + wave * 16 * BMT;
+  const int64_t m0 = (int64_t)blockIdx.x * (16 * MT * BWAVES) + wave * 16 * MT;
   const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
   const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
   D += (int64_t)blockIdx.y * dsplit;
 
-  const uint16_t* xr[BMT];
+  const uint16_t* xr[MT];
 #pragma unroll
-  for (int t = 0; t < BMT; ++t) {
+  for (int t = 0; t < MT; ++t) {
     int64_t row = m0 + 16 * t + c;
     row = row < M ? row : M - 1;
     xr[t] = X + row * ldx + 16 * g;
@@ -74,72 +78,77 @@ __global__ __launch_bounds__(64 * BWAVES, 1) void gemm_bf16_nt_kernel(
   // factor staging: thread tid copies chunk (tid % YCH) of rows tid / YCH + 32 p
   const int ych = tid % YCH, yrow0 = tid / YCH;
 
-  f32x4 acc[BMT][NT];
+  f32x4 acc[MT][NT];
 #pragma unroll
-  for (int t = 0; t < BMT; ++t)
+  for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nfull = (kend - kbeg) / BK;
-  XFrag xf[STAGES];
-  u32x4 yv[YPASS];
+  XFrag<MT> xf[STAGES];
+  u32x4 yv[2][YPASS];  // factor slices of the next two steps, in registers
 
-  auto load_x = [&](XFrag& f, int64_t k0) {
+  auto load_x = [&](XFrag<MT>& f, int64_t k0) {
 #pragma unroll
-    for (int t = 0; t < BMT; ++t) {
+    for (int t = 0; t < MT; ++t) {
       f.v[t][0] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(xr[t] + k0));
       f.v[t][1] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(xr[t] + k0 + 8));
     }
   };
-  auto load_y = [&](int64_t k0) {
+  auto load_y = [&](u32x4 (&v)[YPASS], int64_t k0) {
 #pragma unroll
     for (int p = 0; p < YPASS; ++p) {
-      const int r = yrow0 + p * (256 / YCH);
-      if (r < NR) yv[p] = *reinterpret_cast<const u32x4*>(Y + (int64_t)r * ldy + k0 + 8 * ych);
+      const int r = yrow0 + p * YRP;
+      const int rg = r < NR ? r : NR - 1;
+      v[p] = *reinterpret_cast<const u32x4*>(Y + (int64_t)rg * ldy + k0 + 8 * ych);
     }
   };
-  auto store_y = [&](int buf) {
+  auto store_y = [&](const u32x4 (&v)[YPASS], int buf) {
 #pragma unroll
     for (int p = 0; p < YPASS; ++p) {
-      const int r = yrow0 + p * (256 / YCH);
-      if (r < NR) *reinterpret_cast<u32x4*>(&Ys[buf][r * YLD + 8 * ych]) = yv[p];
+      const int r = yrow0 + p * YRP;
+      *reinterpret_cast<u32x4*>(&Ys[buf][r * YLD + 8 * ych]) = v[p];
     }
   };
-  auto compute = [&](const XFrag& f, int buf) {
+  auto compute = [&](const XFrag<MT>& f, int buf) {
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const uint16_t* yp = &Ys[buf][(16 * j + c) * YLD + 16 * g];
       const bf16x8 b0 = as_bf16x8(*reinterpret_cast<const u32x4*>(yp));
       const bf16x8 b1 = as_bf16x8(*reinterpret_cast<const u32x4*>(yp + 8));
 #pragma unroll
-      for (int t = 0; t < BMT; ++t) {
+      for (int t = 0; t < MT; ++t) {
         acc[t][j] = mfma_bf16(as_bf16x8(f.v[t][0]), b0, acc[t][j]);
         acc[t][j] = mfma_bf16(as_bf16x8(f.v[t][1]), b1, acc[t][j]);
       }
     }
   };
 
+  // Memory loads complete in issue order as far as the wait counter is
+  // concerned, so each step issues the factor slice it will need two steps
+  // later before the matrix rows it will need STAGES - 1 steps later: the
+  // slice written to LDS at the end of a step was issued a full step earlier,
+  // ahead of the newest row loads, and waiting for it leaves those in flight.
+  static_assert(STAGES % 2 == 0, "the unrolled ring also indexes the two factor slices");
   if (nfull > 0) {
-    // prologue: X steps 0 .. STAGES-2 in flight, factor slice of step 0 in LDS
+    load_y(yv[0], kbeg);
 #pragma unroll
     for (int s = 0; s < STAGES - 1; ++s)
       if (s < nfull) load_x(xf[s], kbeg + s * BK);
-    load_y(kbeg);
-    store_y(0);
+    if (nfull > 1) load_y(yv[1], kbeg + BK);
+    store_y(yv[0], 0);
     __syncthreads();
     // steady state, unrolled STAGES times so every ring index is a constant
-    int64_t s = 0;
-    for (; s < nfull; s += STAGES) {
+    for (int64_t s = 0; s < nfull; s += STAGES) {
 #pragma unroll
       for (int u = 0; u < STAGES; ++u) {
         const int64_t st = s + u;
         if (st < nfull) {
+          if (st + 2 < nfull) load_y(yv[u & 1], kbeg + (st + 2) * BK);
           const int64_t pre = st + STAGES - 1;
           if (pre < nfull) load_x(xf[(u + STAGES - 1) % STAGES], kbeg + pre * BK);
-          const bool more = st + 1 < nfull;
-          if (more) load_y(kbeg + (st + 1) * BK);
-          compute(xf[u], (int)(st & 1));
-          if (more) store_y((int)((st + 1) & 1));
+          compute(xf[u], u & 1);
+          if (st + 1 < nfull) store_y(yv[(u + 1) & 1], (u + 1) & 1);
           __syncthreads();
         }
       }
@@ -148,9 +157,9 @@ __global__ __launch_bounds__(64 * BWAVES, 1) void gemm_bf16_nt_kernel(
   // K tail (fewer than BK values left): element loads, zero beyond kend
   const int64_t kt = kbeg + nfull * BK;
   if (kt < kend) {
-    XFrag f;
+    XFrag<MT> f;
 #pragma unroll
-    for (int t = 0; t < BMT; ++t)
+    for (int t = 0; t < MT; ++t)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         unsigned w[4];
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(64 * BWAVES, 1) void gemm_bf16_nt_kernel(
   }
   // store: element r of tile (t, j) is row 4 g + r, column c
 #pragma unroll
-  for (int t = 0; t < BMT; ++t)
+  for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = m0 + 16 * t + 4 * g + r;
@@ -213,6 +222,9 @@ hipError_t pack_bf16_t(const float* F, int64_t rows, int KP, uint16_t* Ft, int64
   return NMF_LAUNCH_CHECK();
 }
 
+constexpr int B_MT = 2, B_STAGES = 2, B_WPE = 1;  // launch shape (timing sweep at 131072 x 65536, k = 100)
+constexpr int BROWS = 16 * B_MT * BWAVES;
+
 int64_t gemm_bf16_splits(int64_t M, int64_t K) {
   const int64_t blocks = cdiv(M, BROWS);
   int64_t s = 1;
@@ -234,8 +246,8 @@ hipError_t gemm_bf16_nt(const uint16_t* X, int64_t ldx, const uint16_t* Y, int64
   const int NT = N / 16;
 #define CASE(J)                                                                            \
   case J:                                                                                  \
-    gemm_bf16_nt_kernel<J, 3><<<grid, 64 * BWAVES, 0, st>>>(X, ldx, Y, ldy, out, ldo,      \
-                                                            dsplit, M, K, kchunk);         \
+    gemm_bf16_nt_kernel<J, B_MT, B_STAGES, B_WPE><<<grid, 64 * BWAVES, 0, st>>>(          \
+        X, ldx, Y, ldy, out, ldo, dsplit, M, K, kchunk);                                   \
     break;
   switch (NT) {
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)

@@ -151,3 +151,65 @@ def test_csr_2e20_abpp_sampled_parity():
     # its start, and e_t against the oracle's evaluation of the same factors.
     assert (Wg >= 0).all() and (Hg >= 0).all()
     assert errs[1] < errs[0]
+
+
+def test_bf16_131072x65536_k100_hals_one_iteration_full_parity():
+    """Precision workload at full size: A = W0 H0 + |N(0, 0.01)| stored in
+    bfloat16 (131072 x 65536, 17.2 GB), k = 100, one HALS iteration with the
+    products on the BF16 matrix cores. The oracle repeats the iteration in
+    FP64 on the same bfloat16 values, rounding the product's factor operand
+    to bfloat16 as the method does (oracle.round_bf16), from host copies of
+    A streamed in row blocks."""
+    import torch
+
+    m, n, k = 131072, 65536, 100
+    dev = torch.device("cuda:0")
+    step("fullsize bf16: generate A 131072 x 65536 bf16")
+    A = planted_dense_torch(m, n, 100, sigma=0.01, seed=1609, device=dev, dtype=torch.bfloat16)
+    W0n, H0n = init_factors(m, n, k, seed=9154)
+    W0n = W0n.astype(np.float32)
+    H0n = H0n.astype(np.float32)
+    W = torch.from_numpy(W0n).to(dev)
+    H = torch.from_numpy(H0n).to(dev)
+    step("fullsize bf16: one HALS iteration on the GPU")
+    errs, st = nmf.nmf_dense(A, W, H, algo="hals", iters=1, objective=True)
+    torch.cuda.synchronize()
+    Wg, Hg = host(W).astype(np.float64), host(H).astype(np.float64)
+
+    def blocks(what):
+        for r0 in range(0, m, ROWS):
+            r1 = min(m, r0 + ROWS)
+            if r0 % (8 * ROWS) == 0:
+                step("fullsize bf16 oracle: %s, rows %d of %d" % (what, r0, m))
+            yield r0, r1, A[r0:r1].cpu().to(torch.float64).numpy()
+
+    step("fullsize bf16: oracle iteration from host blocks of A")
+    W0 = W0n.astype(np.float64)
+    H0 = H0n.astype(np.float64)
+    Q = oracle.gram_fixed_H(H0)
+    H0r = oracle.round_bf16(H0)
+    P = np.empty((m, k))
+    normA = 0.0
+    res0 = 0.0
+    for r0, r1, Ab in blocks("A H^T"):
+        P[r0:r1] = oracle.product_AHt(Ab, H0r)
+        normA += float(np.sum(Ab * Ab))
+        res0 += oracle.objective_sq(Ab, W0[r0:r1], H0)
+    W1, Hs = oracle.hals_update_W(W0, H0, Q, P)
+    S = oracle.gram_fixed_W(W1)
+    W1r = oracle.round_bf16(W1)
+    R = np.zeros((k, n))
+    for r0, r1, Ab in blocks("W^T A"):
+        R += oracle.product_WtA(Ab, W1r[r0:r1])
+    H1 = oracle.hals_update_H(Hs, S, R)
+    res1 = 0.0
+    for r0, r1, Ab in blocks("residual"):
+        res1 += oracle.objective_sq(Ab, W1[r0:r1], H1)
+    e_ref = [np.sqrt(res0 / normA), np.sqrt(res1 / normA)]
+    d_e = rel_diff(errs, e_ref)
+    d_w = float(np.max(np.abs(Wg - W1)) / np.abs(W1).max())
+    d_h = float(np.max(np.abs(Hg - H1)) / np.abs(H1).max())
+    print("fullsize bf16 HALS: rel err gpu %s oracle %s; objective diff %.2e, "
+          "max |dW|/max|W| %.2e, max |dH|/max|H| %.2e" % (errs, e_ref, d_e, d_w, d_h))
+    assert d_e <= 1e-4
+    assert d_w <= 1e-2 and d_h <= 1e-2
