@@ -29,3 +29,4 @@ from .nmf import (  # noqa: F401
     round_bf16, MU_EPS,
 )
 from .bpp import bpp_nnls, passive_solve  # noqa: F401
+from .autodiff import mu_unrolled_forward, mu_unrolled_vjp  # noqa: F401
