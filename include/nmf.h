@@ -233,6 +233,42 @@ nmf_status nmf_csr_relerr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
                           const float* vals, int k, const float* W,
                           const float* Ht, double* out);
 
+/* ---- Differentiation through unrolled MU iterations -------------------------
+ * The map (A, W_0, H_0) -> (W_T, H_T) of T iterations of Algorithm 1 with the
+ * MU rule of Section 4.1, Eq. (3) (W step, then H step; eps added to every
+ * denominator), and its reverse-mode gradient for any scalar loss of
+ * (W_T, H_T). Dense A, NMF_F32 or NMF_F64, 1 <= k <= 64.
+ *
+ * Checkpoints: the forward pass stores the factors entering iterations
+ * 0, c, 2c, ... (c = ckpt_every >= 1) in a device buffer of
+ * nmf_mu_ckpt_elems(m, n, k, T, c) elements of dtype (the library's internal
+ * padded row layout; opaque to the caller). The backward pass recomputes each
+ * segment of c iterations from its checkpoint and runs the adjoint through
+ * it in reverse, so its memory grows with c, not with T. It must be given the
+ * same m, n, A, k, T, eps and c as the forward pass that wrote the buffer.
+ */
+
+/* Elements of dtype in the checkpoint buffer, or -1 for invalid sizes. */
+int64_t nmf_mu_ckpt_elems(int64_t m, int64_t n, int k, int iters, int ckpt_every);
+
+/* W (m x k, leading dimension k) and H (k x n, leading dimension n): W_0 and
+ * H_0 on entry, W_T and H_T on return. ckpt: device buffer as above, or NULL
+ * when no backward pass will follow. */
+nmf_status nmf_mu_unrolled_forward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
+                                   int64_t n, const void* A, int64_t lda, int k,
+                                   int iters, double eps, int ckpt_every,
+                                   void* W, void* H, void* ckpt);
+
+/* Given gW = dL/dW_T (m x k) and gH = dL/dH_T (k x n), writes
+ * gW0 = dL/dW_0 (m x k), gH0 = dL/dH_0 (k x n) and, if gA is not NULL,
+ * gA = dL/dA (m x n, leading dimension ldga >= n; overwritten). */
+nmf_status nmf_mu_unrolled_backward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
+                                    int64_t n, const void* A, int64_t lda, int k,
+                                    int iters, double eps, int ckpt_every,
+                                    const void* ckpt, const void* gW,
+                                    const void* gH, void* gA, int64_t ldga,
+                                    void* gW0, void* gH0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ from ._lib import (NMF_ABPP, NMF_BF16, NMF_F32, NMF_F64, NMF_HALS, NMF_MU, NMF_O
                    NMF_OBJ_NONE, NMFError, NmfStats, default_opts)
 
 __all__ = ["Context", "NMFError", "nmf_dense", "nmf_csr", "nmf_gram", "nmf_dense_AF",
+           "nmf_mu_unrolled_forward", "nmf_mu_unrolled_backward", "mu_unrolled",
            "nmf_dense_AtF", "nmf_csr_AF", "nmf_csr_transpose", "nmf_update",
            "nmf_hals_normalize", "nmf_dense_relerr", "nmf_csr_relerr", "library_path"]
 
@@ -296,3 +297,90 @@ def nmf_csr_relerr(rowptr, colidx, vals, n, W, Ht, ctx=None):
                                     _dev(Ht, "Ht", dtype=torch.float32, shape=(n, k)),
                                     ctypes.byref(out)))
     return out.value
+
+
+# ---- differentiation through unrolled MU iterations ----------------------
+
+def nmf_mu_unrolled_forward(A, W0, H0, iters, eps=1e-16, ckpt_every=10, want_ckpt=True,
+                            ctx=None):
+    """T = iters MU iterations from (W0, H0) (not modified). Returns
+    (W_T, H_T, ckpt) where ckpt (or None) feeds nmf_mu_unrolled_backward."""
+    torch = _torch()
+    m, n = A.shape
+    k = W0.shape[1]
+    _dev(A, "A")
+    _dev(W0, "W0", dtype=A.dtype, shape=(m, k))
+    _dev(H0, "H0", dtype=A.dtype, shape=(k, n))
+    W = W0.clone()
+    H = H0.clone()
+    ckpt = None
+    if want_ckpt:
+        ne = _lib.lib().nmf_mu_ckpt_elems(m, n, k, iters, ckpt_every)
+        if ne < 0:
+            raise ValueError("invalid sizes for the unrolled MU gradient")
+        ckpt = torch.empty(max(ne, 1), dtype=A.dtype, device=A.device)
+    c = _ctx(ctx, A.device.index or 0)
+    c.check(_lib.lib().nmf_mu_unrolled_forward(
+        c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0), k, iters, float(eps),
+        ckpt_every, _dev(W, "W"), _dev(H, "H"),
+        _dev(ckpt, "ckpt") if ckpt is not None else None))
+    return W, H, ckpt
+
+
+def nmf_mu_unrolled_backward(A, ckpt, gW, gH, iters, eps=1e-16, ckpt_every=10, want_gA=True,
+                             ctx=None):
+    """(dL/dA or None, dL/dW0, dL/dH0) from dL/dW_T = gW and dL/dH_T = gH."""
+    torch = _torch()
+    m, n = A.shape
+    k = gW.shape[1]
+    _dev(gW, "gW", dtype=A.dtype, shape=(m, k))
+    _dev(gH, "gH", dtype=A.dtype, shape=(k, n))
+    gA = torch.empty((m, n), dtype=A.dtype, device=A.device) if want_gA else None
+    gW0 = torch.empty((m, k), dtype=A.dtype, device=A.device)
+    gH0 = torch.empty((k, n), dtype=A.dtype, device=A.device)
+    c = _ctx(ctx, A.device.index or 0)
+    c.check(_lib.lib().nmf_mu_unrolled_backward(
+        c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0), k, iters, float(eps),
+        ckpt_every, _dev(ckpt, "ckpt"), _dev(gW, "gW"), _dev(gH, "gH"),
+        _dev(gA, "gA") if gA is not None else None, n, _dev(gW0, "gW0"), _dev(gH0, "gH0")))
+    return gA, gW0, gH0
+
+
+def _mu_unrolled_function():
+    torch = _torch()
+
+    class MUUnrolled(torch.autograd.Function):
+        """T unrolled MU iterations as a differentiable layer: forward and
+        backward both run in the library (checkpoints every ckpt_every
+        iterations, segments recomputed in the backward pass)."""
+
+        @staticmethod
+        def forward(fctx, A, W0, H0, iters, eps, ckpt_every):
+            A, W0, H0 = A.contiguous(), W0.contiguous(), H0.contiguous()
+            W, H, ckpt = nmf_mu_unrolled_forward(A, W0, H0, iters, eps, ckpt_every)
+            fctx.save_for_backward(A, ckpt)
+            fctx.meta = (iters, eps, ckpt_every, W0.shape, H0.shape)
+            return W, H
+
+        @staticmethod
+        def backward(fctx, gW, gH):
+            A, ckpt = fctx.saved_tensors
+            iters, eps, ckpt_every, ws, hs = fctx.meta
+            gW = torch.zeros(ws, dtype=A.dtype, device=A.device) if gW is None else gW.contiguous()
+            gH = torch.zeros(hs, dtype=A.dtype, device=A.device) if gH is None else gH.contiguous()
+            gA, gW0, gH0 = nmf_mu_unrolled_backward(A, ckpt, gW, gH, iters, eps, ckpt_every,
+                                                    want_gA=fctx.needs_input_grad[0])
+            return gA, gW0, gH0, None, None, None
+
+    return MUUnrolled
+
+
+_MU_FN = None
+
+
+def mu_unrolled(A, W0, H0, iters, eps=1e-16, ckpt_every=10):
+    """Differentiable (W_T, H_T) = T MU iterations from (W0, H0) on dense A."""
+    global _MU_FN
+    if _MU_FN is None:
+        _MU_FN = _mu_unrolled_function()
+    return _MU_FN.apply(A, W0, H0, iters, eps, ckpt_every)

@@ -63,6 +63,12 @@ SIGNATURES = {
     "nmf_hals_normalize": (_int, [_vp, _int, _i64, _i64, _int, _vp, _vp, _vp, _vp]),
     "nmf_dense_relerr": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _vp, _vp, _dp]),
     "nmf_csr_relerr": (_int, [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _int, _vp, _vp, _dp]),
+    "nmf_mu_ckpt_elems": (_i64, [_i64, _i64, _int, _int, _int]),
+    "nmf_mu_unrolled_forward": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _int,
+                                       ctypes.c_double, _int, _vp, _vp, _vp]),
+    "nmf_mu_unrolled_backward": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _int,
+                                        ctypes.c_double, _int, _vp, _vp, _vp, _vp, _i64, _vp,
+                                        _vp]),
 }
 
 

@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "update.hip", "objective.hip", "sparse.hip", "bpp.hip", "api.hip"]
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "update.hip", "objective.hip", "sparse.hip", "bpp.hip", "autograd.hip", "api.hip"]
 LIB_NAME = "libnmf_mi355x.so"
 ARCH = "gfx950"
 

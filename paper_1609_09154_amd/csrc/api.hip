@@ -1106,3 +1106,269 @@ nmf_status nmf_csr_relerr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Differentiation of T unrolled MU iterations (Section 4.1, Eq. (3)).
+// ===========================================================================
+namespace {
+
+int64_t mu_ckpt_count(int iters, int every) { return iters <= 0 ? 0 : cdiv(iters, every); }
+
+// Buffers shared by the forward and backward passes.
+template <typename T> struct MuWork {
+  T *W, *Ht, *P, *R, *Q, *S, *Ft, *part;
+};
+
+template <typename T>
+size_t mu_plan_common(int64_t m, int64_t n, int KP, Carve& cv, size_t off[8]) {
+  const int64_t mx = std::max(m, n);
+  const int64_t ps = std::max({nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
+                               nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n),
+                               nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m),
+                               nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, n, KP, m),
+                               (int64_t)1});
+  const int64_t part = std::max<int64_t>(ps * mx * KP, gram_splits(mx) * KP * KP);
+  off[0] = cv.take<T>(m * KP);
+  off[1] = cv.take<T>(n * KP);
+  off[2] = cv.take<T>(m * KP);
+  off[3] = cv.take<T>(n * KP);
+  off[4] = cv.take<T>(KP * KP);
+  off[5] = cv.take<T>(KP * KP);
+  off[6] = cv.take<T>(mx * KP);
+  off[7] = cv.take<T>(part);
+  return cv.off;
+}
+
+template <typename T>
+MuWork<T> mu_bind(nmf_ctx* ctx, const size_t off[8]) {
+  return MuWork<T>{at<T>(ctx, off[0]), at<T>(ctx, off[1]), at<T>(ctx, off[2]),
+                   at<T>(ctx, off[3]), at<T>(ctx, off[4]), at<T>(ctx, off[5]),
+                   at<T>(ctx, off[6]), at<T>(ctx, off[7])};
+}
+
+// Rank-side operands of the dense products are read from a transposed copy
+// when its rows are 16-byte aligned.
+template <typename T>
+nmf_status mu_prod_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int k,
+                      int KP, T* Out, MuWork<T>& w) {
+  const bool tf = (n * (int64_t)sizeof(T)) % 16 == 0;
+  if (tf) HIP_TRY(nmfk::transpose_rows<T>(F, n, KP, w.Ft, ctx->stream));
+  return product_AF<T>(ctx, pb, m, n, F, tf ? w.Ft : nullptr, k, KP, Out, w.part);
+}
+
+template <typename T>
+nmf_status mu_prod_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int k,
+                       int KP, T* Out, MuWork<T>& w) {
+  const bool tf = (m * (int64_t)sizeof(T)) % 16 == 0;
+  if (tf) HIP_TRY(nmfk::transpose_rows<T>(F, m, KP, w.Ft, ctx->stream));
+  return product_AtF<T>(ctx, pb, m, n, F, tf ? w.Ft : nullptr, k, KP, Out, w.part);
+}
+
+// One MU iteration from (W, Ht) into (Wn, Htn) (which may alias W, Ht),
+// leaving P = A H^T, Q = H H^T, R = A^T Wn, S = Wn^T Wn in the given buffers.
+template <typename T>
+nmf_status mu_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
+                        T eps, const T* W, const T* Ht, T* Wn, T* Htn, T* P, T* Q, T* R, T* S,
+                        MuWork<T>& w) {
+  hipStream_t st = ctx->stream;
+  nmf_status s;
+  if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part)) != NMF_OK) return s;
+  if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, P, w)) != NMF_OK) return s;
+  if (Wn != W) HIP_TRY(hipMemcpyAsync(Wn, W, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(nmfk::mu_rows<T>(Wn, P, Q, m, k, KP, eps, st));
+  if ((s = gram<T>(ctx, Wn, m, KP, S, w.part)) != NMF_OK) return s;
+  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, R, w)) != NMF_OK) return s;
+  if (Htn != Ht) HIP_TRY(hipMemcpyAsync(Htn, Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(nmfk::mu_rows<T>(Htn, R, S, n, k, KP, eps, st));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status mu_prepare_A(nmf_ctx* ctx, const T* A, int64_t lda, int64_t m, int64_t n,
+                        Prob<T>& pb) {
+  pb.A = A;
+  pb.lda = lda;
+  return transposed_copy<T>(ctx, A, lda, m, n, m, &pb.At);
+}
+
+template <typename T>
+nmf_status mu_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t lda, int k,
+                           int iters, T eps, int every, T* W, T* H, T* ckpt) {
+  const int KP = kp_dense(k);
+  Carve cv;
+  size_t off[8];
+  mu_plan_common<T>(m, n, KP, cv, off);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  MuWork<T> w = mu_bind<T>(ctx, off);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, st));
+  HIP_TRY(nmfk::transpose_in<T>(H, k, n, w.Ht, KP, st));
+  Prob<T> pb;
+  if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
+  const int64_t slot = (m + n) * KP;
+  for (int t = 0; t < iters; ++t) {
+    if (ckpt && t % every == 0) {
+      T* c = ckpt + (int64_t)(t / every) * slot;
+      HIP_TRY(hipMemcpyAsync(c, w.W, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(c + m * KP, w.Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
+    }
+    s = mu_iteration<T>(ctx, pb, m, n, k, KP, eps, w.W, w.Ht, w.W, w.Ht, w.P, w.Q, w.R, w.S, w);
+    if (s != NMF_OK) return s;
+  }
+  HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
+  HIP_TRY(nmfk::transpose_out<T>(w.Ht, k, n, KP, H, st));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t lda, int k,
+                            int iters, T eps, int every, const T* ckpt, const T* gWT,
+                            const T* gHT, T* gA, int64_t ldga, T* gW0, T* gH0) {
+  const int KP = kp_dense(k);
+  const int64_t mx = std::max(m, n);
+  const int seg = std::min(every, std::max(iters, 1));
+  Carve cv;
+  size_t off[8];
+  mu_plan_common<T>(m, n, KP, cv, off);
+  const size_t oWs = cv.take<T>((seg + 1) * m * KP);   // W_t over one segment
+  const size_t oHs = cv.take<T>((seg + 1) * n * KP);   // H_t^T over one segment
+  const size_t oPs = cv.take<T>(seg * m * KP);         // A H_t^T
+  const size_t oRs = cv.take<T>(seg * n * KP);         // A^T W_{t+1}
+  const size_t oQs = cv.take<T>(seg * KP * KP);
+  const size_t oSs = cv.take<T>(seg * KP * KP);
+  const size_t ogW = cv.take<T>(m * KP);
+  const size_t ogH = cv.take<T>(n * KP);
+  const size_t ogW2 = cv.take<T>(m * KP);
+  const size_t ogH2 = cv.take<T>(n * KP);
+  const size_t ogR = cv.take<T>(n * KP);
+  const size_t ogP = cv.take<T>(m * KP);
+  const size_t ogD = cv.take<T>(mx * KP);
+  const size_t otmp = cv.take<T>(mx * KP);
+  const size_t ogG = cv.take<T>(KP * KP);
+  const size_t ogGs = cv.take<T>(KP * KP);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  MuWork<T> w = mu_bind<T>(ctx, off);
+  T *Ws = at<T>(ctx, oWs), *Hs = at<T>(ctx, oHs), *Ps = at<T>(ctx, oPs), *Rs = at<T>(ctx, oRs);
+  T *Qs = at<T>(ctx, oQs), *Ss = at<T>(ctx, oSs);
+  T *gW = at<T>(ctx, ogW), *gH = at<T>(ctx, ogH), *gW2 = at<T>(ctx, ogW2), *gH2 = at<T>(ctx, ogH2);
+  T *gR = at<T>(ctx, ogR), *gP = at<T>(ctx, ogP), *gD = at<T>(ctx, ogD), *tmp = at<T>(ctx, otmp);
+  T *gG = at<T>(ctx, ogG), *gGs = at<T>(ctx, ogGs);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(nmfk::pad_rows<T>(gWT, m, k, gW, KP, st));
+  HIP_TRY(nmfk::transpose_in<T>(gHT, k, n, gH, KP, st));
+  if (gA) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
+  Prob<T> pb;
+  if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
+  const int64_t slot = (m + n) * KP;
+  const int64_t nck = mu_ckpt_count(iters, every);
+  for (int64_t j = nck - 1; j >= 0; --j) {
+    const int t0 = (int)(j * every);
+    const int L = std::min(iters, t0 + every) - t0;
+    // recompute the segment's states from its checkpoint
+    HIP_TRY(hipMemcpyAsync(Ws, ckpt + j * slot, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(Hs, ckpt + j * slot + m * KP, sizeof(T) * n * KP,
+                           hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < L; ++i) {
+      s = mu_iteration<T>(ctx, pb, m, n, k, KP, eps, Ws + i * m * KP, Hs + i * n * KP,
+                          Ws + (i + 1) * m * KP, Hs + (i + 1) * n * KP, Ps + i * m * KP,
+                          Qs + i * KP * KP, Rs + i * n * KP, Ss + i * KP * KP, w);
+      if (s != NMF_OK) return s;
+    }
+    for (int i = L - 1; i >= 0; --i) {
+      const T* W0s = Ws + i * m * KP;
+      const T* W1s = Ws + (i + 1) * m * KP;
+      const T* H0s = Hs + i * n * KP;
+      const T* H1s = Hs + (i + 1) * n * KP;
+      // H step: Ht' = Ht * R / (Ht S + eps), R = A^T W1, S = W1^T W1
+      HIP_TRY(nmfk::mu_adjoint_rows<T>(H0s, H1s, Rs + i * n * KP, Ss + i * KP * KP, gH, n, k,
+                                       KP, eps, gR, gD, gH2, st));
+      {
+        nmfk::GemmArgs<T> a{H0s, KP, gD, KP, gG, KP, KP, KP, n, false, 0};
+        HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(n), w.part, st));
+      }
+      HIP_TRY(nmfk::symmetrize<T>(gG, KP, gGs, st));
+      if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w)) != NMF_OK) return s;
+      HIP_TRY(nmfk::add_to<T>(gW, tmp, m * KP, st));
+      HIP_TRY(nmfk::rowmm_add<T>(W1s, gGs, m, k, KP, gW, st));
+      // W step: W1 = W0 * P / (W0 Q + eps), P = A H0^T, Q = H0 H0^T
+      HIP_TRY(nmfk::mu_adjoint_rows<T>(W0s, W1s, Ps + i * m * KP, Qs + i * KP * KP, gW, m, k,
+                                       KP, eps, gP, gD, gW2, st));
+      {
+        nmfk::GemmArgs<T> a{W0s, KP, gD, KP, gG, KP, KP, KP, m, false, 0};
+        HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(m), w.part, st));
+      }
+      HIP_TRY(nmfk::symmetrize<T>(gG, KP, gGs, st));
+      if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w)) != NMF_OK) return s;
+      HIP_TRY(nmfk::add_to<T>(gH2, tmp, n * KP, st));
+      HIP_TRY(nmfk::rowmm_add<T>(H0s, gGs, n, k, KP, gH2, st));
+      // dL/dA += W1 gR^T (from R = A^T W1) + gP H0 (from P = A H0^T)
+      if (gA) HIP_TRY(nmfk::rank_update<T>(gA, ldga, m, n, W1s, gR, gP, H0s, KP, st));
+      std::swap(gW, gW2);
+      std::swap(gH, gH2);
+    }
+  }
+  HIP_TRY(nmfk::unpad_rows<T>(gW, m, k, KP, gW0, st));
+  HIP_TRY(nmfk::transpose_out<T>(gH, k, n, KP, gH0, st));
+  return NMF_OK;
+}
+
+nmf_status mu_check(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const void* A,
+                    int64_t lda, int k, int iters, double eps, int every) {
+  nmf_status s = check_common(ctx, m, n, k);
+  if (s != NMF_OK) return s;
+  if (dtype != NMF_F32 && dtype != NMF_F64) return fail(ctx, NMF_EINVAL, "dtype must be F32 or F64");
+  if (k > 64) return fail(ctx, NMF_EINVAL, "unrolled MU gradient supports k <= 64");
+  if (!A) return fail(ctx, NMF_EINVAL, "null A");
+  if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
+  if (iters < 0 || every < 1) return fail(ctx, NMF_EINVAL, "iters < 0 or ckpt_every < 1");
+  if (!(eps >= 0.0)) return fail(ctx, NMF_EINVAL, "eps must be >= 0");
+  return NMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t nmf_mu_ckpt_elems(int64_t m, int64_t n, int k, int iters, int ckpt_every) {
+  if (m < 1 || n < 1 || k < 1 || k > 64 || iters < 0 || ckpt_every < 1) return -1;
+  return mu_ckpt_count(iters, ckpt_every) * (m + n) * (int64_t)kp_dense(k);
+}
+
+nmf_status nmf_mu_unrolled_forward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
+                                   const void* A, int64_t lda, int k, int iters, double eps,
+                                   int ckpt_every, void* W, void* H, void* ckpt) {
+  nmf_status s = mu_check(ctx, dtype, m, n, A, lda, k, iters, eps, ckpt_every);
+  if (s != NMF_OK) return s;
+  if (!W || !H) return fail(ctx, NMF_EINVAL, "null W or H");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return mu_forward_impl<float>(ctx, m, n, (const float*)A, lda, k, iters, (float)eps,
+                                  ckpt_every, (float*)W, (float*)H, (float*)ckpt);
+  return mu_forward_impl<double>(ctx, m, n, (const double*)A, lda, k, iters, eps, ckpt_every,
+                                 (double*)W, (double*)H, (double*)ckpt);
+}
+
+nmf_status nmf_mu_unrolled_backward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
+                                    const void* A, int64_t lda, int k, int iters, double eps,
+                                    int ckpt_every, const void* ckpt, const void* gW,
+                                    const void* gH, void* gA, int64_t ldga, void* gW0,
+                                    void* gH0) {
+  nmf_status s = mu_check(ctx, dtype, m, n, A, lda, k, iters, eps, ckpt_every);
+  if (s != NMF_OK) return s;
+  if (!gW || !gH || !gW0 || !gH0 || (iters > 0 && !ckpt))
+    return fail(ctx, NMF_EINVAL, "null checkpoint or gradient array");
+  if (gA && ldga < n) return fail(ctx, NMF_EINVAL, "ldga < n");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return mu_backward_impl<float>(ctx, m, n, (const float*)A, lda, k, iters, (float)eps,
+                                   ckpt_every, (const float*)ckpt, (const float*)gW,
+                                   (const float*)gH, (float*)gA, ldga, (float*)gW0,
+                                   (float*)gH0);
+  return mu_backward_impl<double>(ctx, m, n, (const double*)A, lda, k, iters, eps, ckpt_every,
+                                  (const double*)ckpt, (const double*)gW, (const double*)gH,
+                                  (double*)gA, ldga, (double*)gW0, (double*)gH0);
+}
+
+}  // extern "C"

@@ -119,6 +119,28 @@ hipError_t csr_residual_sq(const int64_t* rowptr, const int32_t* colidx, const f
                            hipStream_t st);
 hipError_t csr_sumsq(const float* vals, int64_t nnz, double* partial, int64_t np,
                      hipStream_t st);
+// Reverse mode through unrolled multiplicative updates (row layout, KP in
+// {16, 32, 48, 64}). For Xn = X * N / (X G + eps): gN = gXn * X / D,
+// gD = -gXn * Xn / D, gX = gXn * N / D + gD G^T (D = X G + eps).
+template <typename T>
+hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* gXn,
+                           int64_t rows, int k, int KP, T eps, T* gN, T* gD, T* gX,
+                           hipStream_t st);
+// Out[r] += X[r] M (M KP x KP), columns < k.
+template <typename T>
+hipError_t rowmm_add(const T* X, const T* M, int64_t rows, int k, int KP, T* Out,
+                     hipStream_t st);
+// M = G + G^T.
+template <typename T>
+hipError_t symmetrize(const T* G, int KP, T* M, hipStream_t st);
+// Y += X (n elements).
+template <typename T>
+hipError_t add_to(T* Y, const T* X, int64_t n, hipStream_t st);
+// D (m x n, ldd) += X1 Y1^T + X2 Y2^T, X* m x KP, Y* n x KP (X2 may be null).
+template <typename T>
+hipError_t rank_update(T* D, int64_t ldd, int64_t m, int64_t n, const T* X1, const T* Y1,
+                       const T* X2, const T* Y2, int KP, hipStream_t st);
+
 // Input checks: sets *flag (device int) nonzero on a bad entry.
 template <typename T>
 hipError_t check_dense(const T* A, int64_t lda, int64_t m, int64_t n, int* flag,

@@ -123,3 +123,25 @@ def test_step_argument_errors(hctx):
     assert L.nmf_dense_relerr(hctx, 1, 10, 8, P, 8, 3, P, P, ctypes.byref(out)) == EDEVICE
     assert L.nmf_csr_transpose(hctx, 10, 8, -2, P, P, P, P, P, P) == EINVAL
     assert L.nmf_hals_normalize(hctx, 1, 10, 8, 0, P, P, None, None) == EINVAL
+
+
+def test_mu_unrolled_argument_errors(hctx):
+    L = _lib.lib()
+    assert L.nmf_mu_ckpt_elems(10, 8, 3, 25, 10) == 3 * (10 + 8) * 16
+    assert L.nmf_mu_ckpt_elems(10, 8, 65, 5, 1) == -1
+    assert L.nmf_mu_ckpt_elems(10, 8, 3, 5, 0) == -1
+    assert L.nmf_mu_ckpt_elems(10, 8, 3, 0, 4) == 0
+    fw = L.nmf_mu_unrolled_forward
+    assert fw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P) == EDEVICE
+    assert fw(hctx, 1, 10, 8, P, 8, 65, 5, 1e-16, 2, P, P, P) == EINVAL   # k > 64
+    assert fw(hctx, 2, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P) == EINVAL    # BF16 A
+    assert fw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 0, P, P, P) == EINVAL    # ckpt_every 0
+    assert fw(hctx, 1, 10, 8, P, 8, 3, -1, 1e-16, 2, P, P, P) == EINVAL   # iters < 0
+    assert fw(hctx, 1, 10, 8, P, 8, 3, 5, -1.0, 2, P, P, P) == EINVAL     # eps < 0
+    assert fw(hctx, 1, 10, 8, P, 7, 3, 5, 1e-16, 2, P, P, P) == EINVAL    # lda < n
+    assert fw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, None, P, P) == EINVAL
+    bw = L.nmf_mu_unrolled_backward
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P, P, 8, P, P) == EDEVICE
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, None, P, P, P, 8, P, P) == EINVAL
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P, P, 7, P, P) == EINVAL  # ldga
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P, None, 0, P, P) == EDEVICE
