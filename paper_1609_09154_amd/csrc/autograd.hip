@@ -14,93 +14,132 @@
 
 namespace nmfk {
 
-// One thread per row r (KP <= 64 values in registers; G read with uniform
-// loads). Writes gN, gD (= dL/dD) and gX for the row; entries k..KP-1 are 0.
+// Rows are split over TPR threads (a power of two, whole rows per wave) of
+// RPT outputs each; 256 threads cover 256 / TPR rows; G is staged in LDS.
+template <int KP> struct AdjSplit {
+  static constexpr int TPR = KP == 48 ? 4 : KP / 8;
+  static constexpr int RPT = KP / TPR;
+  static constexpr int ROWS = 256 / TPR;
+};
+
+// Local adjoint of Xn = X * N / (X G + eps) for the rows of one block: writes
+// gN, gD (= dL/dD) and gX; entries k..KP-1 are 0. G, the block's rows of X
+// and dL/dD (shared between a row's threads for the (dL/dD) G^T term) live in
+// LDS.
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void mu_adjoint_rows_kernel(
     const T* __restrict__ X, const T* __restrict__ Xn, const T* __restrict__ N,
     const T* __restrict__ G, const T* __restrict__ gXn, int64_t rows, int k, T eps,
     T* __restrict__ gN, T* __restrict__ gD, T* __restrict__ gX) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  const T* xr = X + r * KP;
-  T x[KP];
+  constexpr int TPR = AdjSplit<KP>::TPR, RPT = AdjSplit<KP>::RPT, ROWS = AdjSplit<KP>::ROWS;
+  constexpr int VEC = Tr<T>::VEC;
+  constexpr int DLD = KP + VEC;
+  __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
+  __shared__ __attribute__((aligned(16))) T Xs[ROWS * DLD];
+  __shared__ __attribute__((aligned(16))) T Ds[ROWS * DLD];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) Gs[e] = G[e];
+  const int64_t rb = (int64_t)blockIdx.x * ROWS;
+  for (int e = threadIdx.x; e < ROWS * KP; e += 256) {
+    const int q = e / KP, j = e % KP;
+    Xs[q * DLD + j] = rb + q < rows ? X[(rb + q) * KP + j] : T(0);
+  }
+  __syncthreads();
+  const int lr = threadIdx.x / TPR;
+  const int64_t r = rb + lr;
+  const bool live = r < rows;
+  const int i0 = (threadIdx.x % TPR) * RPT;
+  const T* xs = &Xs[lr * DLD];
+  T d[RPT];
 #pragma unroll
-  for (int i = 0; i < KP; ++i) x[i] = xr[i];
-  T dd[KP];  // dL/dD of this row
-  constexpr int CH = 16;
+  for (int ii = 0; ii < RPT; ++ii) d[ii] = T(0);
+#pragma unroll 8
+  for (int j = 0; j < KP; ++j) {
+    const T xj = xs[j];
 #pragma unroll
-  for (int i0 = 0; i0 < KP; i0 += CH) {
-    T d[CH];
+    for (int q = 0; q < RPT / VEC; ++q) {
+      const V16<T> v = load16<T>(&Gs[j * KP + i0 + q * VEC]);
 #pragma unroll
-    for (int ii = 0; ii < CH; ++ii) d[ii] = T(0);
+      for (int w = 0; w < VEC; ++w) d[q * VEC + w] = fma(xj, v.v[w], d[q * VEC + w]);
+    }
+  }
 #pragma unroll
-    for (int j = 0; j < KP; ++j)
-#pragma unroll
-      for (int ii = 0; ii < CH; ++ii) d[ii] = fma(x[j], G[j * KP + i0 + ii], d[ii]);
-#pragma unroll
-    for (int ii = 0; ii < CH; ++ii) {
-      const int i = i0 + ii;
+  for (int ii = 0; ii < RPT; ++ii) {
+    const int i = i0 + ii;
+    T dd = T(0);
+    if (live) {
       const int64_t e = r * KP + i;
       if (i < k) {
         const T den = d[ii] + eps;
         const T g = gXn[e];
-        gN[e] = g * x[i] / den;
-        dd[i] = -g * Xn[e] / den;
-        gX[e] = g * N[e] / den;  // direct term; (dL/dD) G is added below
+        gN[e] = g * xs[i] / den;
+        dd = -g * Xn[e] / den;
+        gX[e] = g * N[e] / den;  // direct term; (dL/dD) G^T is added below
       } else {
         gN[e] = T(0);
-        dd[i] = T(0);
         gX[e] = T(0);
       }
+      gD[e] = dd;
     }
+    Ds[lr * DLD + i] = dd;
   }
+  __syncthreads();
+  if (!live) return;
+  // D_i = sum_j x_j G[j][i], so dL/dx_i picks up sum_j dd_j G[i][j]
 #pragma unroll
-  for (int i0 = 0; i0 < KP; i0 += CH) {
-    T s[CH];
+  for (int ii = 0; ii < RPT; ++ii) {
+    const int i = i0 + ii;
+    if (i < k) {
+      T acc = T(0);
+#pragma unroll 4
+      for (int q = 0; q < KP / VEC; ++q) {
+        const V16<T> gv = load16<T>(&Gs[i * KP + q * VEC]);
+        const V16<T> dv = load16<T>(&Ds[lr * DLD + q * VEC]);
 #pragma unroll
-    for (int ii = 0; ii < CH; ++ii) s[ii] = T(0);
-    // D_i = sum_j x_j G[j][i], so dL/dx_i picks up sum_j dd_j G[i][j]
-#pragma unroll
-    for (int j = 0; j < KP; ++j)
-#pragma unroll
-      for (int ii = 0; ii < CH; ++ii) s[ii] = fma(dd[j], G[(i0 + ii) * KP + j], s[ii]);
-#pragma unroll
-    for (int ii = 0; ii < CH; ++ii) {
-      const int i = i0 + ii;
-      const int64_t e = r * KP + i;
-      gD[e] = dd[i];
-      if (i < k) gX[e] += s[ii];
+        for (int w = 0; w < VEC; ++w) acc = fma(dv.v[w], gv.v[w], acc);
+      }
+      gX[r * KP + i] += acc;
     }
   }
 }
 
-// Out[r] += X[r] M for rows x KP X and KP x KP M (one thread per row).
+// Out[r] += X[r] M for rows x KP X and KP x KP M.
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void rowmm_add_kernel(const T* __restrict__ X,
                                                         const T* __restrict__ M, int64_t rows,
                                                         int k, T* __restrict__ Out) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int TPR = AdjSplit<KP>::TPR, RPT = AdjSplit<KP>::RPT, ROWS = AdjSplit<KP>::ROWS;
+  constexpr int VEC = Tr<T>::VEC;
+  constexpr int XLD = KP + VEC;
+  __shared__ __attribute__((aligned(16))) T Ms[KP * KP];
+  __shared__ __attribute__((aligned(16))) T Xs[ROWS * XLD];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) Ms[e] = M[e];
+  const int64_t rb = (int64_t)blockIdx.x * ROWS;
+  for (int e = threadIdx.x; e < ROWS * KP; e += 256) {
+    const int q = e / KP, j = e % KP;
+    Xs[q * XLD + j] = rb + q < rows ? X[(rb + q) * KP + j] : T(0);
+  }
+  __syncthreads();
+  const int lr = threadIdx.x / TPR;
+  const int64_t r = rb + lr;
   if (r >= rows) return;
-  T x[KP];
+  const int i0 = (threadIdx.x % TPR) * RPT;
+  const T* xs = &Xs[lr * XLD];
+  T s[RPT];
 #pragma unroll
-  for (int i = 0; i < KP; ++i) x[i] = X[r * KP + i];
-  constexpr int CH = 16;
+  for (int ii = 0; ii < RPT; ++ii) s[ii] = T(0);
+#pragma unroll 8
+  for (int j = 0; j < KP; ++j) {
+    const T xj = xs[j];
 #pragma unroll
-  for (int i0 = 0; i0 < KP; i0 += CH) {
-    if (i0 < k) {
-      T s[CH];
+    for (int q = 0; q < RPT / VEC; ++q) {
+      const V16<T> v = load16<T>(&Ms[j * KP + i0 + q * VEC]);
 #pragma unroll
-      for (int ii = 0; ii < CH; ++ii) s[ii] = T(0);
-#pragma unroll
-      for (int j = 0; j < KP; ++j)
-#pragma unroll
-        for (int ii = 0; ii < CH; ++ii) s[ii] = fma(x[j], M[j * KP + i0 + ii], s[ii]);
-#pragma unroll
-      for (int ii = 0; ii < CH; ++ii)
-        if (i0 + ii < k) Out[r * KP + i0 + ii] += s[ii];
+      for (int w = 0; w < VEC; ++w) s[q * VEC + w] = fma(xj, v.v[w], s[q * VEC + w]);
     }
   }
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii)
+    if (i0 + ii < k) Out[r * KP + i0 + ii] += s[ii];
 }
 
 // M = G + G^T (KP x KP).
@@ -194,12 +233,11 @@ hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, cons
                            int64_t rows, int k, int KP, T eps, T* gN, T* gD, T* gX,
                            hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)cdiv(rows, 256);
   switch (KP) {
 #define CASE(K)                                                                               \
   case K:                                                                                     \
-    mu_adjoint_rows_kernel<T, K><<<blocks, 256, 0, st>>>(X, Xn, N, G, gXn, rows, k, eps, gN, \
-                                                          gD, gX);                            \
+    mu_adjoint_rows_kernel<T, K><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0, st>>>(   \
+        X, Xn, N, G, gXn, rows, k, eps, gN, gD, gX);                                          \
     break;
     CASE(16) CASE(32) CASE(48) CASE(64)
 #undef CASE
@@ -212,10 +250,13 @@ template <typename T>
 hipError_t rowmm_add(const T* X, const T* M, int64_t rows, int k, int KP, T* Out,
                      hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)cdiv(rows, 256);
   switch (KP) {
-#define CASE(K)                                                                 \
-  case K: rowmm_add_kernel<T, K><<<blocks, 256, 0, st>>>(X, M, rows, k, Out); break;
+#define CASE(K)                                                                              \
+  case K:                                                                                    \
+    rowmm_add_kernel<T, K><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0, st>>>(X, M,     \
+                                                                                  rows, k,   \
+                                                                                  Out);      \
+    break;
     CASE(16) CASE(32) CASE(48) CASE(64)
 #undef CASE
     default: return hipErrorInvalidValue;

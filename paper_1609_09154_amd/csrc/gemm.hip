@@ -449,10 +449,10 @@ template <typename T> static constexpr Shape tn_shape(int NT) {
 constexpr int WAVES = 4;  // waves per workgroup of the product kernels
 
 // Split the reduction until the grid has about one workgroup per CU, keeping
-// every split at least 4096 long.
+// every split at least 256 long.
 static int64_t auto_splits(int64_t wgs, int64_t K) {
   int64_t s = 1;
-  while (wgs * s < 256 && K / (2 * s) >= 4096 && s < MAX_PRODUCT_SPLITS) s *= 2;
+  while (wgs * s < 256 && K / (2 * s) >= 256 && s < MAX_PRODUCT_SPLITS) s *= 2;
   return s;
 }
 

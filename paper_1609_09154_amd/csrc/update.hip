@@ -1,9 +1,10 @@
-// Local update computations (LUC) of Algorithm 1 on the row layout: one
-// thread owns one row x of the factor being updated (a row of W, or a row of
-// H^T, i.e. a column of H) and keeps it in registers; the k x k Gram G of the
-// fixed factor is read with wave-uniform (scalar) loads. Rows are independent
-// (Section 5: rows of W and columns of H can be updated in parallel), so the
-// grid is simply one thread per row.
+// Local update computations (LUC) of Algorithm 1 on the row layout: a row x
+// of the factor being updated (a row of W, or a row of H^T, i.e. a column of
+// H) is independent of every other row (Section 5: rows of W and columns of H
+// can be updated in parallel). HALS gives each row one thread, which keeps x
+// in registers and reads the k x k Gram G of the fixed factor with
+// wave-uniform loads; MU splits each row's outputs over several threads with
+// G staged in LDS.
 //
 //   MU   (Section 4.1, Eq. (3)):  x_i <- x_i p_i / ((x G)_i + eps), all i at once
 //   HALS (Section 4.2, Eq. (5)):  i = 1..k in order, newest values:
@@ -41,36 +42,6 @@ __device__ __forceinline__ void store_row(T* __restrict__ dst, const T (&x)[KP])
 }
 
 template <typename T, int KP>
-__global__ __launch_bounds__(256) void mu_rows_kernel(T* __restrict__ X, const T* __restrict__ P,
-                                                      const T* __restrict__ G, int64_t rows,
-                                                      int k, T eps) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  T x[KP];
-  load_row<T, KP>(X + r * KP, x);
-  const T* pr = P + r * KP;
-  T* xr = X + r * KP;
-  constexpr int CH = 16;
-#pragma unroll
-  for (int i0 = 0; i0 < KP; i0 += CH) {
-    if (i0 < k) {
-      T d[CH];
-#pragma unroll
-      for (int ii = 0; ii < CH; ++ii) d[ii] = T(0);
-#pragma unroll
-      for (int j = 0; j < KP; ++j)
-#pragma unroll
-        for (int ii = 0; ii < CH; ++ii) d[ii] = fma(x[j], G[j * KP + i0 + ii], d[ii]);
-#pragma unroll
-      for (int ii = 0; ii < CH; ++ii) {
-        const int i = i0 + ii;
-        if (i < k) xr[i] = x[i] * pr[i] / (d[ii] + eps);
-      }
-    }
-  }
-}
-
-template <typename T, int KP>
 __global__ __launch_bounds__(256) void hals_rows_kernel(T* __restrict__ X,
                                                         const T* __restrict__ P,
                                                         const T* __restrict__ G, int64_t rows,
@@ -100,6 +71,62 @@ __global__ __launch_bounds__(256) void hals_rows_kernel(T* __restrict__ X,
 // (column tid of a [KP][64] array, so accesses are bank-conflict free) and
 // runtime loops, instead of fully unrolled register code. G is symmetric, so
 // G[i*KP + j] is read along j with uniform loads.
+// MU with several threads per row: the KP outputs of a row are split over
+// TPR threads of RPT outputs each, and a block of 256 threads covers 256 / TPR
+// rows. G and the block's rows of x are staged in LDS first (so the in-place
+// update of X reads nothing a lane has already written) and read with
+// 16-byte loads.
+template <int KP> struct RowSplit {
+  static constexpr int TPR = KP == 48 ? 4 : KP / 8;
+  static constexpr int RPT = KP / TPR;
+  static constexpr int ROWS = 256 / TPR;
+};
+
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void mu_rows_tpr_kernel(T* __restrict__ X,
+                                                          const T* __restrict__ P,
+                                                          const T* __restrict__ G, int64_t rows,
+                                                          int k, T eps) {
+  constexpr int TPR = RowSplit<KP>::TPR, RPT = RowSplit<KP>::RPT, ROWS = RowSplit<KP>::ROWS;
+  constexpr int VEC = Tr<T>::VEC;
+  static_assert(RPT % VEC == 0, "16-byte reads of G");
+  constexpr int XLD = KP + VEC;
+  __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
+  __shared__ __attribute__((aligned(16))) T Xs[ROWS * XLD];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) Gs[e] = G[e];
+  const int64_t rb = (int64_t)blockIdx.x * ROWS;
+  for (int e = threadIdx.x; e < ROWS * KP; e += 256) {
+    const int lr = e / KP, j = e % KP;
+    Xs[lr * XLD + j] = rb + lr < rows ? X[(rb + lr) * KP + j] : T(0);
+  }
+  __syncthreads();
+  const int lr = threadIdx.x / TPR;
+  const int64_t r = rb + lr;
+  if (r >= rows) return;  // no barrier below
+  const int i0 = (threadIdx.x % TPR) * RPT;
+  const T* xs = &Xs[lr * XLD];
+  T d[RPT];
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) d[ii] = T(0);
+#pragma unroll 8
+  for (int j = 0; j < KP; ++j) {
+    const T xj = xs[j];
+#pragma unroll
+    for (int q = 0; q < RPT / VEC; ++q) {
+      const V16<T> v = load16<T>(&Gs[j * KP + i0 + q * VEC]);
+#pragma unroll
+      for (int w = 0; w < VEC; ++w) d[q * VEC + w] = fma(xj, v.v[w], d[q * VEC + w]);
+    }
+  }
+  const T* pr = P + r * KP;
+  T* xr = X + r * KP;
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) {
+    const int i = i0 + ii;
+    if (i < k) xr[i] = xs[i] * pr[i] / (d[ii] + eps);
+  }
+}
+
 constexpr int LDS_ROWS = 64;
 template <typename T>
 __global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(T* __restrict__ X,
@@ -156,8 +183,8 @@ template <typename T>
 hipError_t mu_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, T eps,
                    hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)cdiv(rows, 256);
-  KP_SWITCH(KP, (mu_rows_kernel<T, KPc><<<blocks, 256, 0, st>>>(X, P, G, rows, k, eps)),
+  KP_SWITCH(KP, (mu_rows_tpr_kernel<T, KPc><<<(unsigned)cdiv(rows, RowSplit<KPc>::ROWS), 256,
+                                               0, st>>>(X, P, G, rows, k, eps)),
             (mu_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
                 X, P, G, rows, k, KP, eps)));
   return NMF_LAUNCH_CHECK();

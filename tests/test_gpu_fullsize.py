@@ -18,7 +18,7 @@ import scipy.sparse
 
 import oracle
 import paper_1609_09154_amd as nmf
-from synth import erdos_renyi_csr, init_factors, planted_dense_torch
+from synth import erdos_renyi_csr, init_factors, planted_dense, planted_dense_torch
 from tests.gpu_util import host, rel_diff, step
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
@@ -213,3 +213,43 @@ def test_bf16_131072x65536_k100_hals_one_iteration_full_parity():
           "max |dW|/max|W| %.2e, max |dH|/max|H| %.2e" % (errs, e_ref, d_e, d_w, d_h))
     assert d_e <= 1e-4
     assert d_w <= 1e-2 and d_h <= 1e-2
+
+
+def test_mu_unrolled_8192x4096_k64_T50_gradient_full_parity():
+    """Differentiation workload at full size: A = W0 H0 + |N(0, 0.01)| with
+    planted rank 64 (8192 x 4096, float32), k = 64, 50 unrolled MU
+    iterations, checkpoints every 10; loss <GW, W_T> + <GH, H_T>. The oracle's
+    FP64 reference gradient runs on the same float32 inputs."""
+    import torch
+
+    m, n, k, T, every = 8192, 4096, 64, 50, 10
+    dev = torch.device("cuda:0")
+    A = planted_dense(m, n, 64, sigma=0.01, seed=1609).astype(np.float32)
+    W0, H0 = init_factors(m, n, k, seed=9154)
+    W0 = W0.astype(np.float32)
+    H0 = H0.astype(np.float32)
+    from synth import uniform
+
+    GW = (uniform((m, k), seed=11) - 0.5).astype(np.float32)
+    GH = (uniform((k, n), seed=12) - 0.5).astype(np.float32)
+    step("fullsize autograd: forward + backward on the GPU")
+    Ad = torch.from_numpy(A).to(dev)
+    W, H, ck = nmf.nmf_mu_unrolled_forward(Ad, torch.from_numpy(W0).to(dev),
+                                           torch.from_numpy(H0).to(dev), T, ckpt_every=every)
+    gA, gW0, gH0 = nmf.nmf_mu_unrolled_backward(Ad, ck, torch.from_numpy(GW).to(dev),
+                                                torch.from_numpy(GH).to(dev), T,
+                                                ckpt_every=every)
+    torch.cuda.synchronize()
+    step("fullsize autograd: oracle FP64 reference gradient")
+    A64 = A.astype(np.float64)
+    Wr, Hr, _ = oracle.mu_unrolled_forward(A64, W0.astype(np.float64), H0.astype(np.float64), T)
+    rA, rW, rH = oracle.mu_unrolled_vjp(A64, W0.astype(np.float64), H0.astype(np.float64), T,
+                                        GW.astype(np.float64), GH.astype(np.float64))
+
+    def mr(a, b):
+        return float(np.max(np.abs(host(a).astype(np.float64) - b)) / np.abs(b).max())
+
+    errs = [mr(W, Wr), mr(H, Hr), mr(gA, rA), mr(gW0, rW), mr(gH0, rH)]
+    print("fullsize autograd FP32 vs FP64 oracle: W_T %.2e H_T %.2e dA %.2e dW0 %.2e dH0 %.2e"
+          % tuple(errs))
+    assert max(errs) <= 1e-3
