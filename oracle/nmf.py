@@ -226,6 +226,42 @@ def relative_error(A, W, H, normA_sq: float | None = None) -> float:
     return float(np.sqrt(max(objective_sq(A, W, H), 0.0) / normA_sq))
 
 
+# --- stationarity: the projected gradient (Section 6.2) --------------------
+#
+# Section 6.2 names the projected gradient, beside the relative error, as a
+# measure of the factors' quality and as a stopping test, without a formula;
+# the definition below is the usual one for bound-constrained problems (Lin's,
+# also used by the NMF survey the paper cites there). For
+# f(W, H) = 1/2 ||A - W H||_F^2:
+#     grad_W f = W (H H^T) - A H^T,      grad_H f = (W^T W) H - W^T A,
+# and the projection onto the feasible directions at x >= 0 keeps a gradient
+# entry where x > 0 and only its negative part where x = 0. The norm is zero
+# exactly at the stationary points of the constrained problem (the KKT
+# conditions of Section 4.3, Eq. (7), for both factors at once).
+
+def gradients(A, W, H):
+    """(grad_W, grad_H) of 1/2 ||A - W H||_F^2."""
+    W = _f64(W)
+    H = _f64(H)
+    gW = W @ gram_fixed_H(H) - product_AHt(A, H)
+    gH = gram_fixed_W(W) @ H - product_WtA(A, W)
+    return gW, gH
+
+
+def projected_gradient_sq(X, G) -> float:
+    """Sum of squares of the projected gradient G at X >= 0."""
+    X = _f64(X)
+    G = _f64(G)
+    P = np.where(X > 0, G, np.minimum(G, 0.0))
+    return float(np.sum(P * P))
+
+
+def projected_gradient_norm(A, W, H) -> float:
+    """||(proj grad_W f, proj grad_H f)||_F at (W, H)."""
+    gW, gH = gradients(A, W, H)
+    return float(np.sqrt(projected_gradient_sq(W, gW) + projected_gradient_sq(H, gH)))
+
+
 # --- Algorithm 1 ---------------------------------------------------------
 
 def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
@@ -275,3 +311,32 @@ def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
         if track_error:
             errs.append(relative_error(A, W, H, normA_sq))
     return W, H, errs
+
+
+def run_until(A, k: int, algo: str, max_iters: int, W0, H0, stop: str, tol: float,
+              eps: float = MU_EPS, max_pivots=None):
+    """Algorithm 1 with a stopping criterion (Section 6.2: the iteration
+    count together with a tolerance on a quality metric). After iteration t
+    it stops when
+      stop == "pgrad":  ||proj grad f(W_t, H_t)|| <= tol ||proj grad f(W_0, H_0)||
+      stop == "relerr": e_{t-1} - e_t < tol e_{t-1}  (relative error improvement)
+    or when t == max_iters. Returns (W, H, rel_err[0..t], pg_ratio[0..t], t)."""
+    if stop not in ("pgrad", "relerr"):
+        raise ValueError("unknown stopping metric %r" % stop)
+    W = _f64(W0).copy()
+    H = _f64(H0).copy()
+    normA_sq = _norm_sq(A)
+    errs = [relative_error(A, W, H, normA_sq)]
+    pg0 = projected_gradient_norm(A, W, H)
+    ratios = [1.0]
+    t = 0
+    while t < max_iters:
+        W, H, _ = run(A, k, algo, 1, W, H, eps, max_pivots, track_error=False)
+        t += 1
+        errs.append(relative_error(A, W, H, normA_sq))
+        ratios.append(projected_gradient_norm(A, W, H) / pg0)
+        if stop == "pgrad" and ratios[-1] <= tol:
+            break
+        if stop == "relerr" and errs[-2] - errs[-1] < tol * errs[-2]:
+            break
+    return W, H, errs, ratios, t
