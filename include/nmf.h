@@ -71,6 +71,16 @@ typedef enum { NMF_MU = 0, NMF_HALS = 1, NMF_ABPP = 2 } nmf_algo;
 typedef enum { NMF_F64 = 0, NMF_F32 = 1, NMF_BF16 = 2 } nmf_dtype;
 
 typedef enum {
+  NMF_STOP_ITERS = 0,  /* run exactly opts->iters iterations               */
+  NMF_STOP_PGRAD = 1,  /* also stop after iteration t once the projected   */
+                       /* gradient (see nmf_projected_gradient_sq) has     */
+                       /* fallen to ||pg(W_t,H_t)|| <= tol ||pg(W_0,H_0)|| */
+  NMF_STOP_RELERR = 2  /* also stop after iteration t once the relative    */
+                       /* error improves by less than tol: e_{t-1} - e_t < */
+                       /* tol e_{t-1} (needs opts->objective)              */
+} nmf_stop;
+
+typedef enum {
   NMF_OBJ_NONE = 0,    /* do not evaluate the objective                    */
   NMF_OBJ_DIRECT = 1   /* ||A - W H||_F from the residual: dense A forms   */
                        /* A - W H tile by tile; CSR A sums (a - wh)^2 -    */
@@ -93,6 +103,11 @@ typedef struct {
                      /* products then stream A row by row); -1 never does.   */
                      /* NMF_BF16 A always needs the copy: -1 is rejected and */
                      /* a copy that does not fit returns NMF_ENOMEM          */
+  double tol;        /* tolerance of the stopping test (>= 0)                */
+  int stop;          /* nmf_stop. Section 6.2: the iteration count together  */
+                     /* with a tolerance on a quality metric. With a metric, */
+                     /* iters is the cap and the call synchronises once per  */
+                     /* iteration to read it                                 */
 } nmf_opts;
 
 typedef struct {
@@ -105,13 +120,16 @@ typedef struct {
   long long bpp_pivots; /* ABPP: total passive-set solves over all RHS       */
   double ms_mm_aht;  /* the A H^T part of ms_mm (one launch group per iter.) */
   double ms_mm_wta;  /* the W^T A part of ms_mm                              */
+  long long iters_done; /* iterations performed (< iters when a stop fired)  */
+  double pgrad_ratio;   /* NMF_STOP_PGRAD: ||pg(W,H)|| / ||pg(W_0,H_0)|| at the */
+                        /* returned factors; otherwise NaN                    */
 } nmf_stats;
 
 typedef struct nmf_ctx nmf_ctx;
 
 /* Fills *opts with the defaults: MU, 0 iterations, eps_mu 1e-16,
  * max_pivots 0 (= 50 k), no objective, no timers, no input check,
- * transpose_a 0. */
+ * transpose_a 0, tol 0, stop NMF_STOP_ITERS. */
 void nmf_default_opts(nmf_opts* opts);
 
 /* Creates a context bound to HIP device `device` and the HIP stream
@@ -135,6 +153,7 @@ const char* nmf_last_error(const nmf_ctx* ctx);
  *           only takes its starting passive sets from it), the final W.
  *   H       k x n (leading dimension n): initial H on entry, final H on return.
  *   rel_err host array of iters+1 doubles or NULL; requires opts->objective.
+ *           Entries after the last iteration performed (a stop fired) are NaN.
  *   stats   host pointer or NULL.
  * HALS returns W with unit-norm nonzero columns, the scale carried by H. */
 nmf_status nmf_dense(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
@@ -232,6 +251,17 @@ nmf_status nmf_csr_relerr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
                           const int64_t* rowptr, const int32_t* colidx,
                           const float* vals, int k, const float* W,
                           const float* Ht, double* out);
+
+/* Stationarity measure of Section 6.2 for one factor: with X rows x k (the
+ * rows of W, or of H^T), P = A F (rows x k, the product with the other
+ * factor) and G = F^T F (k x k), the gradient of 1/2 ||A - W H||_F^2 in X is
+ * X G - P; its projection onto the feasible directions keeps an entry where
+ * x > 0 and only its negative part where x = 0. *out (host) receives the sum
+ * of the squared projected entries (accumulated in double); the norm of
+ * nmf_opts' NMF_STOP_PGRAD test is the square root of the W and H sums. */
+nmf_status nmf_projected_gradient_sq(nmf_ctx* ctx, nmf_dtype dtype, int64_t rows,
+                                     int k, const void* X, const void* P,
+                                     const void* G, double* out);
 
 /* ---- Differentiation through unrolled MU iterations -------------------------
  * The map (A, W_0, H_0) -> (W_T, H_T) of T iterations of Algorithm 1 with the

@@ -17,6 +17,7 @@ from ._lib import (NMF_ABPP, NMF_BF16, NMF_F32, NMF_F64, NMF_HALS, NMF_MU, NMF_O
 
 __all__ = ["Context", "NMFError", "nmf_dense", "nmf_csr", "nmf_gram", "nmf_dense_AF",
            "nmf_mu_unrolled_forward", "nmf_mu_unrolled_backward", "mu_unrolled",
+           "nmf_projected_gradient_sq",
            "nmf_dense_AtF", "nmf_csr_AF", "nmf_csr_transpose", "nmf_update",
            "nmf_hals_normalize", "nmf_dense_relerr", "nmf_csr_relerr", "library_path"]
 
@@ -114,12 +115,25 @@ def _ctx(ctx, device) -> Context:
     return c
 
 
+def _stop_opts(stop, tol):
+    code = _lib.STOPS["iters" if stop is None else stop]
+    return dict(stop=code, tol=float(tol))
+
+
+def _errs(errs, stats):
+    if errs is None:
+        return None
+    return list(errs)[: int(stats.iters_done) + 1]
+
+
 def nmf_dense(A, W, H, algo="hals", iters=10, objective=True, eps_mu=1e-16, max_pivots=0,
-              timers=False, check_input=False, transpose_a=True, ctx=None):
+              timers=False, check_input=False, transpose_a=True, stop=None, tol=0.0, ctx=None):
     """Algorithm 1 on dense A (m x n); W (m x k) and H (k x n) are updated in
     place. transpose_a=False keeps the library from holding a transposed
     copy of A. A may be bfloat16 (then W and H are float32, the products run
-    on the BF16 matrix cores). Returns (rel_err list or None, stats dict)."""
+    on the BF16 matrix cores). stop = "pgrad" or "relerr" adds the tolerance
+    test of nmf_opts (iters is then the cap). Returns (rel_err list or None,
+    stats dict); the list ends at the last iteration performed."""
     torch = _torch()
     m, n = A.shape
     k = W.shape[1]
@@ -131,18 +145,19 @@ def nmf_dense(A, W, H, algo="hals", iters=10, objective=True, eps_mu=1e-16, max_
     o = default_opts(algo=algo, iters=iters, eps_mu=eps_mu, max_pivots=max_pivots,
                      objective=NMF_OBJ_DIRECT if objective else NMF_OBJ_NONE,
                      timers=1 if timers else 0, check_input=1 if check_input else 0,
-                     transpose_a=0 if transpose_a else -1)
+                     transpose_a=0 if transpose_a else -1, **_stop_opts(stop, tol))
     errs = (ctypes.c_double * (iters + 1))() if objective else None
     stats = NmfStats()
     rc = _lib.lib().nmf_dense(c.handle, _dtype_code(A), m, n, pa, A.stride(0), k, ctypes.byref(o),
                             pw, ph, errs, ctypes.byref(stats))
     c.check(rc)
     del torch
-    return (list(errs) if errs is not None else None), stats.as_dict()
+    return _errs(errs, stats), stats.as_dict()
 
 
 def nmf_csr(rowptr, colidx, vals, n, W, H, algo="abpp", iters=10, objective=True,
-            eps_mu=1e-16, max_pivots=0, timers=False, check_input=False, ctx=None):
+            eps_mu=1e-16, max_pivots=0, timers=False, check_input=False, stop=None, tol=0.0,
+            ctx=None):
     """Algorithm 1 on CSR A (float32); W (m x k), H (k x n) float32, in place."""
     torch = _torch()
     m = rowptr.numel() - 1
@@ -155,13 +170,14 @@ def nmf_csr(rowptr, colidx, vals, n, W, H, algo="abpp", iters=10, objective=True
     c = _ctx(ctx, W.device.index or 0)
     o = default_opts(algo=algo, iters=iters, eps_mu=eps_mu, max_pivots=max_pivots,
                      objective=NMF_OBJ_DIRECT if objective else NMF_OBJ_NONE,
-                     timers=1 if timers else 0, check_input=1 if check_input else 0)
+                     timers=1 if timers else 0, check_input=1 if check_input else 0,
+                     **_stop_opts(stop, tol))
     errs = (ctypes.c_double * (iters + 1))() if objective else None
     stats = NmfStats()
     rc = _lib.lib().nmf_csr(c.handle, m, n, nnz, *args, k, ctypes.byref(o), pw, ph, errs,
                           ctypes.byref(stats))
     c.check(rc)
-    return (list(errs) if errs is not None else None), stats.as_dict()
+    return _errs(errs, stats), stats.as_dict()
 
 
 def nmf_gram(X, ctx=None):
@@ -279,6 +295,20 @@ def nmf_dense_relerr(A, W, Ht, ctx=None):
     c = _ctx(ctx, A.device.index or 0)
     c.check(_lib.lib().nmf_dense_relerr(c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0),
                                       k, _dev(W, "W"), _dev(Ht, "Ht"), ctypes.byref(out)))
+    return out.value
+
+
+def nmf_projected_gradient_sq(X, P, G, ctx=None):
+    """Sum of squares of the projected gradient in the factor whose rows are
+    X (rows x k), given its product P (rows x k) and the Gram G (k x k) of
+    the other factor."""
+    rows, k = X.shape
+    _dev(P, "P", dtype=X.dtype, shape=(rows, k))
+    _dev(G, "G", dtype=X.dtype, shape=(k, k))
+    out = ctypes.c_double(0.0)
+    c = _ctx(ctx, X.device.index or 0)
+    c.check(_lib.lib().nmf_projected_gradient_sq(c.handle, _dtype_code(X), rows, k, _dev(X, "X"),
+                                               _dev(P, "P"), _dev(G, "G"), ctypes.byref(out)))
     return out.value
 
 

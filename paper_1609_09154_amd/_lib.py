@@ -25,10 +25,14 @@ _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
+STOPS = {"iters": 0, "pgrad": 1, "relerr": 2}
+
+
 class NmfOpts(ctypes.Structure):
     _fields_ = [("algo", _int), ("iters", _int), ("eps_mu", ctypes.c_double),
                 ("max_pivots", _int), ("objective", _int), ("timers", _int),
-                ("check_input", _int), ("transpose_a", _int)]
+                ("check_input", _int), ("transpose_a", _int), ("tol", ctypes.c_double),
+                ("stop", _int)]
 
 
 class NmfStats(ctypes.Structure):
@@ -36,7 +40,8 @@ class NmfStats(ctypes.Structure):
                 ("ms_luc", ctypes.c_double), ("ms_gram", ctypes.c_double),
                 ("ms_obj", ctypes.c_double), ("ms_setup", ctypes.c_double),
                 ("bpp_pivots", ctypes.c_longlong), ("ms_mm_aht", ctypes.c_double),
-                ("ms_mm_wta", ctypes.c_double)]
+                ("ms_mm_wta", ctypes.c_double), ("iters_done", ctypes.c_longlong),
+                ("pgrad_ratio", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -63,6 +68,7 @@ SIGNATURES = {
     "nmf_hals_normalize": (_int, [_vp, _int, _i64, _i64, _int, _vp, _vp, _vp, _vp]),
     "nmf_dense_relerr": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _vp, _vp, _dp]),
     "nmf_csr_relerr": (_int, [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _int, _vp, _vp, _dp]),
+    "nmf_projected_gradient_sq": (_int, [_vp, _int, _i64, _int, _vp, _vp, _vp, _dp]),
     "nmf_mu_ckpt_elems": (_i64, [_i64, _i64, _int, _int, _int]),
     "nmf_mu_unrolled_forward": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _int,
                                        ctypes.c_double, _int, _vp, _vp, _vp]),

@@ -121,6 +121,11 @@ nmf_status check_opts(nmf_ctx* ctx, const nmf_opts* o, int k, bool have_relerr) 
     return fail(ctx, NMF_EINVAL, "rel_err requested with objective NMF_OBJ_NONE");
   if (o->algo == NMF_MU && !(o->eps_mu >= 0.0)) return fail(ctx, NMF_EINVAL, "eps_mu must be >= 0");
   if (o->algo == NMF_ABPP && k > 64) return fail(ctx, NMF_EINVAL, "ABPP supports k <= 64");
+  if (!(o->tol >= 0.0)) return fail(ctx, NMF_EINVAL, "tol must be >= 0");
+  if (o->stop < NMF_STOP_ITERS || o->stop > NMF_STOP_RELERR)
+    return fail(ctx, NMF_EINVAL, "unknown stopping test");
+  if (o->stop == NMF_STOP_RELERR && o->objective == NMF_OBJ_NONE)
+    return fail(ctx, NMF_EINVAL, "NMF_STOP_RELERR needs the objective");
   return NMF_OK;
 }
 
@@ -171,9 +176,16 @@ template <typename T> struct Work {
   T *Wt, *Hk;  // W^T (KP x m) and H (KP x n): the rank side of the dense products
   double* ginv;  // KP x KP, ABPP
   double *obj_part, *relerr, *normA;
+  double *pg_part, *pg_val;  // projected-gradient partials; [0] H half, [1] W half
   int* status;
   unsigned long long* pivots;
   int64_t obj_np;
+};
+
+// Outcome of a call with a stopping test.
+struct StopInfo {
+  long long iters_done = 0;
+  double ratio = NAN;
 };
 
 // status points at 4 device ints: [0] ABPP flags, [1] input check, [2] G^-1 ok.
@@ -205,7 +217,7 @@ nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part) {
 // Workspace offsets for an AU-NMF call on an m x n problem.
 template <typename T>
 size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_t extra_part,
-                 Carve& cv, size_t off[15]) {
+                 Carve& cv, size_t off[17]) {
   const int64_t ps_p = std::max(nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
                                 nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n));
   const int64_t ps_r = nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m);
@@ -228,11 +240,13 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[12] = cv.take<T>(m * KP);
   off[13] = cv.take<T>(n * KP);
   off[14] = cv.take<double>(KP * KP);
+  off[15] = cv.take<double>(nmfk::pgrad_partials(std::max(m, n)));
+  off[16] = cv.take<double>(4);
   return cv.off;
 }
 
 template <typename T>
-Work<T> bind_work(nmf_ctx* ctx, const size_t off[15], int64_t obj_np) {
+Work<T> bind_work(nmf_ctx* ctx, const size_t off[17], int64_t obj_np) {
   Work<T> w;
   w.W = at<T>(ctx, off[0]);
   w.Ht = at<T>(ctx, off[1]);
@@ -250,6 +264,8 @@ Work<T> bind_work(nmf_ctx* ctx, const size_t off[15], int64_t obj_np) {
   w.Wt = at<T>(ctx, off[12]);
   w.Hk = at<T>(ctx, off[13]);
   w.ginv = at<double>(ctx, off[14]);
+  w.pg_part = at<double>(ctx, off[15]);
+  w.pg_val = at<double>(ctx, off[16]);
   w.obj_np = obj_np;
   return w;
 }
@@ -401,17 +417,52 @@ nmf_status norm_sq_A(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, Work
   return NMF_OK;
 }
 
-// Algorithm 1 on the prepared workspace.
+// Squared projected gradient of one factor (rows of X against its product P
+// and Gram G) into w.pg_val[slot].
+template <typename T>
+nmf_status pg_half(nmf_ctx* ctx, const T* X, const T* P, const T* G, int64_t rows, int k,
+                   int KP, Work<T>& w, int slot) {
+  HIP_TRY(nmfk::pgrad_sq<T>(X, P, G, rows, k, KP, w.pg_part, ctx->stream));
+  HIP_TRY(nmfk::finish_relerr<T>(w.pg_part, nmfk::pgrad_blocks<T>(rows, KP), (const T*)nullptr,
+                                 (const T*)nullptr, 0, (const double*)nullptr, w.pg_val + slot,
+                                 ctx->stream));
+  return NMF_OK;
+}
+
+nmf_status read_doubles(nmf_ctx* ctx, const double* d, double* h, int count) {
+  HIP_TRY(hipMemcpyAsync(h, d, sizeof(double) * count, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return NMF_OK;
+}
+
+// Algorithm 1 on the prepared workspace. With a stopping test (Section 6.2)
+// the loop reads the metric once per iteration: the projected gradient at
+// (W_t, H_t) is its H half, formed right after the H update from that step's
+// S = W^T W and R = A^T W, plus its W half, formed at the start of the next
+// iteration from Q = H H^T and P = A H^T before W changes.
 template <typename T>
 nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
-                      const nmf_opts* o, Work<T>& w, bool want_obj, Timers& tm) {
+                      const nmf_opts* o, Work<T>& w, bool want_obj, Timers& tm,
+                      StopInfo& si) {
   hipStream_t st = ctx->stream;
   nmf_status s = NMF_OK;
 #define RUN(x) do { s = (x); if (s != NMF_OK) return s; } while (0)
+  const bool pgstop = o->stop == NMF_STOP_PGRAD;
+  const bool errstop = o->stop == NMF_STOP_RELERR;
+  si.iters_done = o->iters;
+  si.ratio = NAN;
+  double pg0 = 0.0;
   if (want_obj) {
     tm.mark(PH_OBJ);
     RUN(norm_sq_A<T>(ctx, pb, m, n, w));
     RUN(objective<T>(ctx, pb, m, n, k, KP, w, 0));
+  }
+  if (pgstop) {
+    // H half at the initial factors
+    tm.mark(PH_OBJ);
+    RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
+    RUN(product_AtF<T>(ctx, pb, m, n, w.W, nullptr, k, KP, w.R, w.part));
+    RUN(pg_half<T>(ctx, w.Ht, w.R, w.S, n, k, KP, w, 0));
   }
   // Transposed factor copies for the dense products (read with 16-byte loads,
   // so their rows must stay 16-byte aligned).
@@ -424,6 +475,19 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     RUN(gram<T>(ctx, w.Ht, n, KP, w.Q, w.part));
     tm.mark(PH_MM);
     RUN(product_AF<T>(ctx, pb, m, n, w.Ht, tH ? w.Hk : nullptr, k, KP, w.P, w.part));
+    if (pgstop) {
+      tm.mark(PH_OBJ);
+      RUN(pg_half<T>(ctx, w.W, w.P, w.Q, m, k, KP, w, 1));
+      double h[2];
+      RUN(read_doubles(ctx, w.pg_val, h, 2));
+      const double pg = std::sqrt(std::max(h[0] + h[1], 0.0));
+      if (t == 0) pg0 = pg;
+      si.ratio = pg0 > 0.0 ? pg / pg0 : 0.0;
+      if ((t > 0 || pg0 == 0.0) && si.ratio <= o->tol) {
+        si.iters_done = t;
+        break;
+      }
+    }
     tm.mark(PH_LUC);
     RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv));
     // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
@@ -439,9 +503,31 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     tm.mark(PH_LUC);
     RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots, w.ginv));
     if (tH && t + 1 < o->iters) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
+    if (pgstop) {
+      tm.mark(PH_OBJ);
+      RUN(pg_half<T>(ctx, w.Ht, w.R, w.S, n, k, KP, w, 0));
+    }
     if (want_obj) {
       tm.mark(PH_OBJ);
       RUN(objective<T>(ctx, pb, m, n, k, KP, w, t + 1));
+    }
+    if (errstop) {
+      double e[2];
+      RUN(read_doubles(ctx, w.relerr + t, e, 2));
+      if (e[0] - e[1] < o->tol * e[0]) {
+        si.iters_done = t + 1;
+        break;
+      }
+    }
+    if (pgstop && t + 1 == o->iters) {
+      // the W half at the returned factors, for the final ratio
+      tm.mark(PH_OBJ);
+      RUN(gram<T>(ctx, w.Ht, n, KP, w.Q, w.part));
+      RUN(product_AF<T>(ctx, pb, m, n, w.Ht, nullptr, k, KP, w.P, w.part));
+      RUN(pg_half<T>(ctx, w.W, w.P, w.Q, m, k, KP, w, 1));
+      double h[2];
+      RUN(read_doubles(ctx, w.pg_val, h, 2));
+      si.ratio = pg0 > 0.0 ? std::sqrt(std::max(h[0] + h[1], 0.0)) / pg0 : 0.0;
     }
   }
   tm.mark(PH_END);
@@ -452,7 +538,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
 template <typename T>
 nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_obj,
                        double* rel_err, nmf_stats* stats, Timers& tm, hipEvent_t t0,
-                       hipEvent_t t1) {
+                       hipEvent_t t1, const StopInfo& si) {
   long long piv = 0;
   const bool need_status = o->algo == NMF_ABPP || o->check_input;
   if (need_status) {
@@ -460,8 +546,9 @@ nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_ob
     if (s != NMF_OK) return s;
   }
   if (rel_err && want_obj) {
-    HIP_TRY(hipMemcpyAsync(rel_err, w.relerr, sizeof(double) * (o->iters + 1),
+    HIP_TRY(hipMemcpyAsync(rel_err, w.relerr, sizeof(double) * (si.iters_done + 1),
                            hipMemcpyDeviceToHost, ctx->stream));
+    for (int t = (int)si.iters_done + 1; t <= o->iters; ++t) rel_err[t] = NAN;
   }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
@@ -471,6 +558,8 @@ nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_ob
     stats->ms_total = ms;
     tm.collect(stats);
     stats->bpp_pivots = piv;
+    stats->iters_done = si.iters_done;
+    stats->pgrad_ratio = si.ratio;
   }
   if (rel_err || stats) HIP_TRY(hipStreamSynchronize(ctx->stream));
   return NMF_OK;
@@ -527,7 +616,7 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, const uint
   const int64_t obj_np = std::max(nmfk::residual_partials<T>(m, n), nmfk::sumsq_partials<T>(m, n));
   const Bf16Plan bp = Ab ? bf16_plan(m, n, KP) : Bf16Plan{0, 0};
   Carve cv;
-  size_t off[15];
+  size_t off[17];
   plan_work<T>(m, n, KP, o->iters, obj_np, bp.part_elems, cv, off);
   const size_t ofb = cv.take<uint16_t>(Ab ? bp.fb_elems : 0);
   nmf_status s = ensure_ws(ctx, cv.off);
@@ -567,12 +656,13 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, const uint
   } else if (o->iters > 0 && o->transpose_a == 0) {
     if ((s = transposed_copy<T>(ctx, A, lda, m, n, m, &pb.At)) != NMF_OK) return s;
   }
-  s = run_au_nmf<T>(ctx, pb, m, n, k, KP, o, w, want_obj, tm);
+  StopInfo si;
+  s = run_au_nmf<T>(ctx, pb, m, n, k, KP, o, w, want_obj, tm, si);
   if (stats) HIP_TRY(hipEventRecord(t1, st));
   if (s == NMF_OK) {
     HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
     HIP_TRY(nmfk::transpose_out<T>(w.Ht, k, n, KP, H, st));
-    s = finish_call<T>(ctx, o, w, want_obj, rel_err, stats, tm, t0, t1);
+    s = finish_call<T>(ctx, o, w, want_obj, rel_err, stats, tm, t0, t1, si);
   }
   if (t0) hipEventDestroy(t0);
   if (t1) hipEventDestroy(t1);
@@ -588,6 +678,8 @@ extern "C" {
 
 void nmf_default_opts(nmf_opts* o) {
   if (!o) return;
+  o->tol = 0.0;
+  o->stop = NMF_STOP_ITERS;
   o->algo = NMF_MU;
   o->iters = 0;
   o->eps_mu = 1e-16;
@@ -692,7 +784,7 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   const bool want_obj = opts->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max<int64_t>(nmfk::csr_residual_partials(m), 1024);
   Carve cv;
-  size_t off[15];
+  size_t off[17];
   plan_work<T>(m, n, KP, opts->iters, obj_np, 0, cv, off);
   const size_t o_rpt = cv.take<int64_t>(n + 1);
   const size_t o_cit = cv.take<int32_t>(nnz);
@@ -734,12 +826,13 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
     HIP_TRY(hipEventCreate(&t1));
     HIP_TRY(hipEventRecord(t0, st));
   }
-  s = run_au_nmf<T>(ctx, pb, m, n, k, KP, opts, w, want_obj, tm);
+  StopInfo si;
+  s = run_au_nmf<T>(ctx, pb, m, n, k, KP, opts, w, want_obj, tm, si);
   if (stats) HIP_TRY(hipEventRecord(t1, st));
   if (s == NMF_OK) {
     HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
     HIP_TRY(nmfk::transpose_out<T>(w.Ht, k, n, KP, H, st));
-    s = finish_call<T>(ctx, opts, w, want_obj, rel_err, stats, tm, t0, t1);
+    s = finish_call<T>(ctx, opts, w, want_obj, rel_err, stats, tm, t0, t1, si);
   }
   if (t0) hipEventDestroy(t0);
   if (t1) hipEventDestroy(t1);
@@ -918,7 +1011,7 @@ nmf_status relerr_impl(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, in
                                    : std::max(nmfk::residual_partials<T>(m, n),
                                               nmfk::sumsq_partials<T>(m, n));
   Carve cv;
-  size_t off[15];
+  size_t off[17];
   plan_work<T>(m, n, KP, 0, obj_np, 0, cv, off);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
@@ -1369,6 +1462,55 @@ nmf_status nmf_mu_unrolled_backward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, in
   return mu_backward_impl<double>(ctx, m, n, (const double*)A, lda, k, iters, eps, ckpt_every,
                                   (const double*)ckpt, (const double*)gW, (const double*)gH,
                                   (double*)gA, ldga, (double*)gW0, (double*)gH0);
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+nmf_status pgrad_impl(nmf_ctx* ctx, int64_t rows, int k, const T* X, const T* Pm, const T* G,
+                      double* out) {
+  const int KP = kp_dense(k);
+  Carve cv;
+  const size_t oX = cv.take<T>(rows * KP);
+  const size_t oP = cv.take<T>(rows * KP);
+  const size_t oG = cv.take<T>(KP * KP);
+  const size_t oq = cv.take<double>(nmfk::pgrad_partials(rows));
+  const size_t ov = cv.take<double>(1);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  hipStream_t st = ctx->stream;
+  T* Xp = at<T>(ctx, oX);
+  T* Pp = at<T>(ctx, oP);
+  T* Gp = at<T>(ctx, oG);
+  HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
+  HIP_TRY(nmfk::pad_rows<T>(Pm, rows, k, Pp, KP, st));
+  HIP_TRY(nmfk::pad_rows<T>(G, k, k, Gp, KP, st));
+  if (KP > k) HIP_TRY(hipMemsetAsync(Gp + (size_t)k * KP, 0, sizeof(T) * (KP - k) * KP, st));
+  HIP_TRY(nmfk::pgrad_sq<T>(Xp, Pp, Gp, rows, k, KP, at<double>(ctx, oq), st));
+  HIP_TRY(nmfk::finish_relerr<T>(at<double>(ctx, oq), nmfk::pgrad_blocks<T>(rows, KP),
+                                 (const T*)nullptr, (const T*)nullptr, 0, (const double*)nullptr,
+                                 at<double>(ctx, ov), st));
+  return read_doubles(ctx, at<double>(ctx, ov), out, 1);
+}
+}  // namespace
+
+extern "C" {
+
+nmf_status nmf_projected_gradient_sq(nmf_ctx* ctx, nmf_dtype dtype, int64_t rows, int k,
+                                     const void* X, const void* P, const void* G,
+                                     double* out) {
+  nmf_status s = check_common(ctx, rows, 1, k);
+  if (s != NMF_OK) return s;
+  if (!X || !P || !G || !out) return fail(ctx, NMF_EINVAL, "null argument");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return pgrad_impl<float>(ctx, rows, k, (const float*)X, (const float*)P, (const float*)G,
+                             out);
+  if (dtype == NMF_F64)
+    return pgrad_impl<double>(ctx, rows, k, (const double*)X, (const double*)P,
+                              (const double*)G, out);
+  return fail(ctx, NMF_EINVAL, "dtype must be F32 or F64");
 }
 
 }  // extern "C"

@@ -98,6 +98,16 @@ int64_t sumsq_partials(int64_t m, int64_t n);
 template <typename T>
 hipError_t sumsq(const T* A, int64_t lda, int64_t m, int64_t n, double* partial,
                  hipStream_t st);
+// Squares of the projected gradient of 1/2 ||A - W H||^2 in the factor whose
+// rows are X (rows x KP): g = x G - p per row, kept where x > 0, negative part
+// where x = 0; one double per block: pgrad_blocks<T>(rows, KP) of them, at
+// most pgrad_partials(rows).
+int64_t pgrad_partials(int64_t rows);
+template <typename T>
+int64_t pgrad_blocks(int64_t rows, int KP);
+template <typename T>
+hipError_t pgrad_sq(const T* X, const T* P, const T* G, int64_t rows, int k, int KP,
+                    double* partial, hipStream_t st);
 // out[slot] = sqrt(max(0, sum(partial[0..np)) + add) / ref) where add is the
 // <G1, G2> Frobenius product of two KP x KP matrices (nullable) and ref the
 // double at *ref_sq (nullable: out = the sum itself, no sqrt).

@@ -124,6 +124,99 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const T* __restrict__ A, int
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// Projected gradient of 1/2 ||A - W H||_F^2 in one factor (Section 6.2's
+// stationarity measure), on the row layout: for each row x with its product
+// row p and the Gram G of the other factor, g = x G - p, and the projection
+// keeps g_i where x_i > 0 and min(g_i, 0) where x_i = 0. Each block sums the
+// squares of its rows in double: TPR threads per row (4; 16 for a double
+// 128 x 128 Gram, to stay within LDS), RPT = KP / TPR entries each, with G
+// and the block's rows staged in LDS.
+template <typename T, int KP> struct PgSplit {
+  static constexpr int TPR = (sizeof(T) == 8 && KP == 128) ? 16 : 4;
+  static constexpr int ROWS = 256 / TPR;
+};
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void pgrad_sq_kernel(const T* __restrict__ X,
+                                                       const T* __restrict__ P,
+                                                       const T* __restrict__ G, int64_t rows,
+                                                       int k, double* __restrict__ partial) {
+  constexpr int PG_TPR = PgSplit<T, KP>::TPR, PG_ROWS = PgSplit<T, KP>::ROWS;
+  constexpr int RPT = KP / PG_TPR;
+  constexpr int VEC = Tr<T>::VEC;
+  constexpr int XLD = KP + VEC;
+  __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
+  __shared__ __attribute__((aligned(16))) T Xs[PG_ROWS * XLD];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) Gs[e] = G[e];
+  const int64_t rb = (int64_t)blockIdx.x * PG_ROWS;
+  for (int e = threadIdx.x; e < PG_ROWS * KP; e += 256) {
+    const int q = e / KP, j = e % KP;
+    Xs[q * XLD + j] = rb + q < rows ? X[(rb + q) * KP + j] : T(0);
+  }
+  __syncthreads();
+  const int lr = threadIdx.x / PG_TPR;
+  const int64_t r = rb + lr;
+  const int i0 = (threadIdx.x % PG_TPR) * RPT;
+  const T* xs = &Xs[lr * XLD];
+  double local = 0.0;
+  if (r < rows) {
+    T g[RPT];
+#pragma unroll
+    for (int ii = 0; ii < RPT; ++ii) g[ii] = T(0);
+#pragma unroll 8
+    for (int j = 0; j < KP; ++j) {
+      const T xj = xs[j];
+#pragma unroll
+      for (int q = 0; q < RPT / VEC; ++q) {
+        const V16<T> v = load16<T>(&Gs[j * KP + i0 + q * VEC]);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) g[q * VEC + w] = fma(xj, v.v[w], g[q * VEC + w]);
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < RPT; ++ii) {
+      const int i = i0 + ii;
+      if (i < k) {
+        const double gi = (double)g[ii] - (double)P[r * KP + i];
+        const double pr = xs[i] > T(0) ? gi : (gi < 0.0 ? gi : 0.0);
+        local += pr * pr;
+      }
+    }
+  }
+  const double s = block_sum(local);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Upper bound on the blocks of any pgrad_sq launch (16 rows per block), and
+// the exact count of one launch.
+int64_t pgrad_partials(int64_t rows) { return cdiv(rows, 16); }
+template <typename T>
+int64_t pgrad_blocks(int64_t rows, int KP) {
+  return cdiv(rows, (sizeof(T) == 8 && KP == 128) ? 16 : 64);
+}
+template int64_t pgrad_blocks<float>(int64_t, int);
+template int64_t pgrad_blocks<double>(int64_t, int);
+
+template <typename T>
+hipError_t pgrad_sq(const T* X, const T* P, const T* G, int64_t rows, int k, int KP,
+                    double* partial, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  switch (KP) {
+#define CASE(K)                                                                             \
+  case K:                                                                                   \
+    pgrad_sq_kernel<T, K><<<(unsigned)cdiv(rows, PgSplit<T, K>::ROWS), 256, 0, st>>>(      \
+        X, P, G, rows, k, partial);                                                         \
+    break;
+    CASE(16) CASE(32) CASE(48) CASE(64) CASE(80) CASE(96) CASE(112) CASE(128)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return NMF_LAUNCH_CHECK();
+}
+template hipError_t pgrad_sq<float>(const float*, const float*, const float*, int64_t, int, int,
+                                    double*, hipStream_t);
+template hipError_t pgrad_sq<double>(const double*, const double*, const double*, int64_t, int,
+                                     int, double*, hipStream_t);
+
 template <typename T>
 int64_t sumsq_partials(int64_t m, int64_t n) {
   (void)n;

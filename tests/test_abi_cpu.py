@@ -41,7 +41,8 @@ def test_status_strings_and_defaults():
     assert o.algo == _lib.NMF_MU and o.iters == 0 and o.eps_mu == 1e-16
     assert o.max_pivots == 0 and o.objective == 0 and o.transpose_a == 0
     # the ctypes mirrors must be at least as large as the C structs they stand for
-    assert ctypes.sizeof(_lib.NmfOpts) == 8 * 5 and ctypes.sizeof(_lib.NmfStats) == 8 * 9
+    assert o.tol == 0.0 and o.stop == 0
+    assert ctypes.sizeof(_lib.NmfOpts) == 8 * 7 and ctypes.sizeof(_lib.NmfStats) == 8 * 11
 
 
 @pytest.fixture
@@ -145,3 +146,18 @@ def test_mu_unrolled_argument_errors(hctx):
     assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, None, P, P, P, 8, P, P) == EINVAL
     assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P, P, 7, P, P) == EINVAL  # ldga
     assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P, None, 0, P, P) == EDEVICE
+
+
+def test_stop_options_and_pgrad_argument_errors(hctx):
+    L = _lib.lib()
+    assert dense(hctx, opts=_lib.default_opts(algo="hals", iters=2, stop=1, tol=0.1)) == EDEVICE
+    assert dense(hctx, opts=_lib.default_opts(algo="hals", iters=2, stop=3)) == EINVAL
+    assert dense(hctx, opts=_lib.default_opts(algo="hals", iters=2, stop=1, tol=-1.0)) == EINVAL
+    # the relative-error test needs the objective
+    assert dense(hctx, opts=_lib.default_opts(algo="hals", iters=2, stop=2, tol=0.1)) == EINVAL
+    assert dense(hctx, opts=_lib.default_opts(algo="hals", iters=2, stop=2, tol=0.1,
+                                              objective=1)) == EDEVICE
+    out = ctypes.c_double()
+    assert L.nmf_projected_gradient_sq(hctx, 1, 10, 3, P, P, P, ctypes.byref(out)) == EDEVICE
+    assert L.nmf_projected_gradient_sq(hctx, 1, 10, 3, P, None, P, ctypes.byref(out)) == EINVAL
+    assert L.nmf_projected_gradient_sq(hctx, 1, 10, 3, P, P, P, None) == EINVAL
