@@ -74,10 +74,10 @@ def test_dense_fp32_pgrad_ratio_matches_oracle():
     W0, H0 = W0.astype(np.float32), H0.astype(np.float32)
     step("stop fp32 hals pgrad")
     W, H = to_dev(W0, np.float32), to_dev(H0, np.float32)
-    errs, st = nmf.nmf_dense(to_dev(A, np.float32), W, H, algo="hals", iters=40, objective=True,
+    errs, st = nmf.nmf_dense(to_dev(A, np.float32), W, H, algo="hals", iters=60, objective=True,
                              stop="pgrad", tol=0.1)
     t = st["iters_done"]
-    assert t < 40 and st["pgrad_ratio"] <= 0.1
+    assert t < 60 and st["pgrad_ratio"] <= 0.1
     A64 = A.astype(np.float64)
     Wr, Hr, _ = oracle.run(A64, k, "hals", t, W0, H0, track_error=False)
     ratio = oracle.projected_gradient_norm(A64, Wr, Hr) / oracle.projected_gradient_norm(
