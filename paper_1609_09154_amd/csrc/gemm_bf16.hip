@@ -138,8 +138,26 @@ __global__ __launch_bounds__(64 * BWAVES, WPE) void gemm_bf16_nt_kernel(
     if (nfull > 1) load_y(yv[1], kbeg + BK);
     store_y(yv[0], 0);
     __syncthreads();
-    // steady state, unrolled STAGES times so every ring index is a constant
-    for (int64_t s = 0; s < nfull; s += STAGES) {
+    // Steady state: every prefetch is in range, so the unrolled body has no
+    // branch between a load and its use and the wait counts stay exact.
+    // STAGES is even, so ring and buffer indices are constants.
+    constexpr int AHEAD = STAGES - 1 > 2 ? STAGES - 1 : 2;
+    int64_t s = 0;
+    for (; s + STAGES + AHEAD <= nfull; s += STAGES) {
+#pragma unroll
+      for (int u = 0; u < STAGES; ++u) {
+        const int64_t st = s + u;
+        load_y(yv[u & 1], kbeg + (st + 2) * BK);
+        load_x(xf[(u + STAGES - 1) % STAGES], kbeg + (st + STAGES - 1) * BK);
+        // keep the prefetches ahead of this step's matrix-core work
+        __builtin_amdgcn_sched_barrier(0);
+        compute(xf[u], u & 1);
+        store_y(yv[(u + 1) & 1], (u + 1) & 1);
+        __syncthreads();
+      }
+    }
+    // Drain: the last steps, with the loads past the end skipped.
+    for (; s < nfull; s += STAGES) {
 #pragma unroll
       for (int u = 0; u < STAGES; ++u) {
         const int64_t st = s + u;
@@ -222,7 +240,7 @@ hipError_t pack_bf16_t(const float* F, int64_t rows, int KP, uint16_t* Ft, int64
   return NMF_LAUNCH_CHECK();
 }
 
-constexpr int B_MT = 2, B_STAGES = 2, B_WPE = 1;  // launch shape (timing sweep at 131072 x 65536, k = 100)
+constexpr int B_MT = 4, B_STAGES = 4, B_WPE = 1;  // launch shape (timing sweep at 131072 x 65536, k = 100)
 constexpr int BROWS = 16 * B_MT * BWAVES;
 
 int64_t gemm_bf16_splits(int64_t M, int64_t K) {
