@@ -48,6 +48,8 @@ WORKLOADS = {
                                                    algo="abpp", dtype="f32", sparse=True),
     "dense-131072x65536-k100-hals-bf16": dict(m=131072, n=65536, k=100, k_true=100, algo="hals",
                                               dtype="bf16"),
+    "dense-131072x65536-k100-hals-fp8": dict(m=131072, n=65536, k=100, k_true=100, algo="hals",
+                                             dtype="fp8"),
     # Shapes of the paper's Table 1 data sets (synthetic stand-ins; the table
     # quotes 30 iterations at k = 50 on 1536 processors, algorithm not named).
     "dense-1013400x13824-k50-hals-f32": dict(m=1013400, n=13824, k=50, k_true=50, algo="hals",
@@ -213,14 +215,15 @@ def run_sparse(args, wl):
     print(json.dumps(out), flush=True)
 
 
-def run_bf16(args, wl):
-    """Precision workload: the same planted matrix stored in bfloat16 (the
-    two large products on the BF16 matrix cores, everything else float32)
-    and in float32, factorised from the same initial factors. value is the
-    BF16 rate; the FP32 rate and both final relative errors (direct residual
-    against the float32 A, double accumulation) are reported beside it.
-    roofline: the BF16 products stream A (2 bytes per entry) once per launch:
-    HBM-bound at k flops per byte."""
+def run_lowp(args, wl):
+    """Precision workloads: the same planted matrix stored in bfloat16 or
+    FP8 E4M3 (the two large products on the BF16 / FP8 matrix cores,
+    everything else float32) and in float32, factorised from the same
+    initial factors. value is the reduced-precision rate; the FP32 rate and
+    both final relative errors (direct residual against the float32 A,
+    double accumulation) are reported beside it. roofline: the products
+    stream A (2 or 1 bytes per entry) once per launch: HBM-bound at k or 2k
+    flops per byte."""
     import torch
 
     import paper_1609_09154_amd as nmf
@@ -231,13 +234,15 @@ def run_bf16(args, wl):
     print("[bench] generating %s" % args.workload, file=sys.stderr, flush=True)
     A32 = planted_dense_torch(m, n, wl["k_true"], sigma=0.01, seed=1609, device=dev,
                               dtype=torch.float32)
-    Ab = A32.to(torch.bfloat16)
+    lp = wl["dtype"]
+    esize = 2 if lp == "bf16" else 1
+    Ab = A32.to(torch.bfloat16 if lp == "bf16" else torch.float8_e4m3fn)
     W0n, H0n = init_factors(m, n, k, seed=9154)
     W0 = torch.from_numpy(W0n).to(dev, torch.float32)
     H0 = torch.from_numpy(H0n).to(dev, torch.float32)
     torch.cuda.synchronize()
     res = {}
-    for tag, A in (("bf16", Ab), ("f32", A32)):
+    for tag, A in ((lp, Ab), ("f32", A32)):
         print("[bench] %s: warmup %d" % (tag, args.warmup), file=sys.stderr, flush=True)
         W, H = W0.clone(), H0.clone()
         nmf.nmf_dense(A, W, H, algo=wl["algo"], iters=args.warmup, objective=False)
@@ -252,24 +257,26 @@ def run_bf16(args, wl):
         elapsed = time.perf_counter() - t0
         rel = nmf.nmf_dense_relerr(A32, W, H.t().contiguous())
         res[tag] = dict(elapsed=elapsed, stats=st, rel_err=rel)
-    b = res["bf16"]
+    b = res[lp]
     ms_launch = 0.5 * (b["stats"]["ms_mm_aht"] + b["stats"]["ms_mm_wta"]) / args.steps
-    bytes_launch = 2.0 * m * n
+    bytes_launch = float(esize) * m * n
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     f = res["f32"]
     ms_launch32 = 0.5 * (f["stats"]["ms_mm_aht"] + f["stats"]["ms_mm_wta"]) / args.steps
     out = {
-        "metric": "NMF iterations/s (dense HALS, A 131072x65536 bf16, k=100; BF16 products)",
+        "metric": "NMF iterations/s (dense %s, A %dx%d %s, k=%d; %s products)"
+                  % (wl["algo"].upper(), m, n, lp, k, lp.upper()),
         "value": round(args.steps / b["elapsed"], 3), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1000.0 * b["elapsed"] / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": lp, "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "algorithm": wl["algo"],
                    "parallelism": "single-gpu"},
+        "setup_ms": round(b["stats"]["ms_setup"], 3),
         "phase_ms_per_step": {p: round(b["stats"][q] / args.steps, 4) for p, q in
                               (("mm", "ms_mm"), ("luc", "ms_luc"), ("gram", "ms_gram"))},
-        "rel_err_after_steps": {"bf16": b["rel_err"], "f32": f["rel_err"],
-                                "bf16_minus_f32_relative": (b["rel_err"] - f["rel_err"])
+        "rel_err_after_steps": {lp: b["rel_err"], "f32": f["rel_err"],
+                                lp + "_minus_f32_relative": (b["rel_err"] - f["rel_err"])
                                 / f["rel_err"]},
         "f32_same_problem": {"value": round(args.steps / f["elapsed"], 3), "unit": "iters/s",
                              "ms_per_step": round(1000.0 * f["elapsed"] / args.steps, 3),
@@ -278,7 +285,10 @@ def run_bf16(args, wl):
                                                       / 1e12, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "gemm_bf16_nt (A H^T and A^T W, BF16 MFMA 16x16x32)",
+                     "kernel": ("gemm_lp_nt_kernel<uint16_t> (A H^T and A^T W, BF16 MFMA "
+                                "16x16x32)" if lp == "bf16" else
+                                "gemm_lp_nt_kernel<uint8_t> (A H^T and A^T W, FP8 MFMA "
+                                "16x16x128)"),
                      "ms_per_launch": round(ms_launch, 4),
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "tflops": round(2.0 * m * n * k / (ms_launch * 1e-3) / 1e12, 2)},
@@ -386,8 +396,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl.get("sparse"):
         return run_sparse(args, wl)
-    if wl["dtype"] == "bf16":
-        return run_bf16(args, wl)
+    if wl["dtype"] in ("bf16", "fp8"):
+        return run_lowp(args, wl)
     if wl.get("autograd"):
         return run_autograd(args, wl)
     m, n, k = wl["m"], wl["n"], wl["k"]

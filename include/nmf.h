@@ -41,6 +41,15 @@
  *   Grams, updates and the objective are as for NMF_F32. This is the
  *   reduced-precision variant of the products the paper's Section 6.3.1
  *   breakdown calls MM.
+ *   NMF_FP8_E4M3 (dense A only) is the same with A stored as FP8 E4M3 (one
+ *   byte each: sign, 4 exponent bits with bias 7, 3 fraction bits; largest
+ *   finite 448, bits S.1111.111 NaN; lda a multiple of 16, rows 16-byte
+ *   aligned): the products run on the FP8 matrix cores with float
+ *   accumulation; for each product every rank column j of the factor operand
+ *   is divided by s_j, the smallest power of two with max |column j| <=
+ *   448 s_j (1 for a zero column), rounded to E4M3 (nearest even), and the
+ *   output column is multiplied by s_j. Any scaling of A itself is the
+ *   caller's: the factorisation of c A is c times that of A.
  * - 1 <= k <= NMF_MAX_K and k <= min(m, n) is not required, but k must not
  *   exceed NMF_MAX_K. m, n >= 1.
  * - Calls on one context must not overlap (one stream, shared workspace).
@@ -68,7 +77,7 @@ typedef enum {
 
 typedef enum { NMF_MU = 0, NMF_HALS = 1, NMF_ABPP = 2 } nmf_algo;
 
-typedef enum { NMF_F64 = 0, NMF_F32 = 1, NMF_BF16 = 2 } nmf_dtype;
+typedef enum { NMF_F64 = 0, NMF_F32 = 1, NMF_BF16 = 2, NMF_FP8_E4M3 = 3 } nmf_dtype;
 
 typedef enum {
   NMF_STOP_ITERS = 0,  /* run exactly opts->iters iterations               */
@@ -101,7 +110,8 @@ typedef struct {
   int transpose_a;   /* dense A: 0 (default) keeps a transposed copy of A in */
                      /* device memory for the call when it fits (both large  */
                      /* products then stream A row by row); -1 never does.   */
-                     /* NMF_BF16 A always needs the copy: -1 is rejected and */
+                     /* NMF_BF16 and NMF_FP8_E4M3 A always need the copy: */
+                     /* -1 is rejected and                                  */
                      /* a copy that does not fit returns NMF_ENOMEM          */
   double tol;        /* tolerance of the stopping test (>= 0)                */
   int stop;          /* nmf_stop. Section 6.2: the iteration count together  */
@@ -148,7 +158,7 @@ const char* nmf_last_error(const nmf_ctx* ctx);
 /* Full AU-NMF on a dense A (Algorithm 1).
  *   A       m x n, leading dimension lda >= n, element type dtype.
  *   W       m x k (leading dimension k), element type dtype (float for
- *           NMF_BF16): the initial W on
+ *           NMF_BF16 and NMF_FP8_E4M3): the initial W on
  *           entry (read by MU and HALS; ABPP's W step is an exact solve that
  *           only takes its starting passive sets from it), the final W.
  *   H       k x n (leading dimension n): initial H on entry, final H on return.
@@ -185,14 +195,17 @@ nmf_status nmf_gram(nmf_ctx* ctx, nmf_dtype dtype, int64_t rows, int k,
 /* P = A F for dense A (m x n, lda) and F (n x k, ldf): with F = H^T this is
  * the A H^T of the W update. Output P is m x k (leading dimension k).
  * NMF_BF16: A bfloat16 (lda a multiple of 8), F and P float; F is rounded
- * to bfloat16 for the product, as in nmf_dense. */
+ * to bfloat16 for the product, as in nmf_dense. NMF_FP8_E4M3 likewise (lda
+ * a multiple of 16; F scaled per column and rounded to E4M3 as in
+ * nmf_dense). */
 nmf_status nmf_dense_AF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
                         const void* A, int64_t lda, int k, const void* F,
                         int64_t ldf, void* P);
 
 /* R = A^T F for dense A (m x n, lda) and F (m x k, ldf): with F = W this is
  * (W^T A)^T of the H update. Output R is n x k (leading dimension k).
- * NMF_BF16 as for nmf_dense_AF (the call makes a transposed copy of A). */
+ * NMF_BF16 and NMF_FP8_E4M3 as for nmf_dense_AF (the call makes a
+ * transposed copy of A). */
 nmf_status nmf_dense_AtF(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
                          const void* A, int64_t lda, int k, const void* F,
                          int64_t ldf, void* R);
@@ -240,7 +253,7 @@ nmf_status nmf_hals_normalize(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
 /* Relative error ||A - W H||_F / ||A||_F of Section 6.2 for dense A, with W
  * (m x k) and Ht = H^T (n x k). Residual formed explicitly, squares summed
  * in double. Result written to the host double *out (synchronises).
- * NMF_BF16: A bfloat16, W and Ht float. */
+ * NMF_BF16 / NMF_FP8_E4M3: A in that format, W and Ht float. */
 nmf_status nmf_dense_relerr(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
                             int64_t n, const void* A, int64_t lda, int k,
                             const void* W, const void* Ht, double* out);

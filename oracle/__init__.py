@@ -26,7 +26,8 @@ from .nmf import (  # noqa: F401
     gram_fixed_H, gram_fixed_W, product_AHt, product_WtA,
     mu_update_W, mu_update_H, hals_update_W, hals_update_H,
     abpp_update_W, abpp_update_H, relative_error, objective_sq, run,
-    round_bf16, MU_EPS, gradients, projected_gradient_sq, projected_gradient_norm, run_until,
+    round_bf16, round_fp8_e4m3, fp8_column_scales, round_fp8_scaled, FP8_E4M3_MAX,
+    MU_EPS, gradients, projected_gradient_sq, projected_gradient_norm, run_until,
 )
 from .bpp import bpp_nnls, passive_solve  # noqa: F401
 from .autodiff import mu_unrolled_forward, mu_unrolled_vjp  # noqa: F401

@@ -45,6 +45,66 @@ def round_bf16(X):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+# --- FP8 (E4M3) rounding of a product operand -----------------------------
+
+FP8_E4M3_MAX = 448.0
+
+
+def round_fp8_e4m3(X):
+    """Values of X rounded to FP8 E4M3, round to nearest with ties to even,
+    saturating at the largest finite value 448; returned as float64.
+
+    E4M3 has a sign, 4 exponent bits (bias 7) and 3 fraction bits: for
+    2^e <= |x| < 2^(e+1) with -6 <= e <= 8 the representable values are the
+    multiples of 2^(e-3), and below 2^-6 (the subnormals) the multiples of
+    2^-9. Rounding is therefore: find the binade, divide by its spacing,
+    round to the nearest integer with ties to even (np.rint), multiply
+    back; all of it exact in float64. A result past 448 is clamped to 448.
+    Values are first rounded to float32, the type the GPU factors are
+    stored in. NaN is not expected."""
+    x = np.asarray(X, dtype=np.float64).astype(np.float32).astype(np.float64)
+    a = np.abs(x)
+    _, E = np.frexp(a)                 # a = f 2^E with f in [0.5, 1)
+    e = np.maximum(E - 1, -6)          # binade exponent, subnormals share -6
+    spacing = np.ldexp(1.0, e - 3)
+    r = np.minimum(np.rint(a / spacing) * spacing, FP8_E4M3_MAX)
+    return np.copysign(r, x)
+
+
+def fp8_column_scales(X, rank_axis: int):
+    """Per rank index j (along ``rank_axis`` of X), the scale s_j = 2^p of
+    the FP8 product operand: the smallest power of two with
+    max |X_j| <= 448 s_j, and 1 when X_j is all zero. Taken on the float32
+    values of X."""
+    x = np.abs(np.asarray(X, dtype=np.float64).astype(np.float32).astype(np.float64))
+    other = 1 - rank_axis
+    mx = x.max(axis=other) if x.shape[other] else np.zeros(x.shape[rank_axis])
+    s = np.ones(len(mx))
+    for j, v in enumerate(mx):
+        if v == 0.0:
+            continue
+        p = int(np.floor(np.log2(v / FP8_E4M3_MAX)))
+        while FP8_E4M3_MAX * 2.0 ** p < v:          # not yet large enough
+            p += 1
+        while FP8_E4M3_MAX * 2.0 ** (p - 1) >= v:   # a smaller power still fits
+            p -= 1
+        s[j] = 2.0 ** p
+    return s
+
+
+def round_fp8_scaled(X, rank_axis: int):
+    """The FP8 product operand as values: each rank slice X_j divided by its
+    scale s_j (fp8_column_scales), rounded to E4M3, multiplied back by s_j.
+    Since s_j is a power of two, a product with this operand equals the
+    product of the E4M3 codes with the output column multiplied by s_j."""
+    s = fp8_column_scales(X, rank_axis)
+    shape = [1, 1]
+    shape[rank_axis] = -1
+    s = s.reshape(shape)
+    x32 = np.asarray(X, dtype=np.float64).astype(np.float32).astype(np.float64)
+    return round_fp8_e4m3(x32 / s) * s
+
+
 # --- the four products of Algorithm 1 ------------------------------------
 
 def gram_fixed_H(H):
@@ -265,7 +325,8 @@ def projected_gradient_norm(A, W, H) -> float:
 # --- Algorithm 1 ---------------------------------------------------------
 
 def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
-        max_pivots=None, track_error: bool = True, bf16_products: bool = False):
+        max_pivots=None, track_error: bool = True, bf16_products: bool = False,
+        fp8_products: bool = False):
     """AU-NMF (Algorithm 1) for ``iters`` iterations from (W0, H0).
 
     One iteration: Q = H H^T, P = A H^T, update W; S = W^T W, R = W^T A,
@@ -279,8 +340,19 @@ def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
     operand of A H^T and W^T A is rounded to bfloat16 first (round_bf16);
     the products are then exact in float64, and the Grams, updates and the
     error use the unrounded factors as before.
+
+    fp8_products: the same with A stored in FP8 E4M3 and the factor operand
+    scaled per rank index and rounded to E4M3 (round_fp8_scaled).
     """
-    fr = round_bf16 if bf16_products else (lambda X: X)
+    if bf16_products and fp8_products:
+        raise ValueError("choose one reduced-precision product variant")
+    if bf16_products:
+        frH = frW = round_bf16
+    elif fp8_products:
+        frH = lambda X: round_fp8_scaled(X, 0)   # H is k x n: rank along rows
+        frW = lambda X: round_fp8_scaled(X, 1)   # W is m x k: rank along columns
+    else:
+        frH = frW = lambda X: X
     algo = algo.lower()
     if algo not in ("mu", "hals", "abpp"):
         raise ValueError("unknown algorithm %r" % algo)
@@ -293,7 +365,7 @@ def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
         errs.append(relative_error(A, W, H, normA_sq))
     for _ in range(iters):
         Q = gram_fixed_H(H)
-        P = product_AHt(A, fr(H))
+        P = product_AHt(A, frH(H))
         if algo == "mu":
             W = mu_update_W(W, Q, P, eps)
         elif algo == "hals":
@@ -301,7 +373,7 @@ def run(A, k: int, algo: str, iters: int, W0, H0, eps: float = MU_EPS,
         else:
             W = abpp_update_W(Q, P, max_pivots)
         S = gram_fixed_W(W)
-        R = product_WtA(A, fr(W))
+        R = product_WtA(A, frW(W))
         if algo == "mu":
             H = mu_update_H(H, S, R, eps)
         elif algo == "hals":

@@ -12,8 +12,8 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (NMF_ABPP, NMF_BF16, NMF_F32, NMF_F64, NMF_HALS, NMF_MU, NMF_OBJ_DIRECT,  # noqa: F401
-                   NMF_OBJ_NONE, NMFError, NmfStats, default_opts)
+from ._lib import (NMF_ABPP, NMF_BF16, NMF_F32, NMF_F64, NMF_FP8_E4M3, NMF_HALS, NMF_MU,  # noqa: F401
+                   NMF_OBJ_DIRECT, NMF_OBJ_NONE, NMFError, NmfStats, default_opts)
 
 __all__ = ["Context", "NMFError", "nmf_dense", "nmf_csr", "nmf_gram", "nmf_dense_AF",
            "nmf_mu_unrolled_forward", "nmf_mu_unrolled_backward", "mu_unrolled",
@@ -39,15 +39,19 @@ def _dtype_code(t) -> int:
         return NMF_F64
     if t.dtype == torch.bfloat16:
         return NMF_BF16
-    raise TypeError("only float32, float64 and bfloat16 (A) tensors are supported, got %s"
-                    % t.dtype)
+    if t.dtype == getattr(torch, "float8_e4m3fn", None):
+        return NMF_FP8_E4M3
+    raise TypeError("only float32, float64, bfloat16 (A) and float8_e4m3fn (A) tensors are "
+                    "supported, got %s" % t.dtype)
 
 
 def _factor_dtype(A):
     """Element type of W, H and the products for a dense A: float32 when A
-    is bfloat16, A's own type otherwise."""
+    is bfloat16 or float8_e4m3fn, A's own type otherwise."""
     torch = _torch()
-    return torch.float32 if A.dtype == torch.bfloat16 else A.dtype
+    if A.dtype in (torch.bfloat16, getattr(torch, "float8_e4m3fn", None)):
+        return torch.float32
+    return A.dtype
 
 
 def _dev(t, name, dtype=None, shape=None):
@@ -130,8 +134,8 @@ def nmf_dense(A, W, H, algo="hals", iters=10, objective=True, eps_mu=1e-16, max_
               timers=False, check_input=False, transpose_a=True, stop=None, tol=0.0, ctx=None):
     """Algorithm 1 on dense A (m x n); W (m x k) and H (k x n) are updated in
     place. transpose_a=False keeps the library from holding a transposed
-    copy of A. A may be bfloat16 (then W and H are float32, the products run
-    on the BF16 matrix cores). stop = "pgrad" or "relerr" adds the tolerance
+    copy of A. A may be bfloat16 or float8_e4m3fn (then W and H are float32,
+    the products run on the BF16 or FP8 matrix cores). stop = "pgrad" or "relerr" adds the tolerance
     test of nmf_opts (iters is then the cap). Returns (rel_err list or None,
     stats dict); the list ends at the last iteration performed."""
     torch = _torch()
@@ -192,8 +196,8 @@ def nmf_gram(X, ctx=None):
 
 
 def nmf_dense_AF(A, F, ctx=None):
-    """P = A F for dense A (m x n) and F (n x k); A may be bfloat16 (F and P
-    float32)."""
+    """P = A F for dense A (m x n) and F (n x k); A may be bfloat16 or
+    float8_e4m3fn (F and P float32)."""
     torch = _torch()
     m, n = A.shape
     k = F.shape[1]
@@ -206,8 +210,8 @@ def nmf_dense_AF(A, F, ctx=None):
 
 
 def nmf_dense_AtF(A, F, ctx=None):
-    """R = A^T F for dense A (m x n) and F (m x k); A may be bfloat16 (F and R
-    float32)."""
+    """R = A^T F for dense A (m x n) and F (m x k); A may be bfloat16 or
+    float8_e4m3fn (F and R float32)."""
     torch = _torch()
     m, n = A.shape
     k = F.shape[1]

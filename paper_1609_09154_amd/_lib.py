@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libnmf_mi355x.so")
 
 NMF_OK, NMF_EINVAL, NMF_ENOMEM, NMF_EDEVICE, NMF_ENUMERIC, NMF_ENOTCONV = range(6)
 NMF_MU, NMF_HALS, NMF_ABPP = 0, 1, 2
-NMF_F64, NMF_F32, NMF_BF16 = 0, 1, 2
+NMF_F64, NMF_F32, NMF_BF16, NMF_FP8_E4M3 = 0, 1, 2, 3
 NMF_OBJ_NONE, NMF_OBJ_DIRECT = 0, 1
 ALGOS = {"mu": NMF_MU, "hals": NMF_HALS, "abpp": NMF_ABPP}
 

@@ -111,6 +111,19 @@ nmf_status check_common(nmf_ctx* ctx, int64_t m, int64_t n, int k) {
   return NMF_OK;
 }
 
+bool is_lp(int dtype) { return dtype == NMF_BF16 || dtype == NMF_FP8_E4M3; }
+
+// Reduced-precision A: rows 16-byte aligned, lda a whole number of 16 bytes.
+nmf_status check_lp_a(nmf_ctx* ctx, int dtype, const void* A, int64_t lda) {
+  const int64_t unit = dtype == NMF_FP8_E4M3 ? 16 : 8;
+  if (lda % unit != 0)
+    return fail(ctx, NMF_EINVAL, dtype == NMF_FP8_E4M3 ? "FP8 A: lda must be a multiple of 16"
+                                                      : "bfloat16 A: lda must be a multiple of 8");
+  if (((uintptr_t)A) % 16 != 0)
+    return fail(ctx, NMF_EINVAL, "reduced-precision A must be 16-byte aligned");
+  return NMF_OK;
+}
+
 nmf_status check_opts(nmf_ctx* ctx, const nmf_opts* o, int k, bool have_relerr) {
   if (!o) return fail(ctx, NMF_EINVAL, "opts is NULL");
   if (o->algo < NMF_MU || o->algo > NMF_ABPP) return fail(ctx, NMF_EINVAL, "unknown algorithm");
@@ -289,16 +302,43 @@ template <typename T> struct Prob {
   bool sparse = false;
   const T* A = nullptr; int64_t lda = 0;                 // dense
   const T* At = nullptr;                                 // dense A^T (n x m, ld m) or null
-  // bfloat16 A (bits, T = float): A m x n (lda), its transposed copy n x m
-  // (row pitch ldat) and scratch for the packed bfloat16 factor.
-  const uint16_t* Ab = nullptr;
-  const uint16_t* Abt = nullptr;
+  // Reduced-precision A (T = float): lp is NMF_BF16 (bfloat16 bits) or
+  // NMF_FP8_E4M3 (FP8 bits), 0 for none. Alp is A (m x n, lda), Alpt its
+  // transposed copy (n x m, row pitch ldat); fb holds the packed factor and,
+  // for FP8, fscale its KP column scales with fmax KP words of scratch.
+  int lp = 0;
+  const void* Alp = nullptr;
+  const void* Alpt = nullptr;
   int64_t ldat = 0;
-  uint16_t* fb = nullptr;
+  void* fb = nullptr;
+  float* fscale = nullptr;
+  unsigned* fmax = nullptr;
   const int64_t* rp = nullptr; const int32_t* ci = nullptr; const float* cv = nullptr;  // CSR A
   const int64_t* rpt = nullptr; const int32_t* cit = nullptr; const float* cvt = nullptr; // CSR A^T
   int64_t nnz = 0;
 };
+
+// Elements per 16 bytes of a reduced-precision A: the pitch unit of its rows
+// and of the packed factor.
+int64_t lp_align(int lp) { return lp == NMF_FP8_E4M3 ? 16 : 8; }
+
+// Out (M x KP float) = X F^T-style product on the reduced-precision matrix
+// cores: X (M x K, ldx) is A or its transposed copy, F (K x KP float, row
+// layout) the factor, packed (transposed, rounded) into pb.fb first.
+nmf_status lp_product(nmf_ctx* ctx, const Prob<float>& pb, const void* X, int64_t ldx,
+                      int64_t M, int64_t K, const float* F, int KP, float* Out, float* part) {
+  const int64_t ldf = round_up(K, lp_align(pb.lp));
+  if (pb.lp == NMF_BF16) {
+    HIP_TRY(nmfk::pack_bf16_t(F, K, KP, (uint16_t*)pb.fb, ldf, ctx->stream));
+    HIP_TRY(nmfk::gemm_bf16_nt((const uint16_t*)X, ldx, (const uint16_t*)pb.fb, ldf, Out, KP, M,
+                               KP, K, part, ctx->stream));
+    return NMF_OK;
+  }
+  HIP_TRY(nmfk::pack_fp8_t(F, K, KP, (uint8_t*)pb.fb, ldf, pb.fscale, pb.fmax, ctx->stream));
+  HIP_TRY(nmfk::gemm_fp8_nt((const uint8_t*)X, ldx, (const uint8_t*)pb.fb, ldf, pb.fscale, Out,
+                            KP, M, KP, K, part, ctx->stream));
+  return NMF_OK;
+}
 
 // Ft (nullable) is F transposed (KP x rows of F); the dense kernels then read
 // the rank-side operand with 16-byte loads.
@@ -312,16 +352,10 @@ nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, con
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
   }
-  if (pb.Ab) {
-    if constexpr (sizeof(T) == 4) {
-      // P = A (H^T): H packed as bfloat16 rows (KP x n), K = n contiguous
-      const int64_t ldf = round_up(n, 8);
-      HIP_TRY(nmfk::pack_bf16_t(F, n, KP, pb.fb, ldf, ctx->stream));
-      HIP_TRY(nmfk::gemm_bf16_nt(pb.Ab, pb.lda, pb.fb, ldf, Pout, KP, m, KP, n, part,
-                                 ctx->stream));
-      return NMF_OK;
-    }
-    return fail(ctx, NMF_EINVAL, "bfloat16 A takes float factors");
+  if (pb.lp) {
+    // P = A (H^T): H packed as reduced-precision rows (KP x n), K = n contiguous
+    if constexpr (sizeof(T) == 4) return lp_product(ctx, pb, pb.Alp, pb.lda, m, n, F, KP, Pout, part);
+    return fail(ctx, NMF_EINVAL, "reduced-precision A takes float factors");
   }
   if (pb.At) {
     // A H^T = (A^T)^T H^T: the TN kernel streaming A^T row by row.
@@ -346,17 +380,12 @@ nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, co
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
   }
-  if (pb.Ab) {
-    if constexpr (sizeof(T) == 4) {
-      // R = A^T W on the transposed copy: W packed as bfloat16 rows (KP x m)
-      if (!pb.Abt) return fail(ctx, NMF_EINVAL, "bfloat16 A^T W needs the transposed copy");
-      const int64_t ldf = round_up(m, 8);
-      HIP_TRY(nmfk::pack_bf16_t(F, m, KP, pb.fb, ldf, ctx->stream));
-      HIP_TRY(nmfk::gemm_bf16_nt(pb.Abt, pb.ldat, pb.fb, ldf, Rout, KP, n, KP, m, part,
-                                 ctx->stream));
-      return NMF_OK;
-    }
-    return fail(ctx, NMF_EINVAL, "bfloat16 A takes float factors");
+  if (pb.lp) {
+    // R = A^T W on the transposed copy: W packed as reduced-precision rows (KP x m)
+    if (!pb.Alpt) return fail(ctx, NMF_EINVAL, "reduced-precision A^T W needs the transposed copy");
+    if constexpr (sizeof(T) == 4)
+      return lp_product(ctx, pb, pb.Alpt, pb.ldat, n, m, F, KP, Rout, part);
+    return fail(ctx, NMF_EINVAL, "reduced-precision A takes float factors");
   }
   nmfk::GemmArgs<T> a{pb.A, pb.lda, Ft ? Ft : F, Ft ? m : (int64_t)KP, Rout, KP, n, KP, m,
                       Ft != nullptr, k};
@@ -384,10 +413,14 @@ nmf_status objective(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int 
     }
     return NMF_EINVAL;
   }
-  if (pb.Ab) {
+  if (pb.lp == NMF_BF16) {
     if constexpr (sizeof(T) == 4)
-      HIP_TRY((nmfk::residual_sq<float, uint16_t>(pb.Ab, pb.lda, m, n, w.W, w.Ht, KP, w.obj_part,
-                                                  st)));
+      HIP_TRY((nmfk::residual_sq<float, uint16_t>((const uint16_t*)pb.Alp, pb.lda, m, n, w.W,
+                                                  w.Ht, KP, w.obj_part, st)));
+  } else if (pb.lp == NMF_FP8_E4M3) {
+    if constexpr (sizeof(T) == 4)
+      HIP_TRY((nmfk::residual_sq<float, uint8_t>((const uint8_t*)pb.Alp, pb.lda, m, n, w.W,
+                                                 w.Ht, KP, w.obj_part, st)));
   } else {
     HIP_TRY((nmfk::residual_sq<T, T>(pb.A, pb.lda, m, n, w.W, w.Ht, KP, w.obj_part, st)));
   }
@@ -410,7 +443,10 @@ nmf_status norm_sq_A(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, Work
     }
     return NMF_EINVAL;
   }
-  if (pb.Ab) HIP_TRY(nmfk::sumsq<uint16_t>(pb.Ab, pb.lda, m, n, w.obj_part, st));
+  if (pb.lp == NMF_BF16)
+    HIP_TRY(nmfk::sumsq<uint16_t>((const uint16_t*)pb.Alp, pb.lda, m, n, w.obj_part, st));
+  else if (pb.lp == NMF_FP8_E4M3)
+    HIP_TRY(nmfk::sumsq<uint8_t>((const uint8_t*)pb.Alp, pb.lda, m, n, w.obj_part, st));
   else HIP_TRY(nmfk::sumsq<T>(pb.A, pb.lda, m, n, w.obj_part, st));
   HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, nmfk::sumsq_partials<T>(m, n), (const T*)nullptr,
                                  (const T*)nullptr, 0, (const double*)nullptr, w.normA, st));
@@ -466,8 +502,8 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   }
   // Transposed factor copies for the dense products (read with 16-byte loads,
   // so their rows must stay 16-byte aligned).
-  const bool tH = !pb.sparse && !pb.Ab && (n * (int64_t)sizeof(T)) % 16 == 0;
-  const bool tW = !pb.sparse && !pb.Ab && (m * (int64_t)sizeof(T)) % 16 == 0;
+  const bool tH = !pb.sparse && !pb.lp && (n * (int64_t)sizeof(T)) % 16 == 0;
+  const bool tW = !pb.sparse && !pb.lp && (m * (int64_t)sizeof(T)) % 16 == 0;
   if (tH && o->iters > 0) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
@@ -596,29 +632,74 @@ nmf_status transposed_copy(nmf_ctx* ctx, const T* A, int64_t lda, int64_t m, int
   return NMF_OK;
 }
 
-// Scratch for bfloat16 products: the packed factor and the split partials.
-struct Bf16Plan { int64_t fb_elems, part_elems; };
-Bf16Plan bf16_plan(int64_t m, int64_t n, int KP) {
-  Bf16Plan p;
-  p.fb_elems = (int64_t)KP * round_up(std::max(m, n), 8);
-  const int64_t sp = nmfk::gemm_bf16_splits(m, n), sr = nmfk::gemm_bf16_splits(n, m);
+// Scratch for reduced-precision products: the packed factor, the split
+// partials and the FP8 column scales.
+struct LpPlan { int64_t fb_bytes, part_elems; };
+LpPlan lp_plan(int lp, int64_t m, int64_t n, int KP) {
+  LpPlan p;
+  const int64_t esize = lp == NMF_FP8_E4M3 ? 1 : 2;
+  p.fb_bytes = (int64_t)KP * round_up(std::max(m, n), lp_align(lp)) * esize;
+  const int64_t sp = nmfk::gemm_lp_splits(m, n), sr = nmfk::gemm_lp_splits(n, m);
   p.part_elems = std::max<int64_t>(sp > 1 ? sp * m * KP : 0, sr > 1 ? sr * n * KP : 0);
   return p;
 }
 
-// Ab (nullable): A as bfloat16 bits (then A is null and T is float).
+// Carves the reduced-precision scratch and points pb at it (after ensure_ws).
+struct LpOffsets { size_t fb, fscale, fmax; };
+LpOffsets lp_carve(Carve& cv, const LpPlan& p, int KP) {
+  LpOffsets o;
+  o.fb = cv.take<uint8_t>(p.fb_bytes);
+  o.fscale = cv.take<float>(KP);
+  o.fmax = cv.take<unsigned>(KP);
+  return o;
+}
+
+// Points pb at a reduced-precision A and its scratch; with want_t, also
+// makes the transposed copy that A^T W streams.
+nmf_status lp_bind(nmf_ctx* ctx, Prob<float>& pb, int lp, const void* Alp, int64_t lda, int64_t m,
+                   int64_t n, const LpOffsets& lo, bool want_t) {
+  pb.lp = lp;
+  pb.Alp = Alp;
+  pb.lda = lda;
+  pb.fb = at<uint8_t>(ctx, lo.fb);
+  pb.fscale = at<float>(ctx, lo.fscale);
+  pb.fmax = at<unsigned>(ctx, lo.fmax);
+  pb.ldat = round_up(m, lp_align(lp));
+  if (!want_t) return NMF_OK;
+  nmf_status s;
+  if (lp == NMF_BF16) {
+    const uint16_t* t = nullptr;
+    s = transposed_copy<uint16_t>(ctx, (const uint16_t*)Alp, lda, m, n, pb.ldat, &t);
+    pb.Alpt = t;
+  } else {
+    const uint8_t* t = nullptr;
+    s = transposed_copy<uint8_t>(ctx, (const uint8_t*)Alp, lda, m, n, pb.ldat, &t);
+    pb.Alpt = t;
+  }
+  if (s != NMF_OK) return s;
+  if (!pb.Alpt) return fail(ctx, NMF_ENOMEM, "no room for the transposed reduced-precision copy of A");
+  return NMF_OK;
+}
 template <typename T>
-nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, const uint16_t* Ab,
+nmf_status lp_bind(nmf_ctx* ctx, Prob<T>&, int, const void*, int64_t, int64_t, int64_t,
+                   const LpOffsets&, bool) {
+  return fail(ctx, NMF_EINVAL, "reduced-precision A takes float factors");
+}
+
+// With lp nonzero, Alp is A in that reduced format (A is then null and T is
+// float).
+template <typename T>
+nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int lp, const void* Alp,
                       int64_t lda, int k, const nmf_opts* o, T* W, T* H, double* rel_err,
                       nmf_stats* stats) {
   const int KP = kp_dense(k);
   const bool want_obj = o->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max(nmfk::residual_partials<T>(m, n), nmfk::sumsq_partials<T>(m, n));
-  const Bf16Plan bp = Ab ? bf16_plan(m, n, KP) : Bf16Plan{0, 0};
+  const LpPlan bp = lp ? lp_plan(lp, m, n, KP) : LpPlan{0, 0};
   Carve cv;
   size_t off[17];
   plan_work<T>(m, n, KP, o->iters, obj_np, bp.part_elems, cv, off);
-  const size_t ofb = cv.take<uint16_t>(Ab ? bp.fb_elems : 0);
+  const LpOffsets lo = lp_carve(cv, bp, KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   Work<T> w = bind_work<T>(ctx, off, obj_np);
@@ -626,7 +707,10 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, const uint
   HIP_TRY(hipMemsetAsync(w.status, 0, 4 * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(w.pivots, 0, 2 * sizeof(unsigned long long), st));
   if (o->check_input) {
-    if (Ab) HIP_TRY(nmfk::check_dense<uint16_t>(Ab, lda, m, n, w.status + 1, st));
+    if (lp == NMF_BF16)
+      HIP_TRY(nmfk::check_dense<uint16_t>((const uint16_t*)Alp, lda, m, n, w.status + 1, st));
+    else if (lp == NMF_FP8_E4M3)
+      HIP_TRY(nmfk::check_dense<uint8_t>((const uint8_t*)Alp, lda, m, n, w.status + 1, st));
     else HIP_TRY(nmfk::check_dense<T>(A, lda, m, n, w.status + 1, st));
   }
   Timers tm;
@@ -644,15 +728,8 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, const uint
   Prob<T> pb;
   pb.A = A;
   pb.lda = lda;
-  if (Ab) {
-    pb.Ab = Ab;
-    pb.fb = at<uint16_t>(ctx, ofb);
-    pb.ldat = round_up(m, 8);
-    if (o->iters > 0) {
-      if ((s = transposed_copy<uint16_t>(ctx, Ab, lda, m, n, pb.ldat, &pb.Abt)) != NMF_OK)
-        return s;
-      if (!pb.Abt) return fail(ctx, NMF_ENOMEM, "no room for the transposed bfloat16 copy of A");
-    }
+  if (lp) {
+    if ((s = lp_bind(ctx, pb, lp, Alp, lda, m, n, lo, o->iters > 0)) != NMF_OK) return s;
   } else if (o->iters > 0 && o->transpose_a == 0) {
     if ((s = transposed_copy<T>(ctx, A, lda, m, n, m, &pb.At)) != NMF_OK) return s;
   }
@@ -749,22 +826,21 @@ nmf_status nmf_dense(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const 
   if ((s = check_opts(ctx, opts, k, rel_err != nullptr)) != NMF_OK) return s;
   if (!A || !W || !H) return fail(ctx, NMF_EINVAL, "null A, W or H");
   if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
-  if (dtype != NMF_F32 && dtype != NMF_F64 && dtype != NMF_BF16)
+  if (dtype != NMF_F32 && dtype != NMF_F64 && !is_lp(dtype))
     return fail(ctx, NMF_EINVAL, "unknown dtype");
-  if (dtype == NMF_BF16) {
-    if (lda % 8 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A: lda must be a multiple of 8");
-    if (((uintptr_t)A) % 16 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A must be 16-byte aligned");
+  if (is_lp(dtype)) {
+    if ((s = check_lp_a(ctx, dtype, A, lda)) != NMF_OK) return s;
     if (opts->transpose_a != 0)
-      return fail(ctx, NMF_EINVAL, "bfloat16 A needs its transposed copy (transpose_a 0)");
+      return fail(ctx, NMF_EINVAL, "reduced-precision A needs its transposed copy (transpose_a 0)");
   }
   if ((s = bind_device(ctx)) != NMF_OK) return s;
-  if (dtype == NMF_BF16)
-    return dense_impl<float>(ctx, m, n, nullptr, (const uint16_t*)A, lda, k, opts, (float*)W,
-                             (float*)H, rel_err, stats);
+  if (is_lp(dtype))
+    return dense_impl<float>(ctx, m, n, nullptr, dtype, A, lda, k, opts, (float*)W, (float*)H,
+                             rel_err, stats);
   if (dtype == NMF_F32)
-    return dense_impl<float>(ctx, m, n, (const float*)A, nullptr, lda, k, opts, (float*)W,
+    return dense_impl<float>(ctx, m, n, (const float*)A, 0, nullptr, lda, k, opts, (float*)W,
                              (float*)H, rel_err, stats);
-  return dense_impl<double>(ctx, m, n, (const double*)A, nullptr, lda, k, opts, (double*)W,
+  return dense_impl<double>(ctx, m, n, (const double*)A, 0, nullptr, lda, k, opts, (double*)W,
                             (double*)H, rel_err, stats);
 }
 
@@ -910,31 +986,24 @@ nmf_status dense_prod_impl(nmf_ctx* ctx, bool transA, int64_t m, int64_t n, cons
   return NMF_OK;
 }
 
-nmf_status dense_prod_bf16_impl(nmf_ctx* ctx, bool transA, int64_t m, int64_t n,
-                                const uint16_t* Ab, int64_t lda, int k, const float* F,
-                                int64_t ldf, float* Out) {
+nmf_status dense_prod_lp_impl(nmf_ctx* ctx, bool transA, int lp, int64_t m, int64_t n,
+                              const void* Alp, int64_t lda, int k, const float* F, int64_t ldf,
+                              float* Out) {
   const int KP = kp_dense(k);
   const int64_t frows = transA ? m : n, orows = transA ? n : m;
-  const Bf16Plan bp = bf16_plan(m, n, KP);
+  const LpPlan bp = lp_plan(lp, m, n, KP);
   Carve cv;
   const size_t oF = cv.take<float>(frows * KP);
   const size_t oO = cv.take<float>(orows * KP);
   const size_t oP = cv.take<float>(std::max<int64_t>(bp.part_elems, 1));
-  const size_t oB = cv.take<uint16_t>(bp.fb_elems);
+  const LpOffsets lo = lp_carve(cv, bp, KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   float* Fp = at<float>(ctx, oF);
   float* Op = at<float>(ctx, oO);
   if ((s = pad_any<float>(ctx, F, frows, k, ldf, Fp, KP)) != NMF_OK) return s;
   Prob<float> pb;
-  pb.Ab = Ab;
-  pb.lda = lda;
-  pb.fb = at<uint16_t>(ctx, oB);
-  if (transA) {
-    pb.ldat = round_up(m, 8);
-    if ((s = transposed_copy<uint16_t>(ctx, Ab, lda, m, n, pb.ldat, &pb.Abt)) != NMF_OK) return s;
-    if (!pb.Abt) return fail(ctx, NMF_ENOMEM, "no room for the transposed bfloat16 copy of A");
-  }
+  if ((s = lp_bind(ctx, pb, lp, Alp, lda, m, n, lo, transA)) != NMF_OK) return s;
   s = transA ? product_AtF<float>(ctx, pb, m, n, Fp, nullptr, k, KP, Op, at<float>(ctx, oP))
              : product_AF<float>(ctx, pb, m, n, Fp, nullptr, k, KP, Op, at<float>(ctx, oP));
   if (s != NMF_OK) return s;
@@ -1050,14 +1119,11 @@ static nmf_status dense_prod(nmf_ctx* ctx, bool transA, nmf_dtype dtype, int64_t
   if (!A || !F || !Out) return fail(ctx, NMF_EINVAL, "null A, F or output");
   if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
   if (ldf < k) return fail(ctx, NMF_EINVAL, "ldf < k");
-  if (dtype == NMF_BF16) {
-    if (lda % 8 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A: lda must be a multiple of 8");
-    if (((uintptr_t)A) % 16 != 0) return fail(ctx, NMF_EINVAL, "bfloat16 A must be 16-byte aligned");
-  }
+  if (is_lp(dtype) && (s = check_lp_a(ctx, dtype, A, lda)) != NMF_OK) return s;
   if ((s = bind_device(ctx)) != NMF_OK) return s;
-  if (dtype == NMF_BF16)
-    return dense_prod_bf16_impl(ctx, transA, m, n, (const uint16_t*)A, lda, k, (const float*)F,
-                                ldf, (float*)Out);
+  if (is_lp(dtype))
+    return dense_prod_lp_impl(ctx, transA, dtype, m, n, A, lda, k, (const float*)F, ldf,
+                              (float*)Out);
   if (dtype == NMF_F32)
     return dense_prod_impl<float>(ctx, transA, m, n, (const float*)A, lda, k, (const float*)F,
                                   ldf, (float*)Out);
@@ -1171,9 +1237,11 @@ nmf_status nmf_dense_relerr(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
     pb.lda = lda;
     return relerr_impl<double>(ctx, pb, m, n, k, (const double*)W, (const double*)Ht, out);
   }
-  if (dtype == NMF_BF16) {
+  if (is_lp(dtype)) {
+    if ((s = check_lp_a(ctx, dtype, A, lda)) != NMF_OK) return s;
     Prob<float> pb;
-    pb.Ab = (const uint16_t*)A;
+    pb.lp = dtype;
+    pb.Alp = A;
     pb.lda = lda;
     return relerr_impl<float>(ctx, pb, m, n, k, (const float*)W, (const float*)Ht, out);
   }

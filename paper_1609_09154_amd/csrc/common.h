@@ -85,14 +85,23 @@ __device__ __forceinline__ V16<T> load16_stream(const T* p) {
   return r;
 }
 
-// bfloat16 values are carried as their 16 bits (uint16_t) outside the
-// matrix-core operands. to_double widens any stored element type.
+// bfloat16 and FP8 E4M3 values are carried as their bits (uint16_t, uint8_t)
+// outside the matrix-core operands. to_double widens any stored element type.
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t b) {
   return __uint_as_float((unsigned)b << 16);
+}
+// E4M3: exponent field e (bias 7), fraction f: (8 + f) 2^(e - 10) for e > 0,
+// f 2^-9 for e = 0; all ones (S.1111.111) is NaN.
+__device__ __forceinline__ float fp8_e4m3_bits_to_float(uint8_t b) {
+  const int e = (b >> 3) & 15, f = b & 7;
+  float v = e ? ldexpf((float)(8 + f), e - 10) : ldexpf((float)f, -9);
+  if (e == 15 && f == 7) v = __builtin_nanf("");
+  return (b & 0x80) ? -v : v;
 }
 __device__ __forceinline__ double to_double(float x) { return (double)x; }
 __device__ __forceinline__ double to_double(double x) { return x; }
 __device__ __forceinline__ double to_double(uint16_t x) { return (double)bf16_bits_to_float(x); }
+__device__ __forceinline__ double to_double(uint8_t x) { return (double)fp8_e4m3_bits_to_float(x); }
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }

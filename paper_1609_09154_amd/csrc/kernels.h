@@ -38,17 +38,27 @@ template <typename T>
 hipError_t reduce_splits(const T* part, int splits, int64_t dsplit, int64_t M, int N,
                          int64_t ldd, T* D, int64_t ldp, hipStream_t st);
 
-// BF16 products: D (M x N float, ld ldd) = X Y^T for X (M x K) and Y (N x K)
-// bfloat16 bits, K contiguous in both (ldx, ldy multiples of 8, rows 16-byte
-// aligned), N a multiple of 16 up to 128, float accumulation. `part` must
-// hold gemm_bf16_splits(M, K) * M * N floats when that count exceeds 1.
+// Reduced-precision products: D (M x N float, ld ldd) = X Y^T for X (M x K)
+// and Y (N x K) stored as bfloat16 bits (uint16_t) or FP8 E4M3 bits
+// (uint8_t), K contiguous in both (rows 16-byte aligned, ldx and ldy whole
+// multiples of 16 bytes), N a multiple of 16 up to 128, float accumulation.
+// The FP8 form multiplies output column j by colscale[j]. `part` must hold
+// gemm_lp_splits(M, K) * M * N floats when that count exceeds 1.
 hipError_t gemm_bf16_nt(const uint16_t* X, int64_t ldx, const uint16_t* Y, int64_t ldy, float* D,
                         int64_t ldd, int64_t M, int N, int64_t K, float* part, hipStream_t st);
-int64_t gemm_bf16_splits(int64_t M, int64_t K);
+hipError_t gemm_fp8_nt(const uint8_t* X, int64_t ldx, const uint8_t* Y, int64_t ldy,
+                       const float* colscale, float* D, int64_t ldd, int64_t M, int N, int64_t K,
+                       float* part, hipStream_t st);
+int64_t gemm_lp_splits(int64_t M, int64_t K);
 // Ft (KP x rows, row pitch ldt) = F^T rounded to bfloat16 (nearest even), for
 // F rows x KP float.
 hipError_t pack_bf16_t(const float* F, int64_t rows, int KP, uint16_t* Ft, int64_t ldt,
                        hipStream_t st);
+// Ft = FP8 E4M3 of F^T with column j divided by colscale[j] = 2^p_j, the
+// smallest power of two with max_r |F[r][j]| <= 448 2^p_j (1 for a zero
+// column); round to nearest even. maxbits: KP unsigned of scratch. KP <= 128.
+hipError_t pack_fp8_t(const float* F, int64_t rows, int KP, uint8_t* Ft, int64_t ldt,
+                      float* colscale, unsigned* maxbits, hipStream_t st);
 
 // Local updates on rows x KP row-major factors (leading dimension KP); k is
 // the true rank, entries k..KP-1 are zero padding and stay zero.
@@ -71,7 +81,7 @@ hipError_t pad_rows(const T* src, int64_t rows, int k, T* dst, int KP, hipStream
 template <typename T>
 hipError_t unpad_rows(const T* src, int64_t rows, int k, int KP, T* dst, hipStream_t st);
 // At (n x m, row pitch ldt >= m) = A^T for A (m x n, lda). T is float,
-// double or uint16_t (bfloat16 bits).
+// double, uint16_t (bfloat16 bits) or uint8_t (FP8 bits).
 template <typename T>
 hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, int64_t ldt,
                           hipStream_t st);
@@ -88,8 +98,8 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
 // (capacity given by *_partials) and a final reduce sums them in order.
 template <typename T>
 int64_t residual_partials(int64_t m, int64_t n);
-// residual_sq: A is stored as TA (T, or uint16_t bfloat16 bits with float
-// factors). sumsq and check_dense take float, double or uint16_t A.
+// residual_sq: A is stored as TA (T, or with float factors uint16_t bfloat16
+// bits or uint8_t FP8 E4M3 bits). sumsq and check_dense take all four.
 template <typename T, typename TA = T>
 hipError_t residual_sq(const TA* A, int64_t lda, int64_t m, int64_t n, const T* W, const T* Ht,
                        int KP, double* partial, hipStream_t st);

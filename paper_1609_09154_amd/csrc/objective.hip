@@ -291,13 +291,15 @@ hipError_t check_dense(const T* A, int64_t lda, int64_t m, int64_t n, int* flag,
 INST(float)
 INST(double)
 #undef INST
-template hipError_t residual_sq<float, uint16_t>(const uint16_t*, int64_t, int64_t, int64_t,
-                                                 const float*, const float*, int, double*,
-                                                 hipStream_t);
-template int64_t sumsq_partials<uint16_t>(int64_t, int64_t);
-template hipError_t sumsq<uint16_t>(const uint16_t*, int64_t, int64_t, int64_t, double*,
-                                    hipStream_t);
-template hipError_t check_dense<uint16_t>(const uint16_t*, int64_t, int64_t, int64_t, int*,
-                                          hipStream_t);
+#define INST_LP(TA)                                                                         \
+  template hipError_t residual_sq<float, TA>(const TA*, int64_t, int64_t, int64_t,          \
+                                             const float*, const float*, int, double*,       \
+                                             hipStream_t);                                   \
+  template int64_t sumsq_partials<TA>(int64_t, int64_t);                                    \
+  template hipError_t sumsq<TA>(const TA*, int64_t, int64_t, int64_t, double*, hipStream_t); \
+  template hipError_t check_dense<TA>(const TA*, int64_t, int64_t, int64_t, int*, hipStream_t);
+INST_LP(uint16_t)
+INST_LP(uint8_t)
+#undef INST_LP
 
 }  // namespace nmfk

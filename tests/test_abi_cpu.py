@@ -74,6 +74,19 @@ def test_dense_argument_errors(hctx, kw):
     assert _lib.lib().nmf_last_error(hctx)
 
 
+@pytest.mark.parametrize("dtype,unit", [(_lib.NMF_BF16, 8), (_lib.NMF_FP8_E4M3, 16)])
+def test_reduced_precision_A_checks(hctx, dtype, unit):
+    # a row pitch of whole 16-byte units and an aligned A reach the device stage
+    assert dense(hctx, n=8, lda=2 * unit, dtype=dtype) == EDEVICE
+    assert dense(hctx, n=8, lda=unit + unit // 2, dtype=dtype) == EINVAL
+    assert dense(hctx, n=8, lda=2 * unit, dtype=dtype, A=ctypes.c_void_p(4096 + 8)) == EINVAL
+    o = _lib.default_opts(algo="hals", iters=2, transpose_a=-1)
+    assert dense(hctx, n=8, lda=2 * unit, dtype=dtype, opts=o) == EINVAL
+    L = _lib.lib()
+    assert L.nmf_dense_AF(hctx, dtype, 10, 8, P, unit + 1, 3, P, 3, P) == EINVAL
+    assert L.nmf_dense_AF(hctx, dtype, 10, 8, P, 2 * unit, 3, P, 3, P) == EDEVICE
+
+
 def test_dense_bad_options(hctx):
     assert dense(hctx, opts=_lib.default_opts(algo=3)) == EINVAL
     assert dense(hctx, opts=_lib.default_opts(iters=-1)) == EINVAL
