@@ -276,19 +276,44 @@ __global__ __launch_bounds__(256) void pack_bf16_t_kernel(const float* __restric
 }
 
 // FP8 packing, pass 1: maxbits[j] = bits of max_r |F[r][j]| (non-negative
-// floats order like their bit patterns), j < KP <= 128. maxbits starts at 0.
+// floats order like their bit patterns), KP a multiple of 4 up to 128;
+// maxbits starts at 0. Thread (ty, c) of a block reads 16-byte chunks c of
+// rows ty, ty + R, ... of the block's slices (R = 256 / (KP / 4) rows per
+// pass, four passes in flight), the block reduces its maxima in LDS and
+// raises each column's word once.
 __global__ __launch_bounds__(256) void colmax_kernel(const float* __restrict__ F, int64_t rows,
                                                      int KP, unsigned* __restrict__ maxbits) {
-  const int lanes = 256 / KP;  // threads per column in a block
-  if ((int)threadIdx.x >= lanes * KP) return;
-  const int j = threadIdx.x % KP;
-  unsigned mx = 0;
-  for (int64_t r = (int64_t)blockIdx.x * lanes + threadIdx.x / KP; r < rows;
-       r += (int64_t)gridDim.x * lanes) {
-    const float v = F[r * KP + j];
-    mx = max(mx, __float_as_uint(fabsf(v)));
+  __shared__ unsigned part[256 * 4];
+  const int q = KP / 4;           // float4 chunks per row
+  const int R = 256 / q;          // rows per pass
+  const int tid = threadIdx.x;
+  const int c = tid % q, ty = tid / q;
+  unsigned mx[4] = {0u, 0u, 0u, 0u};
+  if (ty < R) {
+    const int64_t stride = (int64_t)gridDim.x * R;
+    for (int64_t r0 = (int64_t)blockIdx.x * R + ty; r0 < rows; r0 += 4 * stride) {
+      f32x4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t r = r0 + u * stride;
+        v[u] = r < rows ? *reinterpret_cast<const f32x4*>(F + r * KP + 4 * c)
+                        : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) mx[e] = max(mx[e], __float_as_uint(fabsf(v[u][e])));
+    }
   }
-  if (mx) atomicMax(&maxbits[j], mx);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) part[tid * 4 + e] = mx[e];
+  __syncthreads();
+  if (tid < KP) {
+    // column tid is element tid % 4 of chunk tid / 4, held by threads ty q + tid / 4
+    unsigned m = 0;
+    for (int t = 0; t < R; ++t) m = max(m, part[(t * q + tid / 4) * 4 + tid % 4]);
+    if (m) atomicMax(&maxbits[tid], m);
+  }
 }
 
 __global__ void zero_u32_kernel(unsigned* __restrict__ p, int n) {
@@ -344,11 +369,11 @@ hipError_t pack_bf16_t(const float* F, int64_t rows, int KP, uint16_t* Ft, int64
 
 hipError_t pack_fp8_t(const float* F, int64_t rows, int KP, uint8_t* Ft, int64_t ldt,
                       float* colscale, unsigned* maxbits, hipStream_t st) {
-  if (KP < 1 || KP > 128) return hipErrorInvalidValue;
+  if (KP < 4 || KP > 128 || KP % 4 != 0) return hipErrorInvalidValue;
   zero_u32_kernel<<<1, 128, 0, st>>>(maxbits, KP);
   if (rows > 0) {
-    const int lanes = 256 / KP;
-    const int64_t want = cdiv(rows, lanes), blocks = want < 2048 ? want : 2048;
+    const int R = 256 / (KP / 4);
+    const int64_t want = cdiv(rows, 4 * R), blocks = want < 1024 ? want : 1024;
     colmax_kernel<<<(unsigned)blocks, 256, 0, st>>>(F, rows, KP, maxbits);
     dim3 grid((unsigned)cdiv(rows, 32), (unsigned)cdiv(KP, 32));
     pack_fp8_t_kernel<<<grid, 256, 0, st>>>(F, rows, KP, maxbits, Ft, ldt, colscale);

@@ -332,32 +332,39 @@ __global__ __launch_bounds__(256) void transpose_full_kernel(const T* __restrict
   }
 }
 
-// Byte matrices (FP8 A) move 4-byte words both ways: a 128 x 128 tile is
-// read as 32 words per row and written as 32 words per output row, each
-// output word gathering one byte from four consecutive input rows. Needs
-// lda, ldt and n multiples of 4 and 4-byte aligned pointers, so that a word
-// read at a column below n and a word written at a row below m stay inside
-// the row pitches.
-__global__ __launch_bounds__(256) void transpose_u8_kernel(const uint8_t* __restrict__ A,
-                                                           int64_t lda, int64_t m, int64_t n,
-                                                           uint8_t* __restrict__ At, int64_t ldt) {
-  __shared__ uint32_t tile[128][33];
+// Byte and 16-bit matrices (FP8 and bfloat16 A) move 4-byte words both
+// ways: a 128 x 128 tile is read as whole words of each row and written as
+// whole words of each output row, an output word gathering one element from
+// each of 4 / sizeof(T) consecutive input rows. Needs lda, ldt and n
+// multiples of the elements per word and 4-byte aligned pointers, so that a
+// word read at a column below n and a word written at a row below m stay
+// inside the row pitches.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_words_kernel(const T* __restrict__ A,
+                                                              int64_t lda, int64_t m, int64_t n,
+                                                              T* __restrict__ At, int64_t ldt) {
+  constexpr int EPW = 4 / (int)sizeof(T);   // elements per word
+  constexpr int WPR = 128 / EPW;            // words per tile row
+  constexpr int RPP = 256 / WPR;            // rows per pass
+  constexpr int EB = 8 * (int)sizeof(T);    // bits per element
+  constexpr uint32_t MASK = (1u << EB) - 1u;
+  __shared__ uint32_t tile[128][WPR + 1];
   const int64_t c0 = (int64_t)blockIdx.x * 128, r0 = (int64_t)blockIdx.y * 128;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int i = ty; i < 128; i += 8) {
-    const int64_t r = r0 + i, c = c0 + 4 * tx;
+  const int tx = threadIdx.x % WPR, ty = threadIdx.x / WPR;
+  for (int i = ty; i < 128; i += RPP) {
+    const int64_t r = r0 + i, c = c0 + EPW * tx;
     tile[i][tx] = (r < m && c < n)
                       ? __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(A + r * lda + c))
                       : 0u;
   }
   __syncthreads();
-  for (int j = ty; j < 128; j += 8) {
-    const int64_t c = c0 + j, r = r0 + 4 * tx;
+  for (int j = ty; j < 128; j += RPP) {
+    const int64_t c = c0 + j, r = r0 + EPW * tx;
     if (c < n && r < m) {
-      const int w = j >> 2, sh = 8 * (j & 3);
+      const int w = j / EPW, sh = EB * (j % EPW);
       uint32_t out = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) out |= ((tile[4 * tx + b][w] >> sh) & 0xffu) << (8 * b);
+      for (int b = 0; b < EPW; ++b) out |= ((tile[EPW * tx + b][w] >> sh) & MASK) << (EB * b);
       *reinterpret_cast<uint32_t*>(At + c * ldt + r) = out;
     }
   }
@@ -366,11 +373,12 @@ __global__ __launch_bounds__(256) void transpose_u8_kernel(const uint8_t* __rest
 template <typename T>
 hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, int64_t ldt,
                           hipStream_t st) {
-  if constexpr (sizeof(T) == 1) {
-    if (lda % 4 == 0 && ldt % 4 == 0 && n % 4 == 0 && (uintptr_t)A % 4 == 0 &&
+  if constexpr (sizeof(T) < 4) {
+    constexpr int EPW = 4 / (int)sizeof(T);
+    if (lda % EPW == 0 && ldt % EPW == 0 && n % EPW == 0 && (uintptr_t)A % 4 == 0 &&
         (uintptr_t)At % 4 == 0) {
       dim3 grid((unsigned)cdiv(n, 128), (unsigned)cdiv(m, 128));
-      transpose_u8_kernel<<<grid, 256, 0, st>>>((const uint8_t*)A, lda, m, n, (uint8_t*)At, ldt);
+      transpose_words_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, At, ldt);
       return NMF_LAUNCH_CHECK();
     }
   }

@@ -153,25 +153,36 @@ def test_csr_2e20_abpp_sampled_parity():
     assert errs[1] < errs[0]
 
 
-def test_bf16_131072x65536_k100_hals_one_iteration_full_parity():
-    """Precision workload at full size: A = W0 H0 + |N(0, 0.01)| stored in
-    bfloat16 (131072 x 65536, 17.2 GB), k = 100, one HALS iteration with the
-    products on the BF16 matrix cores. The oracle repeats the iteration in
-    FP64 on the same bfloat16 values, rounding the product's factor operand
-    to bfloat16 as the method does (oracle.round_bf16), from host copies of
-    A streamed in row blocks."""
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_lowp_131072x65536_k100_hals_one_iteration_full_parity(fmt):
+    """Precision workloads at full size: A = W0 H0 + |N(0, 0.01)| stored in
+    bfloat16 (131072 x 65536, 17.2 GB) or FP8 E4M3 (8.6 GB), k = 100, one
+    HALS iteration with the products on the BF16 or FP8 matrix cores. The
+    oracle repeats the iteration in FP64 on the same stored values, rounding
+    the product's factor operand as the method does (oracle.round_bf16, or
+    oracle.round_fp8_scaled with its per-column scales taken over the whole
+    factor), from host copies of A streamed in row blocks."""
     import torch
 
     m, n, k = 131072, 65536, 100
     dev = torch.device("cuda:0")
-    step("fullsize bf16: generate A 131072 x 65536 bf16")
-    A = planted_dense_torch(m, n, 100, sigma=0.01, seed=1609, device=dev, dtype=torch.bfloat16)
+    step("fullsize %s: generate A 131072 x 65536" % fmt)
+    if fmt == "bf16":
+        A = planted_dense_torch(m, n, 100, sigma=0.01, seed=1609, device=dev,
+                                dtype=torch.bfloat16)
+        round_H, round_W = oracle.round_bf16, oracle.round_bf16
+    else:
+        A = planted_dense_torch(m, n, 100, sigma=0.01, seed=1609, device=dev,
+                                dtype=torch.float32).to(torch.float8_e4m3fn)
+        torch.cuda.synchronize()
+        round_H = lambda X: oracle.round_fp8_scaled(X, 0)   # noqa: E731  (k x n)
+        round_W = lambda X: oracle.round_fp8_scaled(X, 1)   # noqa: E731  (m x k)
     W0n, H0n = init_factors(m, n, k, seed=9154)
     W0n = W0n.astype(np.float32)
     H0n = H0n.astype(np.float32)
     W = torch.from_numpy(W0n).to(dev)
     H = torch.from_numpy(H0n).to(dev)
-    step("fullsize bf16: one HALS iteration on the GPU")
+    step("fullsize %s: one HALS iteration on the GPU" % fmt)
     errs, st = nmf.nmf_dense(A, W, H, algo="hals", iters=1, objective=True)
     torch.cuda.synchronize()
     Wg, Hg = host(W).astype(np.float64), host(H).astype(np.float64)
@@ -180,14 +191,14 @@ def test_bf16_131072x65536_k100_hals_one_iteration_full_parity():
         for r0 in range(0, m, ROWS):
             r1 = min(m, r0 + ROWS)
             if r0 % (8 * ROWS) == 0:
-                step("fullsize bf16 oracle: %s, rows %d of %d" % (what, r0, m))
-            yield r0, r1, A[r0:r1].cpu().to(torch.float64).numpy()
+                step("fullsize %s oracle: %s, rows %d of %d" % (fmt, what, r0, m))
+            yield r0, r1, A[r0:r1].float().cpu().to(torch.float64).numpy()
 
-    step("fullsize bf16: oracle iteration from host blocks of A")
+    step("fullsize %s: oracle iteration from host blocks of A" % fmt)
     W0 = W0n.astype(np.float64)
     H0 = H0n.astype(np.float64)
     Q = oracle.gram_fixed_H(H0)
-    H0r = oracle.round_bf16(H0)
+    H0r = round_H(H0)
     P = np.empty((m, k))
     normA = 0.0
     res0 = 0.0
@@ -197,7 +208,7 @@ def test_bf16_131072x65536_k100_hals_one_iteration_full_parity():
         res0 += oracle.objective_sq(Ab, W0[r0:r1], H0)
     W1, Hs = oracle.hals_update_W(W0, H0, Q, P)
     S = oracle.gram_fixed_W(W1)
-    W1r = oracle.round_bf16(W1)
+    W1r = round_W(W1)
     R = np.zeros((k, n))
     for r0, r1, Ab in blocks("W^T A"):
         R += oracle.product_WtA(Ab, W1r[r0:r1])
@@ -209,8 +220,8 @@ def test_bf16_131072x65536_k100_hals_one_iteration_full_parity():
     d_e = rel_diff(errs, e_ref)
     d_w = float(np.max(np.abs(Wg - W1)) / np.abs(W1).max())
     d_h = float(np.max(np.abs(Hg - H1)) / np.abs(H1).max())
-    print("fullsize bf16 HALS: rel err gpu %s oracle %s; objective diff %.2e, "
-          "max |dW|/max|W| %.2e, max |dH|/max|H| %.2e" % (errs, e_ref, d_e, d_w, d_h))
+    print("fullsize %s HALS: rel err gpu %s oracle %s; objective diff %.2e, "
+          "max |dW|/max|W| %.2e, max |dH|/max|H| %.2e" % (fmt, errs, e_ref, d_e, d_w, d_h))
     assert d_e <= 1e-4
     assert d_w <= 1e-2 and d_h <= 1e-2
 
