@@ -30,4 +30,5 @@ from .nmf import (  # noqa: F401
     MU_EPS, gradients, projected_gradient_sq, projected_gradient_norm, run_until,
 )
 from .bpp import bpp_nnls, passive_solve  # noqa: F401
-from .autodiff import mu_unrolled_forward, mu_unrolled_vjp  # noqa: F401
+from .autodiff import (mu_unrolled_forward, mu_unrolled_vjp, hals_unrolled_forward,  # noqa: F401
+                       hals_unrolled_vjp)
