@@ -62,6 +62,9 @@ WORKLOADS = {
     "dense-8192x4096-k64-mu50-autograd-f32": dict(m=8192, n=4096, k=64, k_true=64, algo="mu",
                                                   dtype="f32", autograd=True, iters=50,
                                                   ckpt_every=10),
+    "dense-8192x4096-k64-hals50-autograd-f32": dict(m=8192, n=4096, k=64, k_true=64,
+                                                    algo="hals", dtype="f32", autograd=True,
+                                                    iters=50, ckpt_every=10),
 }
 
 
@@ -299,13 +302,14 @@ def run_lowp(args, wl):
 
 
 def run_autograd(args, wl):
-    """Differentiation workload: one step = 50 unrolled MU iterations
-    forward (checkpoints every 10) plus the backward pass to dL/dA, dL/dW0,
-    dL/dH0 for L = <GW, W_T> + <GH, H_T> (fixed random GW, GH), all in the
-    library. value is steps/s; the forward alone and the backward alone are
-    reported beside it. roofline: the large products of forward, recompute
-    and adjoint (8 per iteration, 2 m n k flops each) plus the rank-2k dL/dA
-    update (4 m n k flops per iteration), against the FP32 matrix peak."""
+    """Differentiation workloads: one step = 50 unrolled MU or HALS
+    iterations forward (checkpoints every 10) plus the backward pass to
+    dL/dA, dL/dW0, dL/dH0 for L = <GW, W_T> + <GH, H_T> (fixed random GW,
+    GH), all in the library. value is steps/s; the forward alone and the
+    backward alone are reported beside it. roofline: the large products of
+    forward, recompute and adjoint (6 per iteration: 2 of each, 2 m n k flops
+    each) plus the rank-2k dL/dA update (4 m n k flops per iteration),
+    against the FP32 matrix peak."""
     import numpy as np
     import torch
 
@@ -323,10 +327,16 @@ def run_autograd(args, wl):
     GW = torch.from_numpy(uniform((m, k), seed=11) - 0.5).to(dev, torch.float32)
     GH = torch.from_numpy(uniform((k, n), seed=12) - 0.5).to(dev, torch.float32)
 
+    algo = wl["algo"]
+
     def fwd():
+        if algo == "hals":
+            return nmf.nmf_hals_unrolled_forward(A, W0, H0, T, ckpt_every=every)
         return nmf.nmf_mu_unrolled_forward(A, W0, H0, T, ckpt_every=every)
 
     def bwd(ck):
+        if algo == "hals":
+            return nmf.nmf_hals_unrolled_backward(A, ck, GW, GH, T, ckpt_every=every)
         return nmf.nmf_mu_unrolled_backward(A, ck, GW, GH, T, ckpt_every=every)
 
     print("[bench] warmup %d" % args.warmup, file=sys.stderr, flush=True)
@@ -347,11 +357,11 @@ def run_autograd(args, wl):
         tf += b - a
         tb += time.perf_counter() - b
     elapsed = time.perf_counter() - t0
-    flops = (8.0 * 2.0 * m * n * k + 4.0 * m * n * k) * T
+    flops = (6.0 * 2.0 * m * n * k + 4.0 * m * n * k) * T
     achieved = flops / (elapsed / args.steps) / 1e12
     out = {
-        "metric": "unrolled-MU layer steps/s (forward 50 MU iterations + backward to A, W0, H0; "
-                  "A 8192x4096 fp32, k=64)",
+        "metric": "unrolled-%s layer steps/s (forward %d %s iterations + backward to A, W0, "
+                  "H0; A %dx%d fp32, k=%d)" % (algo.upper(), T, algo.upper(), m, n, k),
         "value": round(args.steps / elapsed, 3), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1000.0 * elapsed / args.steps, 3), "higher_is_better": True,
@@ -360,7 +370,7 @@ def run_autograd(args, wl):
                    "ckpt_every": every, "parallelism": "single-gpu"},
         "ms_forward": round(1000.0 * tf / args.steps, 3),
         "ms_backward": round(1000.0 * tb / args.steps, 3),
-        "forward_mu_iters_per_s": round(T * args.steps / tf, 1),
+        "forward_iters_per_s": round(T * args.steps / tf, 1),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                      "traffic": None,

@@ -312,6 +312,30 @@ nmf_status nmf_mu_unrolled_backward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
                                     const void* gH, void* gA, int64_t ldga,
                                     void* gW0, void* gH0);
 
+/* ---- Differentiation through unrolled HALS iterations -----------------------
+ * The map (A, W_0, H_0) -> (W_T, H_T) of T iterations of Algorithm 1 with the
+ * HALS rules of Section 4.2, Eq. (5), exactly as nmf_dense runs them (the
+ * exact block minimiser of each column, the columns of W normalised after
+ * the sweep with H rescaled to compensate, then the sweep over the rows of
+ * H), and its reverse-mode gradient for any scalar loss of (W_T, H_T). The
+ * map is piecewise smooth: the gradient is that of the piece the forward
+ * pass is on (an entry clipped to zero carries none; a column with a zero
+ * Gram diagonal, which the sweep skips, passes its gradient through). Dense
+ * A, NMF_F32 or NMF_F64, 1 <= k <= 64. The checkpoint buffer has
+ * nmf_mu_ckpt_elems(m, n, k, T, c) elements, as for MU, and the backward
+ * pass must be given the same m, n, A, k, T and c as the forward pass. */
+nmf_status nmf_hals_unrolled_forward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
+                                     int64_t n, const void* A, int64_t lda, int k,
+                                     int iters, int ckpt_every, void* W, void* H,
+                                     void* ckpt);
+
+/* As nmf_mu_unrolled_backward, for the HALS map. */
+nmf_status nmf_hals_unrolled_backward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m,
+                                      int64_t n, const void* A, int64_t lda, int k,
+                                      int iters, int ckpt_every, const void* ckpt,
+                                      const void* gW, const void* gH, void* gA,
+                                      int64_t ldga, void* gW0, void* gH0);
+
 #ifdef __cplusplus
 }
 #endif

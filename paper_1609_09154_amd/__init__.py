@@ -17,6 +17,7 @@ from ._lib import (NMF_ABPP, NMF_BF16, NMF_F32, NMF_F64, NMF_FP8_E4M3, NMF_HALS,
 
 __all__ = ["Context", "NMFError", "nmf_dense", "nmf_csr", "nmf_gram", "nmf_dense_AF",
            "nmf_mu_unrolled_forward", "nmf_mu_unrolled_backward", "mu_unrolled",
+           "nmf_hals_unrolled_forward", "nmf_hals_unrolled_backward", "hals_unrolled",
            "nmf_projected_gradient_sq",
            "nmf_dense_AtF", "nmf_csr_AF", "nmf_csr_transpose", "nmf_update",
            "nmf_hals_normalize", "nmf_dense_relerr", "nmf_csr_relerr", "library_path"]
@@ -378,6 +379,90 @@ def nmf_mu_unrolled_backward(A, ckpt, gW, gH, iters, eps=1e-16, ckpt_every=10, w
         ckpt_every, _dev(ckpt, "ckpt"), _dev(gW, "gW"), _dev(gH, "gH"),
         _dev(gA, "gA") if gA is not None else None, n, _dev(gW0, "gW0"), _dev(gH0, "gH0")))
     return gA, gW0, gH0
+
+
+def nmf_hals_unrolled_forward(A, W0, H0, iters, ckpt_every=10, want_ckpt=True, ctx=None):
+    """T = iters HALS iterations from (W0, H0) (not modified), as nmf_dense
+    runs them. Returns (W_T, H_T, ckpt) where ckpt (or None) feeds
+    nmf_hals_unrolled_backward."""
+    torch = _torch()
+    m, n = A.shape
+    k = W0.shape[1]
+    _dev(A, "A")
+    _dev(W0, "W0", dtype=A.dtype, shape=(m, k))
+    _dev(H0, "H0", dtype=A.dtype, shape=(k, n))
+    W = W0.clone()
+    H = H0.clone()
+    ckpt = None
+    if want_ckpt:
+        ne = _lib.lib().nmf_mu_ckpt_elems(m, n, k, iters, ckpt_every)
+        if ne < 0:
+            raise ValueError("invalid sizes for the unrolled HALS gradient")
+        ckpt = torch.empty(max(ne, 1), dtype=A.dtype, device=A.device)
+    c = _ctx(ctx, A.device.index or 0)
+    c.check(_lib.lib().nmf_hals_unrolled_forward(
+        c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0), k, iters, ckpt_every,
+        _dev(W, "W"), _dev(H, "H"), _dev(ckpt, "ckpt") if ckpt is not None else None))
+    return W, H, ckpt
+
+
+def nmf_hals_unrolled_backward(A, ckpt, gW, gH, iters, ckpt_every=10, want_gA=True, ctx=None):
+    """(dL/dA or None, dL/dW0, dL/dH0) of the HALS map from dL/dW_T = gW and
+    dL/dH_T = gH."""
+    torch = _torch()
+    m, n = A.shape
+    k = gW.shape[1]
+    _dev(gW, "gW", dtype=A.dtype, shape=(m, k))
+    _dev(gH, "gH", dtype=A.dtype, shape=(k, n))
+    gA = torch.empty((m, n), dtype=A.dtype, device=A.device) if want_gA else None
+    gW0 = torch.empty((m, k), dtype=A.dtype, device=A.device)
+    gH0 = torch.empty((k, n), dtype=A.dtype, device=A.device)
+    c = _ctx(ctx, A.device.index or 0)
+    c.check(_lib.lib().nmf_hals_unrolled_backward(
+        c.handle, _dtype_code(A), m, n, _dev(A, "A"), A.stride(0), k, iters, ckpt_every,
+        _dev(ckpt, "ckpt"), _dev(gW, "gW"), _dev(gH, "gH"),
+        _dev(gA, "gA") if gA is not None else None, n, _dev(gW0, "gW0"), _dev(gH0, "gH0")))
+    return gA, gW0, gH0
+
+
+def _hals_unrolled_function():
+    torch = _torch()
+
+    class HALSUnrolled(torch.autograd.Function):
+        """T unrolled HALS iterations as a differentiable layer: forward and
+        backward both run in the library (checkpoints every ckpt_every
+        iterations, segments recomputed in the backward pass)."""
+
+        @staticmethod
+        def forward(fctx, A, W0, H0, iters, ckpt_every):
+            A, W0, H0 = A.contiguous(), W0.contiguous(), H0.contiguous()
+            W, H, ckpt = nmf_hals_unrolled_forward(A, W0, H0, iters, ckpt_every)
+            fctx.save_for_backward(A, ckpt)
+            fctx.meta = (iters, ckpt_every, W0.shape, H0.shape)
+            return W, H
+
+        @staticmethod
+        def backward(fctx, gW, gH):
+            A, ckpt = fctx.saved_tensors
+            iters, ckpt_every, ws, hs = fctx.meta
+            gW = torch.zeros(ws, dtype=A.dtype, device=A.device) if gW is None else gW.contiguous()
+            gH = torch.zeros(hs, dtype=A.dtype, device=A.device) if gH is None else gH.contiguous()
+            gA, gW0, gH0 = nmf_hals_unrolled_backward(A, ckpt, gW, gH, iters, ckpt_every,
+                                                      want_gA=fctx.needs_input_grad[0])
+            return gA, gW0, gH0, None, None
+
+    return HALSUnrolled
+
+
+_HALS_FN = None
+
+
+def hals_unrolled(A, W0, H0, iters, ckpt_every=10):
+    """Differentiable (W_T, H_T) = T HALS iterations from (W0, H0) on dense A."""
+    global _HALS_FN
+    if _HALS_FN is None:
+        _HALS_FN = _hals_unrolled_function()
+    return _HALS_FN.apply(A, W0, H0, iters, ckpt_every)
 
 
 def _mu_unrolled_function():

@@ -75,6 +75,10 @@ SIGNATURES = {
     "nmf_mu_unrolled_backward": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _int,
                                         ctypes.c_double, _int, _vp, _vp, _vp, _vp, _i64, _vp,
                                         _vp]),
+    "nmf_hals_unrolled_forward": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _int, _int,
+                                         _vp, _vp, _vp]),
+    "nmf_hals_unrolled_backward": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _int, _int,
+                                          _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
 }
 
 

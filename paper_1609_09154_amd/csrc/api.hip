@@ -1475,12 +1475,183 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
   return NMF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Differentiation of T unrolled HALS iterations (Section 4.2, Eq. (5)).
+// ---------------------------------------------------------------------------
+
+// One HALS iteration from (W, Ht) into (Wn, Htn) (which may alias W, Ht) in
+// the order nmf_dense runs it: Q = H H^T, P = A H^T, the W sweep, S = W^T W,
+// the normalisation (W, H and S rescaled; norms into nrm), R = A^T W, the H
+// sweep. Wp and Hc (nullable) receive W after the sweep and H^T after the
+// rescaling, which the backward pass needs.
+template <typename T>
+nmf_status hals_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
+                          const T* W, const T* Ht, T* Wn, T* Htn, T* Wp, T* Hc, T* nrm, T* Q,
+                          T* S, MuWork<T>& w) {
+  hipStream_t st = ctx->stream;
+  nmf_status s;
+  if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part)) != NMF_OK) return s;
+  if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, w.P, w)) != NMF_OK) return s;
+  if (Wn != W) HIP_TRY(hipMemcpyAsync(Wn, W, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(nmfk::hals_rows<T>(Wn, w.P, Q, m, k, KP, st));
+  if (Wp) HIP_TRY(hipMemcpyAsync(Wp, Wn, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
+  if ((s = gram<T>(ctx, Wn, m, KP, S, w.part)) != NMF_OK) return s;
+  if (Htn != Ht) HIP_TRY(hipMemcpyAsync(Htn, Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(nmfk::hals_normalize<T>(Wn, m, Htn, n, S, nrm, k, KP, st));
+  if (Hc) HIP_TRY(hipMemcpyAsync(Hc, Htn, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
+  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, w.R, w)) != NMF_OK) return s;
+  HIP_TRY(nmfk::hals_rows<T>(Htn, w.R, S, n, k, KP, st));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status hals_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t lda, int k,
+                             int iters, int every, T* W, T* H, T* ckpt) {
+  const int KP = kp_dense(k);
+  Carve cv;
+  size_t off[8];
+  mu_plan_common<T>(m, n, KP, cv, off);
+  const size_t onrm = cv.take<T>(KP);
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  MuWork<T> w = mu_bind<T>(ctx, off);
+  T* nrm = at<T>(ctx, onrm);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, st));
+  HIP_TRY(nmfk::transpose_in<T>(H, k, n, w.Ht, KP, st));
+  Prob<T> pb;
+  if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
+  const int64_t slot = (m + n) * KP;
+  for (int t = 0; t < iters; ++t) {
+    if (ckpt && t % every == 0) {
+      T* c = ckpt + (int64_t)(t / every) * slot;
+      HIP_TRY(hipMemcpyAsync(c, w.W, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(c + m * KP, w.Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
+    }
+    s = hals_iteration<T>(ctx, pb, m, n, k, KP, w.W, w.Ht, w.W, w.Ht, nullptr, nullptr, nrm,
+                          w.Q, w.S, w);
+    if (s != NMF_OK) return s;
+  }
+  HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
+  HIP_TRY(nmfk::transpose_out<T>(w.Ht, k, n, KP, H, st));
+  return NMF_OK;
+}
+
+// Reverse pass, per iteration (H step first): the H sweep's adjoint gives
+// dL/dHc and dL/dR (its deltas); R = A^T Wn and S = Wn^T Wn pass them on to
+// Wn and A; the normalisation's adjoint gives dL/dW' and part of dL/dH; the
+// W sweep's adjoint gives dL/dW and dL/dP; P = A H^T and Q = H H^T pass
+// those on to H and A.
+template <typename T>
+nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64_t lda,
+                              int k, int iters, int every, const T* ckpt, const T* gWT,
+                              const T* gHT, T* gA, int64_t ldga, T* gW0, T* gH0) {
+  const int KP = kp_dense(k);
+  const int64_t mx = std::max(m, n);
+  const int seg = std::min(every, std::max(iters, 1));
+  Carve cv;
+  size_t off[8];
+  mu_plan_common<T>(m, n, KP, cv, off);
+  const size_t oWs = cv.take<T>((seg + 1) * m * KP);   // W_t over one segment
+  const size_t oHs = cv.take<T>((seg + 1) * n * KP);   // H_t^T over one segment
+  const size_t oWp = cv.take<T>(seg * m * KP);         // W after the sweep
+  const size_t oHc = cv.take<T>(seg * n * KP);         // H^T after the rescaling
+  const size_t oNs = cv.take<T>(seg * KP);             // column norms
+  const size_t oQs = cv.take<T>(seg * KP * KP);
+  const size_t oSs = cv.take<T>(seg * KP * KP);
+  const size_t ogW = cv.take<T>(m * KP);
+  const size_t ogH = cv.take<T>(n * KP);
+  const size_t ogW2 = cv.take<T>(m * KP);
+  const size_t ogH2 = cv.take<T>(n * KP);
+  const size_t ogR = cv.take<T>(n * KP);
+  const size_t ogP = cv.take<T>(m * KP);
+  const size_t ogHc = cv.take<T>(n * KP);
+  const size_t ogWp = cv.take<T>(m * KP);
+  const size_t otmp = cv.take<T>(mx * KP);
+  const size_t oT1 = cv.take<T>(KP * KP);
+  const size_t oT2 = cv.take<T>(KP * KP);
+  const size_t oM = cv.take<T>(KP * KP);
+  const size_t odots = cv.take<double>(2 * KP);
+  const size_t odpart = cv.take<double>(nmfk::coldot_partials(KP));
+  nmf_status s = ensure_ws(ctx, cv.off);
+  if (s != NMF_OK) return s;
+  MuWork<T> w = mu_bind<T>(ctx, off);
+  T *Ws = at<T>(ctx, oWs), *Hs = at<T>(ctx, oHs), *Wps = at<T>(ctx, oWp), *Hcs = at<T>(ctx, oHc);
+  T *Ns = at<T>(ctx, oNs), *Qs = at<T>(ctx, oQs), *Ss = at<T>(ctx, oSs);
+  T *gW = at<T>(ctx, ogW), *gH = at<T>(ctx, ogH), *gW2 = at<T>(ctx, ogW2), *gH2 = at<T>(ctx, ogH2);
+  T *gR = at<T>(ctx, ogR), *gP = at<T>(ctx, ogP), *gHc = at<T>(ctx, ogHc), *gWp = at<T>(ctx, ogWp);
+  T *tmp = at<T>(ctx, otmp), *T1 = at<T>(ctx, oT1), *T2 = at<T>(ctx, oT2), *M = at<T>(ctx, oM);
+  double *dots = at<double>(ctx, odots), *dpart = at<double>(ctx, odpart);
+  hipStream_t st = ctx->stream;
+  HIP_TRY(nmfk::pad_rows<T>(gWT, m, k, gW, KP, st));
+  HIP_TRY(nmfk::transpose_in<T>(gHT, k, n, gH, KP, st));
+  if (gA) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
+  Prob<T> pb;
+  if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
+  auto tn = [&](const T* X, const T* Y, int64_t rows, T* D) -> nmf_status {
+    nmfk::GemmArgs<T> a{X, KP, Y, KP, D, KP, KP, KP, rows, false, 0};
+    HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(rows), w.part, st));
+    return NMF_OK;
+  };
+  const int64_t slot = (m + n) * KP;
+  const int64_t nck = mu_ckpt_count(iters, every);
+  for (int64_t j = nck - 1; j >= 0; --j) {
+    const int t0 = (int)(j * every);
+    const int L = std::min(iters, t0 + every) - t0;
+    HIP_TRY(hipMemcpyAsync(Ws, ckpt + j * slot, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(Hs, ckpt + j * slot + m * KP, sizeof(T) * n * KP,
+                           hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < L; ++i) {
+      s = hals_iteration<T>(ctx, pb, m, n, k, KP, Ws + i * m * KP, Hs + i * n * KP,
+                            Ws + (i + 1) * m * KP, Hs + (i + 1) * n * KP, Wps + i * m * KP,
+                            Hcs + i * n * KP, Ns + i * KP, Qs + i * KP * KP, Ss + i * KP * KP, w);
+      if (s != NMF_OK) return s;
+    }
+    for (int i = L - 1; i >= 0; --i) {
+      const T* W0s = Ws + i * m * KP;
+      const T* W1s = Ws + (i + 1) * m * KP;   // normalised W, the H step's fixed factor
+      const T* H0s = Hs + i * n * KP;
+      const T* H1s = Hs + (i + 1) * n * KP;
+      const T* Wp = Wps + i * m * KP;
+      const T* Hc = Hcs + i * n * KP;
+      // H sweep on the rows of Hc with R = A^T Wn and S = Wn^T Wn
+      HIP_TRY(nmfk::hals_adjoint_rows<T>(H1s, Ss + i * KP * KP, gH, n, k, KP, gHc, gR, st));
+      if ((s = tn(H1s, gR, n, T1)) != NMF_OK) return s;
+      if ((s = tn(Hc, gR, n, T2)) != NMF_OK) return s;
+      HIP_TRY(nmfk::hals_gram_grad<T>(T1, T2, KP, M, st));
+      if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w)) != NMF_OK) return s;
+      HIP_TRY(nmfk::add_to<T>(gW, tmp, m * KP, st));
+      HIP_TRY(nmfk::rowmm_add<T>(W1s, M, m, k, KP, gW, st));
+      // normalisation: Wn = W' / s, Hc = s H
+      HIP_TRY(nmfk::coldot<T>(gW, W1s, m, KP, dpart, dots, st));
+      HIP_TRY(nmfk::coldot<T>(gHc, H0s, n, KP, dpart, dots + KP, st));
+      HIP_TRY(nmfk::hals_norm_adjoint<T>(gW, W1s, m, gHc, n, Ns + i * KP, dots, k, KP, gWp, gH2,
+                                         st));
+      // W sweep with P = A H^T and Q = H H^T
+      HIP_TRY(nmfk::hals_adjoint_rows<T>(Wp, Qs + i * KP * KP, gWp, m, k, KP, gW2, gP, st));
+      if ((s = tn(Wp, gP, m, T1)) != NMF_OK) return s;
+      if ((s = tn(W0s, gP, m, T2)) != NMF_OK) return s;
+      HIP_TRY(nmfk::hals_gram_grad<T>(T1, T2, KP, M, st));
+      if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w)) != NMF_OK) return s;
+      HIP_TRY(nmfk::add_to<T>(gH2, tmp, n * KP, st));
+      HIP_TRY(nmfk::rowmm_add<T>(H0s, M, n, k, KP, gH2, st));
+      // dL/dA += Wn gR^T (from R = A^T Wn) + gP H^T (from P = A H^T)
+      if (gA) HIP_TRY(nmfk::rank_update<T>(gA, ldga, m, n, W1s, gR, gP, H0s, KP, st));
+      std::swap(gW, gW2);
+      std::swap(gH, gH2);
+    }
+  }
+  HIP_TRY(nmfk::unpad_rows<T>(gW, m, k, KP, gW0, st));
+  HIP_TRY(nmfk::transpose_out<T>(gH, k, n, KP, gH0, st));
+  return NMF_OK;
+}
+
 nmf_status mu_check(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, const void* A,
                     int64_t lda, int k, int iters, double eps, int every) {
   nmf_status s = check_common(ctx, m, n, k);
   if (s != NMF_OK) return s;
   if (dtype != NMF_F32 && dtype != NMF_F64) return fail(ctx, NMF_EINVAL, "dtype must be F32 or F64");
-  if (k > 64) return fail(ctx, NMF_EINVAL, "unrolled MU gradient supports k <= 64");
+  if (k > 64) return fail(ctx, NMF_EINVAL, "unrolled gradients support k <= 64");
   if (!A) return fail(ctx, NMF_EINVAL, "null A");
   if (lda < n) return fail(ctx, NMF_EINVAL, "lda < n");
   if (iters < 0 || every < 1) return fail(ctx, NMF_EINVAL, "iters < 0 or ckpt_every < 1");
@@ -1530,6 +1701,40 @@ nmf_status nmf_mu_unrolled_backward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, in
   return mu_backward_impl<double>(ctx, m, n, (const double*)A, lda, k, iters, eps, ckpt_every,
                                   (const double*)ckpt, (const double*)gW, (const double*)gH,
                                   (double*)gA, ldga, (double*)gW0, (double*)gH0);
+}
+
+nmf_status nmf_hals_unrolled_forward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
+                                     const void* A, int64_t lda, int k, int iters,
+                                     int ckpt_every, void* W, void* H, void* ckpt) {
+  nmf_status s = mu_check(ctx, dtype, m, n, A, lda, k, iters, 0.0, ckpt_every);
+  if (s != NMF_OK) return s;
+  if (!W || !H) return fail(ctx, NMF_EINVAL, "null W or H");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return hals_forward_impl<float>(ctx, m, n, (const float*)A, lda, k, iters, ckpt_every,
+                                    (float*)W, (float*)H, (float*)ckpt);
+  return hals_forward_impl<double>(ctx, m, n, (const double*)A, lda, k, iters, ckpt_every,
+                                   (double*)W, (double*)H, (double*)ckpt);
+}
+
+nmf_status nmf_hals_unrolled_backward(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
+                                      const void* A, int64_t lda, int k, int iters,
+                                      int ckpt_every, const void* ckpt, const void* gW,
+                                      const void* gH, void* gA, int64_t ldga, void* gW0,
+                                      void* gH0) {
+  nmf_status s = mu_check(ctx, dtype, m, n, A, lda, k, iters, 0.0, ckpt_every);
+  if (s != NMF_OK) return s;
+  if (!gW || !gH || !gW0 || !gH0 || (iters > 0 && !ckpt))
+    return fail(ctx, NMF_EINVAL, "null checkpoint or gradient array");
+  if (gA && ldga < n) return fail(ctx, NMF_EINVAL, "ldga < n");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (dtype == NMF_F32)
+    return hals_backward_impl<float>(ctx, m, n, (const float*)A, lda, k, iters, ckpt_every,
+                                     (const float*)ckpt, (const float*)gW, (const float*)gH,
+                                     (float*)gA, ldga, (float*)gW0, (float*)gH0);
+  return hals_backward_impl<double>(ctx, m, n, (const double*)A, lda, k, iters, ckpt_every,
+                                    (const double*)ckpt, (const double*)gW, (const double*)gH,
+                                    (double*)gA, ldga, (double*)gW0, (double*)gH0);
 }
 
 }  // extern "C"

@@ -8,11 +8,30 @@
 // and the products that formed N and G pass the rest on to A and to the
 // other factor (done by the driver with the product and Gram kernels).
 // This file holds the row kernel of that local adjoint, the rank update that
-// accumulates dL/dA, and the small row-times-matrix update.
+// accumulates dL/dA, and the small row-times-matrix update; and the pieces of
+// the HALS adjoint (reverse column sweep, Gram gradient, normalisation).
 #include "common.h"
 #include "kernels.h"
 
 namespace nmfk {
+
+// Whole-row 16-byte loads and stores of a KP-wide row.
+template <typename T, int KP>
+__device__ __forceinline__ void load_row_g(const T* __restrict__ src, T (&x)[KP]) {
+  constexpr int VEC = Tr<T>::VEC;
+#pragma unroll
+  for (int q = 0; q < KP / VEC; ++q) {
+    const V16<T> t = load16<T>(src + q * VEC);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) x[q * VEC + v] = t.v[v];
+  }
+}
+
+template <typename T, int KP>
+__device__ __forceinline__ void store_row_g(T* __restrict__ dst, const T (&x)[KP]) {
+#pragma unroll
+  for (int q = 0; q < KP; ++q) dst[q] = x[q];
+}
 
 // Rows are split over TPR threads (a power of two, whole rows per wave) of
 // RPT outputs each; 256 threads cover 256 / TPR rows; G is staged in LDS.
@@ -228,6 +247,139 @@ __global__ __launch_bounds__(256) void rank_update_kernel(T* __restrict__ D, int
     }
 }
 
+// --- HALS (Section 4.2, Eq. (5)) -------------------------------------------
+// Column i of a HALS sweep on a row x sets x_i' = max(0, (p_i - sum_{j != i}
+// x_j G_ji) / G_ii) (skipped when G_ii = 0), i = 0..k-1 in order with the
+// newest values. Its reverse, for i = k-1..0, with g the gradient with
+// respect to the row's values at that point and M = [x_i' > 0]:
+//     delta_i = M g_i / G_ii   (= dL/dp_i)
+//     g_j -= G_ji delta_i for j != i,   g_i = 0
+// (x_i' does not depend on the old x_i). What is left in g is dL/dx (old).
+// dL/dG is formed by the driver from the deltas: the value of x_j that
+// column i saw is the new one for j <= i and the old one for j > i, so
+//     dL/dG[j][i] = -(X_new^T Delta)[j][i] for j <= i, -(X_old^T Delta)[j][i]
+//     otherwise.
+// One thread per row keeps g in registers (and, for float, the deltas too)
+// and reads G with wave-uniform loads, like the forward sweep.
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
+    const T* __restrict__ Xnew, const T* __restrict__ G, const T* __restrict__ gXnew,
+    int64_t rows, int k, T* __restrict__ gXold, T* __restrict__ Delta) {
+  constexpr bool DREG = sizeof(T) == 4;   // deltas in registers (float), else stored at once
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  T g[KP];
+  T d[DREG ? KP : 1];
+  uint64_t mask = 0;
+  {
+    T x[KP];
+    load_row_g<T, KP>(Xnew + r * KP, x);
+#pragma unroll
+    for (int j = 0; j < KP; ++j) mask |= (x[j] > T(0) ? 1ull : 0ull) << j;
+  }
+  load_row_g<T, KP>(gXnew + r * KP, g);
+  T* dr = Delta + r * KP;
+#pragma unroll
+  for (int i = KP - 1; i >= 0; --i) {
+    T di = T(0);
+    if (i < k) {
+      const T gii = G[i * KP + i];
+      if (gii > T(0)) {
+        di = ((mask >> i) & 1ull) ? g[i] / gii : T(0);
+#pragma unroll
+        for (int j = 0; j < KP; ++j)
+          if (j != i) g[j] = fma(-G[j * KP + i], di, g[j]);
+        g[i] = T(0);
+      }
+    }
+    if constexpr (DREG) d[i] = di;
+    else dr[i] = di;
+  }
+  store_row_g<T, KP>(gXold + r * KP, g);
+  if constexpr (DREG) store_row_g<T, KP>(dr, d);
+}
+
+// M = S + S^T with S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (KP x KP): the
+// symmetric Gram gradient of a HALS sweep from T1 = X_new^T Delta and
+// T2 = X_old^T Delta.
+template <typename T>
+__global__ void hals_gram_grad_kernel(const T* __restrict__ T1, const T* __restrict__ T2, int KP,
+                                      T* __restrict__ M) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= KP * KP) return;
+  const int a = e / KP, b = e % KP;
+  const T sab = a <= b ? T1[a * KP + b] : T2[a * KP + b];
+  const T sba = b <= a ? T1[b * KP + a] : T2[b * KP + a];
+  M[e] = -(sab + sba);
+}
+
+// Column dot products out[c] = sum_r X[r][c] Y[r][c] (rows x KP, KP <= 128)
+// in double: each block sums a slice of rows per column (256 / KP row lanes,
+// combined in LDS), and one block adds the block partials in order.
+constexpr int COLDOT_BLOCKS = 256;
+template <typename T>
+__global__ __launch_bounds__(256) void coldot_partials_kernel(const T* __restrict__ X,
+                                                              const T* __restrict__ Y,
+                                                              int64_t rows, int KP,
+                                                              double* __restrict__ part) {
+  __shared__ double sh[256];
+  const int lanes = 256 / KP;
+  const int c = threadIdx.x % KP, lr = threadIdx.x / KP;
+  double acc = 0.0;
+  if (lr < lanes)
+    for (int64_t r = (int64_t)blockIdx.x * lanes + lr; r < rows; r += (int64_t)gridDim.x * lanes)
+      acc += (double)X[r * KP + c] * (double)Y[r * KP + c];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < KP) {
+    double t = 0.0;
+    for (int q = 0; q < lanes; ++q) t += sh[q * KP + threadIdx.x];
+    part[(int64_t)blockIdx.x * KP + threadIdx.x] = t;
+  }
+}
+
+__global__ void coldot_finish_kernel(const double* __restrict__ part, int nblocks, int KP,
+                                     double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= KP) return;
+  double t = 0.0;
+  for (int b = 0; b < nblocks; ++b) t += part[(int64_t)b * KP + c];
+  out[c] = t;
+}
+
+// Adjoint of the HALS normalisation Wn = W' diag(1/s), Hc = diag(s) H
+// (s_c = ||w_c'||; columns with s_c = 0 or c >= k pass unchanged):
+//     ds_c = -<gWn_c, Wn_c> / s_c + <gHc_c, H_c>
+//     gW'_c = gWn_c / s_c + ds_c Wn_c,   gH_c = s_c gHc_c
+// on the row layout (H as H^T, n x KP). dots holds <gWn_c, Wn_c> in [0, KP)
+// and <gHc_c, H_c> in [KP, 2 KP). Rows 0..m-1 of the grid write gWp, rows
+// m..m+n-1 write gHt.
+template <typename T>
+__global__ void hals_norm_adjoint_kernel(const T* __restrict__ gWn, const T* __restrict__ Wn,
+                                         int64_t m, const T* __restrict__ gHc, int64_t n,
+                                         const T* __restrict__ norms,
+                                         const double* __restrict__ dots, int k, int KP,
+                                         T* __restrict__ gWp, T* __restrict__ gHt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (m + n) * KP) return;
+  const int64_t r = e / KP;
+  const int c = (int)(e - r * KP);
+  const T s = norms[c];
+  const bool scaled = c < k && s > T(0);
+  if (r < m) {
+    const int64_t q = r * KP + c;
+    if (scaled) {
+      const double ds = -dots[c] / (double)s + dots[KP + c];
+      gWp[q] = (T)((double)gWn[q] / (double)s + ds * (double)Wn[q]);
+    } else {
+      gWp[q] = gWn[q];
+    }
+  } else {
+    const int64_t q = (r - m) * KP + c;
+    gHt[q] = scaled ? s * gHc[q] : gHc[q];
+  }
+}
+
 template <typename T>
 hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* gXn,
                            int64_t rows, int k, int KP, T eps, T* gN, T* gD, T* gX,
@@ -287,7 +439,66 @@ hipError_t rank_update(T* D, int64_t ldd, int64_t m, int64_t n, const T* X1, con
   return NMF_LAUNCH_CHECK();
 }
 
+template <typename T>
+hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t rows, int k,
+                             int KP, T* gXold, T* Delta, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)cdiv(rows, 256);
+  switch (KP) {
+#define CASE(K)                                                                               \
+  case K:                                                                                     \
+    hals_adjoint_rows_kernel<T, K><<<blocks, 256, 0, st>>>(Xnew, G, gXnew, rows, k, gXold,    \
+                                                           Delta);                            \
+    break;
+    CASE(16) CASE(32) CASE(48) CASE(64)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t hals_gram_grad(const T* T1, const T* T2, int KP, T* M, hipStream_t st) {
+  hals_gram_grad_kernel<T><<<(unsigned)cdiv(KP * KP, 256), 256, 0, st>>>(T1, T2, KP, M);
+  return NMF_LAUNCH_CHECK();
+}
+
+int64_t coldot_partials(int KP) { return (int64_t)COLDOT_BLOCKS * KP; }
+
+template <typename T>
+hipError_t coldot(const T* X, const T* Y, int64_t rows, int KP, double* part, double* out,
+                  hipStream_t st) {
+  if (KP < 1 || KP > 128) return hipErrorInvalidValue;
+  const int lanes = 256 / KP;
+  int64_t blocks = cdiv(rows > 0 ? rows : 1, lanes);
+  blocks = blocks < COLDOT_BLOCKS ? blocks : COLDOT_BLOCKS;
+  coldot_partials_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(X, Y, rows, KP, part);
+  hipError_t e = NMF_LAUNCH_CHECK();
+  if (e != hipSuccess) return e;
+  coldot_finish_kernel<<<(unsigned)cdiv(KP, 128), 128, 0, st>>>(part, (int)blocks, KP, out);
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T>
+hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc, int64_t n,
+                             const T* norms, const double* dots, int k, int KP, T* gWp, T* gHt,
+                             hipStream_t st) {
+  const int64_t total = (m + n) * KP;
+  if (total == 0) return hipSuccess;
+  hals_norm_adjoint_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(
+      gWn, Wn, m, gHc, n, norms, dots, k, KP, gWp, gHt);
+  return NMF_LAUNCH_CHECK();
+}
+
 #define INST(T)                                                                               \
+  template hipError_t hals_adjoint_rows<T>(const T*, const T*, const T*, int64_t, int, int,   \
+                                           T*, T*, hipStream_t);                              \
+  template hipError_t hals_gram_grad<T>(const T*, const T*, int, T*, hipStream_t);            \
+  template hipError_t coldot<T>(const T*, const T*, int64_t, int, double*, double*,           \
+                                hipStream_t);                                                 \
+  template hipError_t hals_norm_adjoint<T>(const T*, const T*, int64_t, const T*, int64_t,    \
+                                           const T*, const double*, int, int, T*, T*,         \
+                                           hipStream_t);                                      \
   template hipError_t mu_adjoint_rows<T>(const T*, const T*, const T*, const T*, const T*,    \
                                          int64_t, int, int, T, T*, T*, T*, hipStream_t);      \
   template hipError_t rowmm_add<T>(const T*, const T*, int64_t, int, int, T*, hipStream_t);   \

@@ -146,6 +146,29 @@ template <typename T>
 hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* gXn,
                            int64_t rows, int k, int KP, T eps, T* gN, T* gD, T* gX,
                            hipStream_t st);
+// Reverse of the HALS sweep on rows x KP rows (KP in {16, 32, 48, 64}): from
+// the sweep's output Xnew, the Gram G and gXnew = dL/dXnew, writes
+// gXold = dL/dX (input) and Delta = dL/dP (one delta per row and column).
+template <typename T>
+hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t rows, int k,
+                             int KP, T* gXold, T* Delta, hipStream_t st);
+// M = S + S^T, S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (the sweep's Gram
+// gradient from T1 = Xnew^T Delta and T2 = Xold^T Delta).
+template <typename T>
+hipError_t hals_gram_grad(const T* T1, const T* T2, int KP, T* M, hipStream_t st);
+// out[c] = sum_r X[r][c] Y[r][c] (double, fixed order); part holds
+// coldot_partials(KP) doubles.
+int64_t coldot_partials(int KP);
+template <typename T>
+hipError_t coldot(const T* X, const T* Y, int64_t rows, int KP, double* part, double* out,
+                  hipStream_t st);
+// Adjoint of the HALS normalisation (Wn = W' / s, Hc = s H per column):
+// gWp = dL/dW', gHt = dL/dH^T (pre-scaling) from gWn, gHc; dots[c] =
+// <gWn_c, Wn_c>, dots[KP + c] = <gHc_c, Ht_c>.
+template <typename T>
+hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc, int64_t n,
+                             const T* norms, const double* dots, int k, int KP, T* gWp, T* gHt,
+                             hipStream_t st);
 // Out[r] += X[r] M (M KP x KP), columns < k.
 template <typename T>
 hipError_t rowmm_add(const T* X, const T* M, int64_t rows, int k, int KP, T* Out,

@@ -333,38 +333,50 @@ __global__ __launch_bounds__(256) void transpose_full_kernel(const T* __restrict
 }
 
 // Byte and 16-bit matrices (FP8 and bfloat16 A) move 4-byte words both
-// ways: a 128 x 128 tile is read as whole words of each row and written as
-// whole words of each output row, an output word gathering one element from
-// each of 4 / sizeof(T) consecutive input rows. Needs lda, ldt and n
-// multiples of the elements per word and 4-byte aligned pointers, so that a
-// word read at a column below n and a word written at a row below m stay
-// inside the row pitches.
+// ways: a TR x 128 tile (TR = 128 rows for bytes, 64 for 16-bit elements, so
+// that every output word run is 128 bytes and the tile stays near 16 KB of
+// LDS) is read as whole words of each row and written as whole words of each
+// output row, an output word gathering one element from each of
+// 4 / sizeof(T) consecutive input rows. Needs lda, ldt and n multiples of the
+// elements per word and 4-byte aligned pointers, so that a word read at a
+// column below n and a word written at a row below m stay inside the row
+// pitches.
+template <typename T> struct WordTile {
+  static constexpr int EPW = 4 / (int)sizeof(T);   // elements per word
+  static constexpr int TR = 32 * EPW;              // tile rows
+};
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_words_kernel(const T* __restrict__ A,
                                                               int64_t lda, int64_t m, int64_t n,
                                                               T* __restrict__ At, int64_t ldt) {
-  constexpr int EPW = 4 / (int)sizeof(T);   // elements per word
-  constexpr int WPR = 128 / EPW;            // words per tile row
-  constexpr int RPP = 256 / WPR;            // rows per pass
+  constexpr int EPW = WordTile<T>::EPW;
+  constexpr int TR = WordTile<T>::TR;
+  constexpr int WPR = 128 / EPW;            // words per tile row (128 columns)
+  constexpr int RPP = 256 / WPR;            // tile rows read per pass
+  constexpr int OW = TR / EPW;              // words per output row (32)
+  constexpr int OPP = 256 / OW;             // output rows written per pass
   constexpr int EB = 8 * (int)sizeof(T);    // bits per element
   constexpr uint32_t MASK = (1u << EB) - 1u;
-  __shared__ uint32_t tile[128][WPR + 1];
-  const int64_t c0 = (int64_t)blockIdx.x * 128, r0 = (int64_t)blockIdx.y * 128;
-  const int tx = threadIdx.x % WPR, ty = threadIdx.x / WPR;
-  for (int i = ty; i < 128; i += RPP) {
-    const int64_t r = r0 + i, c = c0 + EPW * tx;
-    tile[i][tx] = (r < m && c < n)
-                      ? __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(A + r * lda + c))
-                      : 0u;
+  __shared__ uint32_t tile[TR][WPR + 1];
+  const int64_t c0 = (int64_t)blockIdx.x * 128, r0 = (int64_t)blockIdx.y * TR;
+  {
+    const int tx = threadIdx.x % WPR, ty = threadIdx.x / WPR;
+    for (int i = ty; i < TR; i += RPP) {
+      const int64_t r = r0 + i, c = c0 + EPW * tx;
+      tile[i][tx] = (r < m && c < n) ? __builtin_nontemporal_load(
+                                           reinterpret_cast<const uint32_t*>(A + r * lda + c))
+                                     : 0u;
+    }
   }
   __syncthreads();
-  for (int j = ty; j < 128; j += RPP) {
-    const int64_t c = c0 + j, r = r0 + EPW * tx;
+  const int ox = threadIdx.x % OW, oy = threadIdx.x / OW;
+  for (int j = oy; j < 128; j += OPP) {
+    const int64_t c = c0 + j, r = r0 + EPW * ox;
     if (c < n && r < m) {
       const int w = j / EPW, sh = EB * (j % EPW);
       uint32_t out = 0;
 #pragma unroll
-      for (int b = 0; b < EPW; ++b) out |= ((tile[EPW * tx + b][w] >> sh) & MASK) << (EB * b);
+      for (int b = 0; b < EPW; ++b) out |= ((tile[EPW * ox + b][w] >> sh) & MASK) << (EB * b);
       *reinterpret_cast<uint32_t*>(At + c * ldt + r) = out;
     }
   }
@@ -377,7 +389,7 @@ hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, 
     constexpr int EPW = 4 / (int)sizeof(T);
     if (lda % EPW == 0 && ldt % EPW == 0 && n % EPW == 0 && (uintptr_t)A % 4 == 0 &&
         (uintptr_t)At % 4 == 0) {
-      dim3 grid((unsigned)cdiv(n, 128), (unsigned)cdiv(m, 128));
+      dim3 grid((unsigned)cdiv(n, 128), (unsigned)cdiv(m, WordTile<T>::TR));
       transpose_words_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, At, ldt);
       return NMF_LAUNCH_CHECK();
     }

@@ -161,6 +161,27 @@ def test_mu_unrolled_argument_errors(hctx):
     assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 1e-16, 2, P, P, P, None, 0, P, P) == EDEVICE
 
 
+def test_hals_unrolled_argument_errors(hctx):
+    L = _lib.lib()
+    fw = L.nmf_hals_unrolled_forward
+    assert fw(hctx, 1, 10, 8, P, 8, 3, 5, 2, P, P, P) == EDEVICE
+    assert fw(hctx, 0, 10, 8, P, 8, 3, 5, 2, P, P, None) == EDEVICE    # no checkpoints
+    assert fw(hctx, 1, 10, 8, P, 8, 65, 5, 2, P, P, P) == EINVAL      # k > 64
+    assert fw(hctx, 2, 10, 8, P, 8, 3, 5, 2, P, P, P) == EINVAL       # BF16 A
+    assert fw(hctx, 1, 10, 8, P, 8, 3, 5, 0, P, P, P) == EINVAL       # ckpt_every 0
+    assert fw(hctx, 1, 10, 8, P, 8, 3, -1, 2, P, P, P) == EINVAL      # iters < 0
+    assert fw(hctx, 1, 10, 8, P, 7, 3, 5, 2, P, P, P) == EINVAL       # lda < n
+    assert fw(hctx, 1, 10, 8, None, 8, 3, 5, 2, P, P, P) == EINVAL
+    assert fw(hctx, 1, 10, 8, P, 8, 3, 5, 2, P, None, P) == EINVAL
+    bw = L.nmf_hals_unrolled_backward
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 2, P, P, P, P, 8, P, P) == EDEVICE
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 2, None, P, P, P, 8, P, P) == EINVAL
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 0, 2, None, P, P, P, 8, P, P) == EDEVICE  # T = 0
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 2, P, P, P, P, 7, P, P) == EINVAL  # ldga
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 2, P, P, None, P, 8, P, P) == EINVAL
+    assert bw(hctx, 1, 10, 8, P, 8, 3, 5, 2, P, P, P, None, 0, P, P) == EDEVICE
+
+
 def test_stop_options_and_pgrad_argument_errors(hctx):
     L = _lib.lib()
     assert dense(hctx, opts=_lib.default_opts(algo="hals", iters=2, stop=1, tol=0.1)) == EDEVICE

@@ -1,0 +1,151 @@
+"""Differentiation through T unrolled HALS iterations (Algorithm 1 with the
+HALS rules of Section 4.2, Eq. (5), as nmf_dense runs them): the forward map
+against nmf_dense itself, the library's adjoint against central finite
+differences of its own forward pass (FP64) and against the oracle's reference
+gradient (FP64 and FP32), invariance to the checkpoint interval, T = 0, and
+the torch.autograd layer."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1609_09154_amd as nmf
+from synth import init_factors, planted_dense, uniform
+from tests.gpu_util import host, step, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(m, n, k, seed):
+    A = planted_dense(m, n, k, seed=seed)
+    W0, H0 = init_factors(m, n, k, seed=seed + 1)
+    GW = uniform((m, k), seed=seed + 2) - 0.5
+    GH = uniform((k, n), seed=seed + 3) - 0.5
+    return A, W0, H0, GW, GH
+
+
+def _maxrel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_forward_is_nmf_dense_hals(dt):
+    """The unrolled forward pass is the HALS iteration of the driver, kernel
+    for kernel: both give the same factors bit for bit."""
+    m, n, k, iters = 300, 208, 12, 7
+    A, W0, H0, _, _ = _problem(m, n, k, seed=3)
+    Ad = to_dev(A, dt)
+    step("hals unrolled forward vs nmf_dense %s" % np.dtype(dt).name)
+    W, H, _ = nmf.nmf_hals_unrolled_forward(Ad, to_dev(W0, dt), to_dev(H0, dt), iters,
+                                            want_ckpt=False)
+    Wd, Hd = to_dev(W0, dt), to_dev(H0, dt)
+    nmf.nmf_dense(Ad, Wd, Hd, algo="hals", iters=iters, objective=False)
+    assert np.array_equal(host(W), host(Wd)) and np.array_equal(host(H), host(Hd))
+
+
+@pytest.mark.parametrize("iters,every", [(6, 6), (8, 3)])
+def test_fd_check_fp64_256x128_k8(iters, every):
+    """Directional central differences of the library's own FP64 forward
+    pass against its FP64 gradient (loss <GW, W_T> + <GH, H_T>), each input
+    on its own and all together."""
+    m, n, k = 256, 128, 8
+    A, W0, H0, GW, GH = _problem(m, n, k, seed=500 + iters)
+    dt = np.float64
+    Ad, W0d, H0d = to_dev(A, dt), to_dev(W0, dt), to_dev(H0, dt)
+    step("hals autograd fd fp64 T=%d every=%d" % (iters, every))
+    _, _, ck = nmf.nmf_hals_unrolled_forward(Ad, W0d, H0d, iters, ckpt_every=every)
+    gA, gW0, gH0 = nmf.nmf_hals_unrolled_backward(Ad, ck, to_dev(GW, dt), to_dev(GH, dt), iters,
+                                                  ckpt_every=every)
+    gA, gW0, gH0 = host(gA), host(gW0), host(gH0)
+
+    def loss(dA, dW, dH, h):
+        W, H, _ = nmf.nmf_hals_unrolled_forward(to_dev(A + h * dA, dt), to_dev(W0 + h * dW, dt),
+                                                to_dev(H0 + h * dH, dt), iters, want_ckpt=False)
+        return float(np.sum(GW * host(W)) + np.sum(GH * host(H)))
+
+    rng = np.random.default_rng(iters)
+    h = 1e-6
+    for which in range(4):
+        d = [rng.standard_normal(x.shape) for x in (A, W0, H0)]
+        if which < 3:
+            d = [x if i == which else np.zeros_like(x) for i, x in enumerate(d)]
+        fd = (loss(*d, h) - loss(*d, -h)) / (2 * h)
+        an = float(np.sum(gA * d[0]) + np.sum(gW0 * d[1]) + np.sum(gH0 * d[2]))
+        print("direction %d: fd %.12e analytic %.12e" % (which, fd, an))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,k,iters,every", [(300, 200, 10, 12, 5), (257, 333, 33, 7, 3),
+                                               (128, 96, 64, 4, 10)])
+def test_gradient_matches_oracle(dt, m, n, k, iters, every):
+    A, W0, H0, GW, GH = _problem(m, n, k, seed=m + k)
+    Ac, W0c, H0c = A.astype(dt), W0.astype(dt), H0.astype(dt)
+    GWc, GHc = GW.astype(dt), GH.astype(dt)
+    step("hals autograd vs oracle %s %dx%d k=%d T=%d" % (np.dtype(dt).name, m, n, k, iters))
+    Ad = to_dev(Ac, dt)
+    W, H, ck = nmf.nmf_hals_unrolled_forward(Ad, to_dev(W0c, dt), to_dev(H0c, dt), iters,
+                                             ckpt_every=every)
+    gA, gW0, gH0 = nmf.nmf_hals_unrolled_backward(Ad, ck, to_dev(GWc, dt), to_dev(GHc, dt),
+                                                  iters, ckpt_every=every)
+    f64 = [x.astype(np.float64) for x in (Ac, W0c, H0c, GWc, GHc)]
+    Wr, Hr = oracle.hals_unrolled_forward(f64[0], f64[1], f64[2], iters)
+    rA, rW, rH = oracle.hals_unrolled_vjp(*f64[:3], iters, f64[3], f64[4])
+    errs = [_maxrel(host(W).astype(np.float64), Wr), _maxrel(host(H).astype(np.float64), Hr),
+            _maxrel(host(gA).astype(np.float64), rA), _maxrel(host(gW0).astype(np.float64), rW),
+            _maxrel(host(gH0).astype(np.float64), rH)]
+    print("W_T %.2e H_T %.2e dA %.2e dW0 %.2e dH0 %.2e" % tuple(errs))
+    # the MU layer's bars: FP64 to rounding over T iterations; FP32 an order
+    # above what float storage of the factors leaves (measured at most 4.4e-5)
+    tol = 1e-10 if dt == np.float64 else 5e-4
+    assert max(errs) <= tol
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    """Recomputed segments repeat the forward pass bit for bit, so every
+    checkpoint interval gives the same gradient."""
+    m, n, k, iters = 200, 150, 16, 9
+    A, W0, H0, GW, GH = _problem(m, n, k, seed=78)
+    dt = np.float32
+    Ad, W0d, H0d = to_dev(A, dt), to_dev(W0, dt), to_dev(H0, dt)
+    outs = []
+    for every in (1, 2, 4, 9, 20):
+        step("hals autograd ckpt every=%d" % every)
+        _, _, ck = nmf.nmf_hals_unrolled_forward(Ad, W0d, H0d, iters, ckpt_every=every)
+        g = nmf.nmf_hals_unrolled_backward(Ad, ck, to_dev(GW, dt), to_dev(GH, dt), iters,
+                                           ckpt_every=every)
+        outs.append([host(x) for x in g])
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_zero_iterations_is_the_identity():
+    m, n, k = 40, 32, 5
+    A, W0, H0, GW, GH = _problem(m, n, k, seed=6)
+    dt = np.float64
+    Ad = to_dev(A, dt)
+    W, H, ck = nmf.nmf_hals_unrolled_forward(Ad, to_dev(W0, dt), to_dev(H0, dt), 0)
+    gA, gW0, gH0 = nmf.nmf_hals_unrolled_backward(Ad, ck, to_dev(GW, dt), to_dev(GH, dt), 0)
+    assert np.array_equal(host(W), W0) and np.array_equal(host(H), H0)
+    assert np.array_equal(host(gW0), GW) and np.array_equal(host(gH0), GH)
+    assert not np.any(host(gA))
+
+
+def test_torch_autograd_layer_gradcheck():
+    """torch.autograd.gradcheck (finite differences in FP64) on the layer,
+    with the fitting loss ||A - W_T H_T||^2 through torch."""
+    import torch
+
+    m, n, k, iters = 24, 16, 3, 4
+    A, W0, H0, _, _ = _problem(m, n, k, seed=10)
+    dev = torch.device("cuda:0")
+    At = torch.tensor(A, device=dev, requires_grad=True)
+    Wt = torch.tensor(W0, device=dev, requires_grad=True)
+    Ht = torch.tensor(H0, device=dev, requires_grad=True)
+
+    def f(A_, W_, H_):
+        W, H = nmf.hals_unrolled(A_, W_, H_, iters, 2)
+        return ((A_ - W @ H) ** 2).sum()
+
+    step("hals autograd gradcheck")
+    assert torch.autograd.gradcheck(f, (At, Wt, Ht), eps=1e-6, atol=1e-7, rtol=1e-5)
