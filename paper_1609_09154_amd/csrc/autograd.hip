@@ -15,24 +15,6 @@
 
 namespace nmfk {
 
-// Whole-row 16-byte loads and stores of a KP-wide row.
-template <typename T, int KP>
-__device__ __forceinline__ void load_row_g(const T* __restrict__ src, T (&x)[KP]) {
-  constexpr int VEC = Tr<T>::VEC;
-#pragma unroll
-  for (int q = 0; q < KP / VEC; ++q) {
-    const V16<T> t = load16<T>(src + q * VEC);
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) x[q * VEC + v] = t.v[v];
-  }
-}
-
-template <typename T, int KP>
-__device__ __forceinline__ void store_row_g(T* __restrict__ dst, const T (&x)[KP]) {
-#pragma unroll
-  for (int q = 0; q < KP; ++q) dst[q] = x[q];
-}
-
 // Rows are split over TPR threads (a power of two, whole rows per wave) of
 // RPT outputs each; 256 threads cover 256 / TPR rows; G is staged in LDS.
 template <int KP> struct AdjSplit {
@@ -259,44 +241,66 @@ __global__ __launch_bounds__(256) void rank_update_kernel(T* __restrict__ D, int
 // column i saw is the new one for j <= i and the old one for j > i, so
 //     dL/dG[j][i] = -(X_new^T Delta)[j][i] for j <= i, -(X_old^T Delta)[j][i]
 //     otherwise.
-// One thread per row keeps g in registers (and, for float, the deltas too)
-// and reads G with wave-uniform loads, like the forward sweep.
+// A group of TPR lanes per row (as in the forward sweep): lane `sub` owns
+// entries sub*R .. sub*R + R - 1 of g, of the mask and of the deltas. At step
+// i the owner of entry i forms delta_i, a group sum (the other lanes add 0)
+// hands it to every lane, and each lane updates its own entries of g with
+// column i of G (staged in LDS, column-contiguous). Rows past the end run on
+// a clamped copy of the last row and store nothing.
+template <int KP> struct HalsAdjGroup {
+  static constexpr int TPR = KP == 16 ? 4 : (KP == 32 ? 8 : 16);
+  static constexpr int R = KP / TPR;
+  static constexpr int ROWS = 256 / TPR;
+};
+
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
     const T* __restrict__ Xnew, const T* __restrict__ G, const T* __restrict__ gXnew,
     int64_t rows, int k, T* __restrict__ gXold, T* __restrict__ Delta) {
-  constexpr bool DREG = sizeof(T) == 4;   // deltas in registers (float), else stored at once
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  T g[KP];
-  T d[DREG ? KP : 1];
-  uint64_t mask = 0;
-  {
-    T x[KP];
-    load_row_g<T, KP>(Xnew + r * KP, x);
-#pragma unroll
-    for (int j = 0; j < KP; ++j) mask |= (x[j] > T(0) ? 1ull : 0ull) << j;
+  constexpr int TPR = HalsAdjGroup<KP>::TPR, R = HalsAdjGroup<KP>::R;
+  constexpr int ROWS = HalsAdjGroup<KP>::ROWS;
+  __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) {
+    const int i = e / KP, j = e - i * KP;
+    Gs[e] = G[j * KP + i];
   }
-  load_row_g<T, KP>(gXnew + r * KP, g);
-  T* dr = Delta + r * KP;
+  __syncthreads();
+  const int sub = threadIdx.x % TPR;
+  const int64_t r = (int64_t)blockIdx.x * ROWS + threadIdx.x / TPR;
+  const int64_t rr = r < rows ? r : rows - 1;
+  T g[R], d[R];
+  unsigned mask = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    g[q] = gXnew[rr * KP + sub * R + q];
+    mask |= (Xnew[rr * KP + sub * R + q] > T(0) ? 1u : 0u) << q;
+    d[q] = T(0);
+  }
 #pragma unroll
   for (int i = KP - 1; i >= 0; --i) {
-    T di = T(0);
     if (i < k) {
-      const T gii = G[i * KP + i];
+      const T gii = Gs[i * KP + i];
       if (gii > T(0)) {
-        di = ((mask >> i) & 1ull) ? g[i] / gii : T(0);
+        const bool own = sub == i / R;
+        const T mine = (own && ((mask >> (i % R)) & 1u)) ? g[i % R] / gii : T(0);
+        const T di = group_sum<TPR>(mine);
+        const T* gc = &Gs[i * KP + sub * R];
 #pragma unroll
-        for (int j = 0; j < KP; ++j)
-          if (j != i) g[j] = fma(-G[j * KP + i], di, g[j]);
-        g[i] = T(0);
+        for (int q = 0; q < R; ++q) g[q] = fma(-gc[q], di, g[q]);
+        if (own) {
+          g[i % R] = T(0);
+          d[i % R] = di;
+        }
       }
     }
-    if constexpr (DREG) d[i] = di;
-    else dr[i] = di;
   }
-  store_row_g<T, KP>(gXold + r * KP, g);
-  if constexpr (DREG) store_row_g<T, KP>(dr, d);
+  if (r < rows) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      gXold[r * KP + sub * R + q] = g[q];
+      Delta[r * KP + sub * R + q] = d[q];
+    }
+  }
 }
 
 // M = S + S^T with S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (KP x KP): the
@@ -315,7 +319,8 @@ __global__ void hals_gram_grad_kernel(const T* __restrict__ T1, const T* __restr
 
 // Column dot products out[c] = sum_r X[r][c] Y[r][c] (rows x KP, KP <= 128)
 // in double: each block sums a slice of rows per column (256 / KP row lanes,
-// combined in LDS), and one block adds the block partials in order.
+// combined in LDS), and a second kernel adds the block partials of each
+// column in a fixed tree.
 constexpr int COLDOT_BLOCKS = 256;
 template <typename T>
 __global__ __launch_bounds__(256) void coldot_partials_kernel(const T* __restrict__ X,
@@ -338,13 +343,19 @@ __global__ __launch_bounds__(256) void coldot_partials_kernel(const T* __restric
   }
 }
 
-__global__ void coldot_finish_kernel(const double* __restrict__ part, int nblocks, int KP,
-                                     double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= KP) return;
-  double t = 0.0;
-  for (int b = 0; b < nblocks; ++b) t += part[(int64_t)b * KP + c];
-  out[c] = t;
+// One block per column: the block partials (at most COLDOT_BLOCKS) are added
+// pairwise in a fixed tree in LDS.
+__global__ __launch_bounds__(COLDOT_BLOCKS) void coldot_finish_kernel(
+    const double* __restrict__ part, int nblocks, int KP, double* __restrict__ out) {
+  __shared__ double sh[COLDOT_BLOCKS];
+  const int c = blockIdx.x, t = threadIdx.x;
+  sh[t] = t < nblocks ? part[(int64_t)t * KP + c] : 0.0;
+  __syncthreads();
+  for (int h = COLDOT_BLOCKS / 2; h > 0; h >>= 1) {
+    if (t < h) sh[t] += sh[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[c] = sh[0];
 }
 
 // Adjoint of the HALS normalisation Wn = W' diag(1/s), Hc = diag(s) H
@@ -443,12 +454,11 @@ template <typename T>
 hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t rows, int k,
                              int KP, T* gXold, T* Delta, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)cdiv(rows, 256);
   switch (KP) {
 #define CASE(K)                                                                               \
   case K:                                                                                     \
-    hals_adjoint_rows_kernel<T, K><<<blocks, 256, 0, st>>>(Xnew, G, gXnew, rows, k, gXold,    \
-                                                           Delta);                            \
+    hals_adjoint_rows_kernel<T, K><<<(unsigned)cdiv(rows, HalsAdjGroup<K>::ROWS), 256, 0,      \
+                                     st>>>(Xnew, G, gXnew, rows, k, gXold, Delta);            \
     break;
     CASE(16) CASE(32) CASE(48) CASE(64)
 #undef CASE
@@ -475,7 +485,7 @@ hipError_t coldot(const T* X, const T* Y, int64_t rows, int KP, double* part, do
   coldot_partials_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(X, Y, rows, KP, part);
   hipError_t e = NMF_LAUNCH_CHECK();
   if (e != hipSuccess) return e;
-  coldot_finish_kernel<<<(unsigned)cdiv(KP, 128), 128, 0, st>>>(part, (int)blocks, KP, out);
+  coldot_finish_kernel<<<(unsigned)KP, COLDOT_BLOCKS, 0, st>>>(part, (int)blocks, KP, out);
   return NMF_LAUNCH_CHECK();
 }
 

@@ -103,6 +103,29 @@ __device__ __forceinline__ double to_double(double x) { return x; }
 __device__ __forceinline__ double to_double(uint16_t x) { return (double)bf16_bits_to_float(x); }
 __device__ __forceinline__ double to_double(uint8_t x) { return (double)fp8_e4m3_bits_to_float(x); }
 
+// Sum over groups of G consecutive lanes (G = 2, 4, 8 or 16, a group inside
+// one 16-lane row) with DPP lane permutations: quad_perm [1,0,3,2] and
+// [2,3,0,1] (partners at xor 1 and xor 2), row_half_mirror (lane i with
+// 7 - i of its 8) and row_mirror (lane i with 15 - i). Each step adds a value
+// that is the same on both partners, so every lane of a group ends with the
+// same bits. Every lane of the wave must take part.
+template <int CTRL> __device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
+  if constexpr (G >= 2) v = v + dpp_move<0xB1>(v);
+  if constexpr (G >= 4) v = v + dpp_move<0x4E>(v);
+  if constexpr (G >= 8) v = v + dpp_move<0x141>(v);
+  if constexpr (G >= 16) v = v + dpp_move<0x140>(v);
+  return v;
+}
+
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 

@@ -1,10 +1,10 @@
 // Local update computations (LUC) of Algorithm 1 on the row layout: a row x
 // of the factor being updated (a row of W, or a row of H^T, i.e. a column of
 // H) is independent of every other row (Section 5: rows of W and columns of H
-// can be updated in parallel). HALS gives each row one thread, which keeps x
-// in registers and reads the k x k Gram G of the fixed factor with
-// wave-uniform loads; MU splits each row's outputs over several threads with
-// G staged in LDS.
+// can be updated in parallel). HALS gives each row a group of lanes that
+// share the sequential sweep (each lane owns a slice of x; the dot product of
+// every step is summed across the group with lane permutations); MU splits
+// each row's outputs over several threads; both stage G in LDS.
 //
 //   MU   (Section 4.1, Eq. (3)):  x_i <- x_i p_i / ((x G)_i + eps), all i at once
 //   HALS (Section 4.2, Eq. (5)):  i = 1..k in order, newest values:
@@ -16,55 +16,62 @@
 
 namespace nmfk {
 
-template <typename T, int KP>
-__device__ __forceinline__ void load_row(const T* __restrict__ src, T (&x)[KP]) {
-  constexpr int VEC = Tr<T>::VEC;
-#pragma unroll
-  for (int q = 0; q < KP / VEC; ++q) {
-    V16<T> t = load16<T>(src + q * VEC);
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) x[q * VEC + v] = t.v[v];
-  }
-}
+// HALS sweep with a group of TPR lanes per row: lane `sub` of a group owns
+// entries sub*R .. sub*R + R - 1 of the row (R = KP / TPR) and the matching
+// products. Step i forms (x G)_i from the owners' partial sums (group_sum,
+// the same bits on every lane of the group) and the owner of entry i updates
+// it. G is staged in LDS with column i contiguous (Gs[i][j] = G[j][i]), so a
+// lane reads its R entries of the column with one vector load. Rows past the
+// end run on a clamped copy of the last row (every lane must join the group
+// sums) and store nothing.
+template <int KP> struct HalsGroup {
+  static constexpr int TPR = KP == 16 ? 4 : (KP == 32 ? 8 : 16);
+  static constexpr int R = KP / TPR;
+  static constexpr int ROWS = 256 / TPR;
+};
 
 template <typename T, int KP>
-__device__ __forceinline__ void store_row(T* __restrict__ dst, const T (&x)[KP]) {
-  constexpr int VEC = Tr<T>::VEC;
-#pragma unroll
-  for (int q = 0; q < KP / VEC; ++q) {
-    if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<float4*>(dst + q * 4) =
-          make_float4(x[q * 4], x[q * 4 + 1], x[q * 4 + 2], x[q * 4 + 3]);
-    } else {
-      *reinterpret_cast<double2*>(dst + q * 2) = make_double2(x[q * 2], x[q * 2 + 1]);
-    }
+__global__ __launch_bounds__(256) void hals_rows_grp_kernel(T* __restrict__ X,
+                                                            const T* __restrict__ P,
+                                                            const T* __restrict__ G,
+                                                            int64_t rows, int k) {
+  constexpr int TPR = HalsGroup<KP>::TPR, R = HalsGroup<KP>::R, ROWS = HalsGroup<KP>::ROWS;
+  __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
+  for (int e = threadIdx.x; e < KP * KP; e += 256) {
+    const int i = e / KP, j = e - i * KP;
+    Gs[e] = G[j * KP + i];
   }
-}
-
-template <typename T, int KP>
-__global__ __launch_bounds__(256) void hals_rows_kernel(T* __restrict__ X,
-                                                        const T* __restrict__ P,
-                                                        const T* __restrict__ G, int64_t rows,
-                                                        int k) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  T x[KP];
-  load_row<T, KP>(X + r * KP, x);
-  const T* pr = P + r * KP;
+  __syncthreads();
+  const int sub = threadIdx.x % TPR;
+  const int64_t r = (int64_t)blockIdx.x * ROWS + threadIdx.x / TPR;
+  const int64_t rr = r < rows ? r : rows - 1;
+  T x[R], p[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    x[q] = X[rr * KP + sub * R + q];
+    p[q] = P[rr * KP + sub * R + q];
+  }
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
     if (i < k) {
-      const T gii = G[i * KP + i];
+      const T gii = Gs[i * KP + i];
       if (gii > T(0)) {
-        T s = T(0);
+        const T* gc = &Gs[i * KP + sub * R];
+        T part = T(0);
 #pragma unroll
-        for (int j = 0; j < KP; ++j) s = fma(x[j], G[j * KP + i], s);
-        const T t = x[i] + (pr[i] - s) / gii;
-        x[i] = t > T(0) ? t : T(0);
+        for (int q = 0; q < R; ++q) part = fma(x[q], gc[q], part);
+        const T s = group_sum<TPR>(part);
+        if (sub == i / R) {
+          const T t = x[i % R] + (p[i % R] - s) / gii;
+          x[i % R] = t > T(0) ? t : T(0);
+        }
       }
     }
   }
-  store_row<T, KP>(X + r * KP, x);
+  if (r < rows) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) X[r * KP + sub * R + q] = x[q];
+  }
 }
 
 // Ranks above 64: the same updates with each thread's row kept in LDS
@@ -194,8 +201,8 @@ template <typename T>
 hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
                      hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)cdiv(rows, 256);
-  KP_SWITCH(KP, (hals_rows_kernel<T, KPc><<<blocks, 256, 0, st>>>(X, P, G, rows, k)),
+  KP_SWITCH(KP, (hals_rows_grp_kernel<T, KPc><<<(unsigned)cdiv(rows, HalsGroup<KPc>::ROWS), 256,
+                                                 0, st>>>(X, P, G, rows, k)),
             (hals_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
                 X, P, G, rows, k, KP)));
   return NMF_LAUNCH_CHECK();
