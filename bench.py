@@ -38,6 +38,8 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dense_65536x65536_k50.json")
 TRAFFIC_FILE_CSR = os.path.join(ROOT, "profiles", "traffic_csr_spmm_1048576_d1e-4_k50.json")
 SPARSE_SOURCES = ("sparse.hip", "common.h")
+LOWP_SOURCES = ("gemm_bf16.hip", "common.h")
+TRAFFIC_FILE_FP8 = os.path.join(ROOT, "profiles", "traffic_fp8_131072x65536_k100.json")
 COPY_CAL_BYTES = 3 << 30
 
 WORKLOADS = {
@@ -263,6 +265,9 @@ def run_lowp(args, wl):
     b = res[lp]
     ms_launch = 0.5 * (b["stats"]["ms_mm_aht"] + b["stats"]["ms_mm_wta"]) / args.steps
     bytes_launch = float(esize) * m * n
+    tr = (load_traffic(kernel_source_hash(LOWP_SOURCES), TRAFFIC_FILE_FP8, args.workload)
+          if lp == "fp8" else None)
+    traffic = tr["hbm_bytes_per_launch"] if tr else None
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     f = res["f32"]
     ms_launch32 = 0.5 * (f["stats"]["ms_mm_aht"] + f["stats"]["ms_mm_wta"]) / args.steps
@@ -287,7 +292,8 @@ def run_lowp(args, wl):
                              "tflops_products": round(2.0 * m * n * k / (ms_launch32 * 1e-3)
                                                       / 1e12, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
                      "kernel": ("gemm_lp_nt_kernel<uint16_t> (A H^T and A^T W, BF16 MFMA "
                                 "16x16x32)" if lp == "bf16" else
                                 "gemm_lp_nt_kernel<uint8_t> (A H^T and A^T W, FP8 MFMA "

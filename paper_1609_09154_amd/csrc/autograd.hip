@@ -162,22 +162,50 @@ __global__ void add_kernel(T* __restrict__ Y, const T* __restrict__ X, int64_t n
 // D (m x n, ld ldd) += X1 Y1^T + X2 Y2^T with X* m x KP and Y* n x KP (row
 // layout, KP contiguous). Each wave forms a 64 x 64 tile on the matrix cores
 // (16 x 16 x 4 tiles, the reduction index permuted so every operand load is
-// 16 bytes) and adds it to D; a workgroup is 64 rows x 256 columns.
+// 16 bytes) and adds it to D; a workgroup is 64 rows x 256 columns. The tile
+// goes to D through LDS, 16 rows at a time, so that each row of D is read and
+// written as whole 16-byte runs across consecutive lanes (vec: n, ldd and D
+// allow it; otherwise element by element).
 constexpr int RU = 64;
 template <typename T>
-__global__ __launch_bounds__(256) void rank_update_kernel(T* __restrict__ D, int64_t ldd,
+__global__ __launch_bounds__(256, 2) void rank_update_kernel(T* __restrict__ D, int64_t ldd,
                                                           int64_t m, int64_t n,
                                                           const T* __restrict__ X1,
                                                           const T* __restrict__ Y1,
                                                           const T* __restrict__ X2,
-                                                          const T* __restrict__ Y2, int KP) {
+                                                          const T* __restrict__ Y2, int KP,
+                                                          int vec) {
   constexpr int VEC = Tr<T>::VEC;
+  constexpr int LD = RU + VEC;          // LDS row pitch of a staged slab
+  constexpr int LPR = RU / VEC;         // lanes per row when draining (16 or 32)
+  constexpr int RPP = 64 / LPR;         // rows per pass (4 or 2)
   typedef typename Tr<T>::acc4 acc4;
+  __shared__ __attribute__((aligned(16))) T slab[4][16 * LD];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
   const int64_t r0 = (int64_t)blockIdx.y * RU;
   const int64_t c0 = ((int64_t)blockIdx.x * 4 + wave) * RU;
   if (c0 >= n) return;
+  // float: the wave's tile of D is loaded at the start, in the layout of the
+  // drain below, so that its latency hides behind the matrix-core work
+  constexpr bool PREFETCH = sizeof(T) == 4;
+  constexpr int NP = 16 / RPP;
+  V16<T> dpre[PREFETCH ? 4 : 1][PREFETCH ? NP : 1];
+  if constexpr (PREFETCH) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int64_t row = r0 + 16 * a + p * RPP + lane / LPR;
+        const int64_t col = c0 + (lane % LPR) * VEC;
+        if (vec && row < m && col < n) {
+          dpre[a][p] = load16<T>(D + row * ldd + col);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) dpre[a][p].v[v] = T(0);
+        }
+      }
+  }
   acc4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -214,19 +242,44 @@ __global__ __launch_bounds__(256) void rank_update_kernel(T* __restrict__ D, int
           for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(xa[a].v[v], yb[b].v[v], acc[a][b]);
     }
   }
+  T* sw = slab[wave];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 4; ++a) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + 16 * a + acc_row<T>(lane, r);
-      if (row < m) {
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int64_t col = c0 + 16 * b + c;
-          if (col < n) D[row * ldd + col] += acc[a][b][r];
+      for (int b = 0; b < 4; ++b) sw[acc_row<T>(lane, r) * LD + 16 * b + c] = acc[a][b][r];
+    // LDS operations of one wave complete in order: the reads below see the
+    // writes above, and the next slab's writes follow these reads.
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int p = 0; p < 16 / RPP; ++p) {
+      const int rl = p * RPP + lane / LPR;
+      const int cl = (lane % LPR) * VEC;
+      const int64_t row = r0 + 16 * a + rl, col = c0 + cl;
+      if (row < m && col < n) {
+        T* dp = D + row * ldd + col;
+        const T* sp = &sw[rl * LD + cl];
+        if (vec) {
+          V16<T> dv;
+          if constexpr (PREFETCH) dv = dpre[a][p];
+          else dv = load16<T>(dp);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) dv.v[v] += sp[v];
+          if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(dp) = make_float4(dv.v[0], dv.v[1], dv.v[2], dv.v[3]);
+          } else {
+            *reinterpret_cast<double2*>(dp) = make_double2(dv.v[0], dv.v[1]);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v)
+            if (col + v < n) dp[v] += sp[v];
         }
       }
     }
+    __builtin_amdgcn_wave_barrier();
+  }
 }
 
 // --- HALS (Section 4.2, Eq. (5)) -------------------------------------------
@@ -445,8 +498,10 @@ hipError_t rank_update(T* D, int64_t ldd, int64_t m, int64_t n, const T* X1, con
                        const T* X2, const T* Y2, int KP, hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (KP % (4 * Tr<T>::VEC) != 0) return hipErrorInvalidValue;
+  constexpr int VEC = Tr<T>::VEC;
+  const int vec = n % VEC == 0 && ldd % VEC == 0 && (uintptr_t)D % 16 == 0;
   dim3 grid((unsigned)cdiv(n, 4 * RU), (unsigned)cdiv(m, RU));
-  rank_update_kernel<T><<<grid, 256, 0, st>>>(D, ldd, m, n, X1, Y1, X2, Y2, KP);
+  rank_update_kernel<T><<<grid, 256, 0, st>>>(D, ldd, m, n, X1, Y1, X2, Y2, KP, vec);
   return NMF_LAUNCH_CHECK();
 }
 
