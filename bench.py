@@ -61,6 +61,15 @@ WORKLOADS = {
         m=627047, n=11708841, k=50, density=3.65e8 / (627047.0 * 11708841.0), algo="hals",
         dtype="f32", sparse=True, table1_s=67.0,
         table1_set="Stack Exchange (sparse, 627,047 x 12 Million)"),
+    "csr-118142155x118142155-nnz1020M-powerlaw-k50-hals-f32": dict(
+        m=118142155, n=118142155, k=50, nnz=1019903190, gen="powerlaw", algo="hals",
+        dtype="f32", sparse=True, table1_s=1500.0,
+        table1_set="Webbase-2001 (sparse, 118 Million x 118 Million, 1,019,903,190 entries)"),
+    "csr-207360x138240-d1e-3-k50-mu-f32": dict(
+        m=207360, n=138240, k=50, density=1e-3, algo="mu", dtype="f32", sparse=True,
+        paper_iter_s=0.065,
+        paper_set="Sparse synthetic (Erdos-Renyi 207,360 x 138,240, density 0.001), MU, "
+                  "16 nodes (Section 6.1)"),
     "dense-8192x4096-k64-mu50-autograd-f32": dict(m=8192, n=4096, k=64, k_true=64, algo="mu",
                                                   dtype="f32", autograd=True, iters=50,
                                                   ckpt_every=10),
@@ -124,8 +133,15 @@ def cpu_baseline(wl, sample_rows, iters=6):
 
 
 def add_paper_context(out, wl):
-    """For the Table 1 shapes: the paper's time beside ours (other hardware,
-    context only)."""
+    """For the Table 1 shapes and the paper's MU timing: the paper's time
+    beside ours (other hardware, context only)."""
+    if "paper_iter_s" in wl:
+        out["paper_context"] = {
+            "data_set_shape": wl["paper_set"],
+            "paper_seconds_per_iteration": wl["paper_iter_s"],
+            "this_seconds_per_iteration": round(out["ms_per_step"] / 1000.0, 5),
+        }
+        return
     if "table1_s" not in wl:
         return
     out["paper_context"] = {
@@ -162,21 +178,44 @@ def run_sparse(args, wl):
     m, n, k = wl["m"], wl["n"], wl["k"]
     dev = torch.device("cuda:0")
     print("[bench] generating %s" % args.workload, file=sys.stderr, flush=True)
-    csr = erdos_renyi_csr(m, n, wl["density"], seed=1609)
-    nnz = csr.nnz
-    rp = torch.from_numpy(csr.rowptr).to(dev)
-    ci = torch.from_numpy(csr.colidx).to(dev)
-    cv = torch.from_numpy(csr.vals.astype(np.float32)).to(dev)
-    W0n, H0n = init_factors(m, n, k, seed=9154)
-    W0 = torch.from_numpy(W0n.astype(np.float32)).to(dev)
-    H0 = torch.from_numpy(H0n.astype(np.float32)).to(dev)
-    del csr
+    if wl.get("gen") == "powerlaw":
+        # drawn on the device: the host copies would be tens of GB; the
+        # initial factors are U(0,1) from torch's seeded generator there
+        from synth import powerlaw_csr_torch
+
+        rp, ci, cv = powerlaw_csr_torch(m, n, wl["nnz"], seed=1609, device=dev)
+        nnz = ci.numel()
+        gen = torch.Generator(device=dev)
+
+        def init():
+            gen.manual_seed(9154)
+            return (torch.rand((m, k), generator=gen, device=dev, dtype=torch.float32),
+                    torch.rand((k, n), generator=gen, device=dev, dtype=torch.float32))
+
+        W, H = init()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    else:
+        csr = erdos_renyi_csr(m, n, wl["density"], seed=1609)
+        nnz = csr.nnz
+        rp = torch.from_numpy(csr.rowptr).to(dev)
+        ci = torch.from_numpy(csr.colidx).to(dev)
+        cv = torch.from_numpy(csr.vals.astype(np.float32)).to(dev)
+        W0n, H0n = init_factors(m, n, k, seed=9154)
+        W0 = torch.from_numpy(W0n.astype(np.float32)).to(dev)
+        H0 = torch.from_numpy(H0n.astype(np.float32)).to(dev)
+        del csr
+
+        def init():
+            return W0.clone(), H0.clone()
+
+        W, H = init()
     torch.cuda.synchronize()
     print("[bench] warmup %d" % args.warmup, file=sys.stderr, flush=True)
-    W, H = W0.clone(), H0.clone()
-    nmf.nmf_csr(rp, ci, cv, n, W, H, algo=wl["algo"], iters=args.warmup, objective=False)
-    W.copy_(W0)
-    H.copy_(H0)
+    if args.warmup > 0:
+        nmf.nmf_csr(rp, ci, cv, n, W, H, algo=wl["algo"], iters=args.warmup, objective=False)
+        del W, H
+        W, H = init()
     torch.cuda.synchronize()
     print("[bench] timing %d steps" % args.steps, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -191,8 +230,9 @@ def run_sparse(args, wl):
     tr = load_traffic(kernel_source_hash(SPARSE_SOURCES), TRAFFIC_FILE_CSR, args.workload)
     traffic = tr["hbm_bytes_per_launch"] if tr else None
     out = {
-        "metric": "NMF iterations/s (sparse %s, ER CSR %dx%d, %d stored entries, k=%d)"
-                  % (wl["algo"].upper(), m, n, nnz, k),
+        "metric": "NMF iterations/s (sparse %s, %s CSR %dx%d, %d stored entries, k=%d)"
+                  % (wl["algo"].upper(), "power-law" if wl.get("gen") == "powerlaw" else "ER",
+                     m, n, nnz, k),
         "value": round(args.steps / elapsed, 3), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",

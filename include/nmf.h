@@ -173,6 +173,9 @@ nmf_status nmf_dense(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n,
 /* Full AU-NMF on a sparse A in CSR form, float32 values.
  *   rowptr  m+1 int64, rowptr[0] = 0, rowptr[m] = nnz, nondecreasing.
  *   colidx  nnz int32 column ids in [0, n), increasing within each row.
+ *   m, n <= 2^31 - 1 (A^T is built with int32 column ids too), nnz < 2^32.
+ *   Rows (of A or A^T) longer than 4096 stored entries are split into
+ *   chunks for the products, so power-law row lengths stay balanced.
  *   vals    nnz floats >= 0.
  * W (m x k) and H (k x n) are float32 as for nmf_dense. The transpose of A
  * (needed for W^T A) is built once per call on the device. */

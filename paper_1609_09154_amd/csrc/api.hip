@@ -230,7 +230,7 @@ nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part) {
 // Workspace offsets for an AU-NMF call on an m x n problem.
 template <typename T>
 size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_t extra_part,
-                 Carve& cv, size_t off[17]) {
+                 Carve& cv, size_t off[17], bool sparse = false) {
   const int64_t ps_p = std::max(nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
                                 nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n));
   const int64_t ps_r = nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m);
@@ -250,8 +250,9 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[9] = cv.take<double>(iters + 2);
   off[10] = cv.take<int>(4);
   off[11] = cv.take<unsigned long long>(2);
-  off[12] = cv.take<T>(m * KP);
-  off[13] = cv.take<T>(n * KP);
+  // transposed factor copies for the dense products (unused for sparse A)
+  off[12] = cv.take<T>(sparse ? 0 : m * KP);
+  off[13] = cv.take<T>(sparse ? 0 : n * KP);
   off[14] = cv.take<double>(KP * KP);
   off[15] = cv.take<double>(nmfk::pgrad_partials(std::max(m, n)));
   off[16] = cv.take<double>(4);
@@ -316,6 +317,8 @@ template <typename T> struct Prob {
   const int64_t* rp = nullptr; const int32_t* ci = nullptr; const float* cv = nullptr;  // CSR A
   const int64_t* rpt = nullptr; const int32_t* cit = nullptr; const float* cvt = nullptr; // CSR A^T
   int64_t nnz = 0;
+  const nmfk::CsrLongRows* lra = nullptr;   // long rows of A and of A^T (nullable)
+  const nmfk::CsrLongRows* lrat = nullptr;
 };
 
 // Elements per 16 bytes of a reduced-precision A: the pitch unit of its rows
@@ -347,7 +350,7 @@ nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, con
                       const T* Ft, int k, int KP, T* Pout, T* part) {
   if (pb.sparse) {
     if constexpr (sizeof(T) == 4) {
-      HIP_TRY(nmfk::csr_spmm(pb.rp, pb.ci, pb.cv, m, F, KP, Pout, ctx->stream));
+      HIP_TRY(nmfk::csr_spmm(pb.rp, pb.ci, pb.cv, m, F, KP, Pout, pb.lra, ctx->stream));
       return NMF_OK;
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
@@ -375,7 +378,7 @@ nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, co
                        const T* Ft, int k, int KP, T* Rout, T* part) {
   if (pb.sparse) {
     if constexpr (sizeof(T) == 4) {
-      HIP_TRY(nmfk::csr_spmm(pb.rpt, pb.cit, pb.cvt, n, F, KP, Rout, ctx->stream));
+      HIP_TRY(nmfk::csr_spmm(pb.rpt, pb.cit, pb.cvt, n, F, KP, Rout, pb.lrat, ctx->stream));
       return NMF_OK;
     }
     return fail(ctx, NMF_EINVAL, "sparse path is float32 only");
@@ -853,7 +856,9 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   if (!rowptr || !W || !H || (nnz > 0 && (!colidx || !vals)))
     return fail(ctx, NMF_EINVAL, "null CSR array, W or H");
   if (nnz < 0 || nnz > ((int64_t)1 << 40)) return fail(ctx, NMF_EINVAL, "bad nnz");
-  if (n > INT32_MAX) return fail(ctx, NMF_EINVAL, "n must fit int32 column ids");
+  if (n > INT32_MAX || m > INT32_MAX)
+    return fail(ctx, NMF_EINVAL, "m and n must fit int32 column ids (of A and of A^T)");
+  if (nnz > (int64_t)UINT32_MAX) return fail(ctx, NMF_EINVAL, "nnz must be below 2^32");
   if ((s = bind_device(ctx)) != NMF_OK) return s;
   typedef float T;
   const int KP = kp_sparse(k);
@@ -861,11 +866,13 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   const int64_t obj_np = std::max<int64_t>(nmfk::csr_residual_partials(m), 1024);
   Carve cv;
   size_t off[17];
-  plan_work<T>(m, n, KP, opts->iters, obj_np, 0, cv, off);
+  plan_work<T>(m, n, KP, opts->iters, obj_np, 0, cv, off, true);
   const size_t o_rpt = cv.take<int64_t>(n + 1);
   const size_t o_cit = cv.take<int32_t>(nnz);
   const size_t o_cvt = cv.take<float>(nnz);
   const size_t o_tw = cv.take<char>(nmfk::csr_transpose_work_bytes(m, n, nnz));
+  const size_t o_la = cv.take<char>(nmfk::csr_long_work_bytes(nnz, KP));
+  const size_t o_lat = cv.take<char>(nmfk::csr_long_work_bytes(nnz, KP));
   if ((s = ensure_ws(ctx, cv.off)) != NMF_OK) return s;
   Work<T> w = bind_work<T>(ctx, off, obj_np);
   hipStream_t st = ctx->stream;
@@ -894,6 +901,11 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   pb.cvt = at<float>(ctx, o_cvt);
   HIP_TRY(nmfk::csr_transpose(rowptr, colidx, vals, m, n, nnz, (int64_t*)pb.rpt, (int32_t*)pb.cit,
                               (float*)pb.cvt, at<char>(ctx, o_tw), st));
+  nmfk::CsrLongRows lra, lrat;
+  HIP_TRY(nmfk::csr_long_rows(rowptr, m, nnz, KP, at<char>(ctx, o_la), &lra, st));
+  HIP_TRY(nmfk::csr_long_rows(pb.rpt, n, nnz, KP, at<char>(ctx, o_lat), &lrat, st));
+  pb.lra = &lra;
+  pb.lrat = &lrat;
   HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, st));
   HIP_TRY(nmfk::transpose_in<T>(H, k, n, w.Ht, KP, st));
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -1157,11 +1169,14 @@ nmf_status nmf_csr_AF(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int
   Carve cv;
   const size_t oF = cv.take<float>(n * KP);
   const size_t oO = cv.take<float>(m * KP);
+  const size_t oL = cv.take<char>(nmfk::csr_long_work_bytes(nnz, KP));
   if ((s = ensure_ws(ctx, cv.off)) != NMF_OK) return s;
   float* Fp = at<float>(ctx, oF);
   float* Op = at<float>(ctx, oO);
   HIP_TRY(nmfk::pad_rows<float>(F, n, k, Fp, KP, ctx->stream));
-  HIP_TRY(nmfk::csr_spmm(rowptr, colidx, vals, m, Fp, KP, Op, ctx->stream));
+  nmfk::CsrLongRows lr;
+  HIP_TRY(nmfk::csr_long_rows(rowptr, m, nnz, KP, at<char>(ctx, oL), &lr, ctx->stream));
+  HIP_TRY(nmfk::csr_spmm(rowptr, colidx, vals, m, Fp, KP, Op, &lr, ctx->stream));
   HIP_TRY(nmfk::unpad_rows<float>(Op, m, k, KP, P, ctx->stream));
   return NMF_OK;
 }
@@ -1173,7 +1188,8 @@ nmf_status nmf_csr_transpose(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz,
   if (s != NMF_OK) return s;
   if (!rowptr || !rowptr_t || (nnz > 0 && (!colidx || !vals || !colidx_t || !vals_t)))
     return fail(ctx, NMF_EINVAL, "null CSR array");
-  if (nnz < 0 || n > INT32_MAX || m > INT32_MAX) return fail(ctx, NMF_EINVAL, "bad sizes");
+  if (nnz < 0 || nnz > (int64_t)UINT32_MAX || n > INT32_MAX || m > INT32_MAX)
+    return fail(ctx, NMF_EINVAL, "bad sizes");
   if ((s = bind_device(ctx)) != NMF_OK) return s;
   Carve cv;
   const size_t oT = cv.take<char>(nmfk::csr_transpose_work_bytes(m, n, nnz));

@@ -126,8 +126,21 @@ hipError_t finish_relerr(const double* partial, int64_t np, const T* G1, const T
                          const double* ref_sq, double* out, hipStream_t st);
 
 // Sparse (CSR, float32 values).
+// Rows with more than a fixed number of stored entries (csr_long_rows, in
+// scratch of csr_long_work_bytes(nnz, KP) bytes; synchronises the stream to
+// read two counts) are computed in chunks by csr_spmm when lr describes them.
+struct CsrLongRows {
+  int64_t nlong = 0, nchunks = 0;
+  const int64_t* ids = nullptr;        // the long rows
+  const int64_t* chunk_off = nullptr;  // nlong + 1 chunk offsets
+  float* part = nullptr;               // nchunks x KP partial sums
+};
+size_t csr_long_work_bytes(int64_t nnz, int KP);
+hipError_t csr_long_rows(const int64_t* rowptr, int64_t m, int64_t nnz, int KP, void* work,
+                         CsrLongRows* out, hipStream_t st);
+// P (m x KP) = A F; lr nullable (then every row is one wave's work).
 hipError_t csr_spmm(const int64_t* rowptr, const int32_t* colidx, const float* vals, int64_t m,
-                    const float* F, int KP, float* P, hipStream_t st);
+                    const float* F, int KP, float* P, const CsrLongRows* lr, hipStream_t st);
 // `work` holds csr_transpose_work_bytes(m, n, nnz) bytes of scratch.
 hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const float* vals,
                          int64_t m, int64_t n, int64_t nnz, int64_t* rowptr_t,

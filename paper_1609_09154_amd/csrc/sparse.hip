@@ -8,24 +8,26 @@
 // major), so a group reads one whole dense row with one instruction and the
 // wave keeps 64/(KP/4) gathers in flight per step. Group partial sums are
 // combined with cross-lane shuffles at the end of the row, in a fixed order.
+// Rows longer than CSR_LONG entries are cut into chunks of that length (one
+// wave each) whose partials are added in chunk order.
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace nmfk {
 
+// Sum over the stored entries b..e-1 of a row of a_ij F[j] (one output row of
+// KP floats), computed by the whole wave and returned, complete, in the
+// lanes of group 0 (lane sub holds columns 4 sub .. 4 sub + 3).
 template <int KP>
-__global__ __launch_bounds__(256) void csr_spmm_kernel(const int64_t* __restrict__ rowptr,
-                                                       const int32_t* __restrict__ colidx,
-                                                       const float* __restrict__ vals,
-                                                       int64_t m, const float* __restrict__ F,
-                                                       float* __restrict__ P) {
+__device__ __forceinline__ float4 segment_sum(const int32_t* __restrict__ colidx,
+                                              const float* __restrict__ vals,
+                                              const float* __restrict__ F, int64_t b, int64_t e,
+                                              int grp, int sub) {
   constexpr int LPN = KP / 4;     // lanes per stored entry
   constexpr int GPW = 64 / LPN;   // entries in flight per wave step
-  const int lane = threadIdx.x & 63;
-  const int grp = lane / LPN, sub = lane % LPN;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= m) return;
-  const int64_t b = rowptr[row], e = rowptr[row + 1];
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   int64_t p = b + grp;
   // unrolled by 4 entries per group
@@ -64,28 +66,106 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(const int64_t* __restrict
     acc.z += __shfl_xor(acc.z, off, 64);
     acc.w += __shfl_xor(acc.w, off, 64);
   }
+  return acc;
+}
+
+// One wave per output row; rows with more than long_limit stored entries
+// are left to the chunked path below.
+template <int KP>
+__global__ __launch_bounds__(256) void csr_spmm_kernel(const int64_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ colidx,
+                                                       const float* __restrict__ vals,
+                                                       int64_t m, const float* __restrict__ F,
+                                                       float* __restrict__ P, int64_t long_limit) {
+  constexpr int LPN = KP / 4;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / LPN, sub = lane % LPN;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= m) return;
+  const int64_t b = rowptr[row], e = rowptr[row + 1];
+  if (e - b > long_limit) return;
+  const float4 acc = segment_sum<KP>(colidx, vals, F, b, e, grp, sub);
   if (grp == 0) *reinterpret_cast<float4*>(P + row * KP + 4 * sub) = acc;
 }
 
+// Long rows (power-law sparsity puts much of the work in a few of them): each
+// is cut into chunks of CSR_LONG stored entries, one wave per chunk writes
+// its partial sums, and the partials of a row are then added in chunk order,
+// so the result does not depend on scheduling.
+constexpr int64_t CSR_LONG = 4096;
+
+template <int KP>
+__global__ __launch_bounds__(256) void csr_chunk_kernel(
+    const int64_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const float* __restrict__ vals, const float* __restrict__ F, const int64_t* __restrict__ ids,
+    const int64_t* __restrict__ chunk_off, int64_t nlong, int64_t nchunks,
+    float* __restrict__ part) {
+  constexpr int LPN = KP / 4;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / LPN, sub = lane % LPN;
+  const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (c >= nchunks) return;
+  // the long row that holds chunk c: the last i with chunk_off[i] <= c
+  int64_t lo = 0, hi = nlong - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (chunk_off[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t row = ids[lo];
+  const int64_t b = rowptr[row] + (c - chunk_off[lo]) * CSR_LONG;
+  const int64_t e = b + CSR_LONG < rowptr[row + 1] ? b + CSR_LONG : rowptr[row + 1];
+  const float4 acc = segment_sum<KP>(colidx, vals, F, b, e, grp, sub);
+  if (grp == 0) *reinterpret_cast<float4*>(part + c * KP + 4 * sub) = acc;
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void csr_chunk_reduce_kernel(
+    const int64_t* __restrict__ ids, const int64_t* __restrict__ chunk_off, int64_t nlong,
+    const float* __restrict__ part, float* __restrict__ P) {
+  constexpr int Q = KP / 4;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / Q;
+  const int q = (int)(t % Q);
+  if (i >= nlong) return;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int64_t c = chunk_off[i]; c < chunk_off[i + 1]; ++c) {
+    const float4 v = *reinterpret_cast<const float4*>(part + c * KP + 4 * q);
+    s.x += v.x;
+    s.y += v.y;
+    s.z += v.z;
+    s.w += v.w;
+  }
+  *reinterpret_cast<float4*>(P + ids[i] * KP + 4 * q) = s;
+}
+
 hipError_t csr_spmm(const int64_t* rowptr, const int32_t* colidx, const float* vals, int64_t m,
-                    const float* F, int KP, float* P, hipStream_t st) {
+                    const float* F, int KP, float* P, const CsrLongRows* lr, hipStream_t st) {
   if (m <= 0) return hipSuccess;
+  const bool split = lr != nullptr && lr->nlong > 0;
+  const int64_t limit = split ? CSR_LONG : INT64_MAX;
   const unsigned blocks = (unsigned)cdiv(m, 4);
+#define CASE(K)                                                                               \
+  case K:                                                                                     \
+    csr_spmm_kernel<K><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P, limit);         \
+    if (split) {                                                                              \
+      csr_chunk_kernel<K><<<(unsigned)cdiv(lr->nchunks, 4), 256, 0, st>>>(                    \
+          rowptr, colidx, vals, F, lr->ids, lr->chunk_off, lr->nlong, lr->nchunks, lr->part);  \
+      csr_chunk_reduce_kernel<K><<<(unsigned)cdiv(lr->nlong * (K / 4), 256), 256, 0, st>>>(    \
+          lr->ids, lr->chunk_off, lr->nlong, lr->part, P);                                    \
+    }                                                                                         \
+    break;
   switch (KP) {
-    case 16: csr_spmm_kernel<16><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
-    case 32: csr_spmm_kernel<32><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
-    case 64: csr_spmm_kernel<64><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
-    case 128: csr_spmm_kernel<128><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P); break;
+    CASE(16) CASE(32) CASE(64) CASE(128)
     default: return hipErrorInvalidValue;
   }
+#undef CASE
   return NMF_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------
 // CSR transpose: count entries per column, exclusive scan into the new row
-// pointers, scatter (slot order within a column is arbitrary), then put each
-// new row in increasing column order by ranking its entries. Keys within a
-// row are distinct, so the result is unique and the same on every run.
+// pointers, then a stable radix sort of the entries by column.
 // ---------------------------------------------------------------------------
 __global__ void count_cols_kernel(const int32_t* __restrict__ colidx, int64_t nnz,
                                   int32_t* __restrict__ counts) {
@@ -170,50 +250,56 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = nnz;
 }
 
-// One thread per source row: scatter its entries into their new rows.
-__global__ void scatter_kernel(const int64_t* __restrict__ rowptr,
-                               const int32_t* __restrict__ colidx,
-                               const float* __restrict__ vals, int64_t m,
-                               const int64_t* __restrict__ rowptr_t,
-                               int32_t* __restrict__ cursor, int32_t* __restrict__ tmp_key,
-                               float* __restrict__ tmp_val) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per source row: each stored entry's payload is its row id (high
+// 32 bits) and its value's bits (low 32 bits).
+__global__ __launch_bounds__(256) void entry_payload_kernel(const int64_t* __restrict__ rowptr,
+                                                            int64_t m,
+                                                            const float* __restrict__ vals,
+                                                            uint64_t* __restrict__ pay) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= m) return;
-  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-    const int32_t j = colidx[p];
-    const int64_t pos = rowptr_t[j] + atomicAdd(&cursor[j], 1);
-    tmp_key[pos] = (int32_t)i;
-    tmp_val[pos] = vals[p];
-  }
+  const uint64_t hi = (uint64_t)i << 32;
+  for (int64_t p = rowptr[i] + lane; p < rowptr[i + 1]; p += 64)
+    pay[p] = hi | (uint64_t)__float_as_uint(vals[p]);
 }
 
-// One wave per new row: rank each entry among the row's keys and write it
-// to its sorted slot.
-__global__ __launch_bounds__(256) void rank_sort_kernel(const int64_t* __restrict__ rowptr_t,
-                                                        int64_t n,
-                                                        const int32_t* __restrict__ tmp_key,
-                                                        const float* __restrict__ tmp_val,
-                                                        int32_t* __restrict__ colidx_t,
-                                                        float* __restrict__ vals_t) {
-  const int lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (j >= n) return;
-  const int64_t b = rowptr_t[j], e = rowptr_t[j + 1];
-  for (int64_t p = b + lane; p < e; p += 64) {
-    const int32_t key = tmp_key[p];
-    int64_t rank = 0;
-    for (int64_t q = b; q < e; ++q) rank += tmp_key[q] < key ? 1 : 0;
-    colidx_t[b + rank] = key;
-    vals_t[b + rank] = tmp_val[p];
-  }
+__global__ void unpack_payload_kernel(const uint64_t* __restrict__ pay, int64_t nnz,
+                                      int32_t* __restrict__ colidx_t, float* __restrict__ vals_t) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  const uint64_t v = pay[q];
+  colidx_t[q] = (int32_t)(v >> 32);
+  vals_t[q] = __uint_as_float((unsigned)(v & 0xffffffffu));
+}
+
+// Key bits of the column ids (enough for n - 1).
+static unsigned col_bits(int64_t n) {
+  unsigned b = 1;
+  while (b < 32 && ((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+static size_t sort_temp_bytes(int64_t n, int64_t nnz) {
+  size_t bytes = 0;
+  if (nnz > 0)
+    (void)rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                    (const uint64_t*)nullptr, (uint64_t*)nullptr, (size_t)nnz, 0u,
+                                    col_bits(n), (hipStream_t)0);
+  return bytes;
 }
 
 size_t csr_transpose_work_bytes(int64_t m, int64_t n, int64_t nnz) {
   (void)m;
   const size_t nb = (size_t)cdiv(n, SCAN_BLOCK);
-  return round_up((size_t)n * 4, 256) + round_up(nb * 8, 256) + round_up((size_t)nnz * 4, 256) * 2;
+  return round_up((size_t)n * 4, 256) + round_up(nb * 8, 256) + round_up((size_t)nnz * 4, 256) +
+         2 * round_up((size_t)nnz * 8, 256) + round_up(sort_temp_bytes(n, nnz), 256);
 }
 
+// Counts per column and their exclusive scan give the new row pointers; a
+// stable radix sort of the entries (in row-major order) by column then puts
+// each new row's entries in increasing order of their source row, so the
+// result is unique and the same on every run, whatever the row lengths.
 hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const float* vals,
                          int64_t m, int64_t n, int64_t nnz, int64_t* rowptr_t,
                          int32_t* colidx_t, float* vals_t, void* work, hipStream_t st) {
@@ -223,9 +309,13 @@ hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const flo
   const int64_t nb = cdiv(n, SCAN_BLOCK);
   int64_t* bsum = (int64_t*)w;
   w += round_up((size_t)nb * 8, 256);
-  int32_t* tmp_key = (int32_t*)w;
+  uint32_t* keys_out = (uint32_t*)w;
   w += round_up((size_t)nnz * 4, 256);
-  float* tmp_val = (float*)w;
+  uint64_t* pay_in = (uint64_t*)w;
+  w += round_up((size_t)nnz * 8, 256);
+  uint64_t* pay_out = (uint64_t*)w;
+  w += round_up((size_t)nnz * 8, 256);
+  void* temp = w;
   hipError_t e = hipMemsetAsync(counts, 0, (size_t)n * 4, st);
   if (e != hipSuccess) return e;
   if (nnz > 0) count_cols_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(colidx, nnz, counts);
@@ -234,12 +324,89 @@ hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const flo
   scan_apply_kernel<<<(unsigned)nb, 256, 0, st>>>(counts, n, bsum, nnz, rowptr_t);
   if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
   if (nnz == 0) return hipSuccess;
-  if ((e = hipMemsetAsync(counts, 0, (size_t)n * 4, st)) != hipSuccess) return e;
-  scatter_kernel<<<(unsigned)cdiv(m, 256), 256, 0, st>>>(rowptr, colidx, vals, m, rowptr_t,
-                                                         counts, tmp_key, tmp_val);
-  rank_sort_kernel<<<(unsigned)cdiv(n, 4), 256, 0, st>>>(rowptr_t, n, tmp_key, tmp_val,
-                                                         colidx_t, vals_t);
+  entry_payload_kernel<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(rowptr, m, vals, pay_in);
+  if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
+  size_t temp_bytes = sort_temp_bytes(n, nnz);
+  e = rocprim::radix_sort_pairs(temp, temp_bytes, (const uint32_t*)colidx, keys_out, pay_in,
+                                pay_out, (size_t)nnz, 0u, col_bits(n), st);
+  if (e != hipSuccess) return e;
+  unpack_payload_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(pay_out, nnz, colidx_t,
+                                                                  vals_t);
   return NMF_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Long rows of a CSR matrix for the chunked SpMM path (built once per call).
+// ---------------------------------------------------------------------------
+__global__ void find_long_kernel(const int64_t* __restrict__ rowptr, int64_t m, int64_t cap,
+                                 int64_t* __restrict__ ids,
+                                 unsigned long long* __restrict__ count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (rowptr[i + 1] - rowptr[i] > CSR_LONG) {
+      const unsigned long long slot = atomicAdd(count, 1ull);
+      if ((int64_t)slot < cap) ids[slot] = i;
+    }
+  }
+}
+
+// off[i] = chunks of long row ids[i] (i < nlong), off[nlong] = 0; an
+// exclusive scan then turns off into the chunk offsets and off[nlong] into
+// the chunk count.
+__global__ void long_chunks_kernel(const int64_t* __restrict__ rowptr,
+                                   const int64_t* __restrict__ ids, int64_t nlong,
+                                   int64_t* __restrict__ off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > nlong) return;
+  off[i] = i < nlong ? cdiv(rowptr[ids[i] + 1] - rowptr[ids[i]], CSR_LONG) : 0;
+}
+
+static int64_t long_cap(int64_t nnz) { return nnz / CSR_LONG + 1; }
+
+size_t csr_long_work_bytes(int64_t nnz, int KP) {
+  const int64_t cap = long_cap(nnz);
+  return 256 + round_up((size_t)cap * 8, 256) + round_up((size_t)(cap + 1) * 8, 256) +
+         round_up((size_t)(2 * cap) * KP * 4, 256);
+}
+
+hipError_t csr_long_rows(const int64_t* rowptr, int64_t m, int64_t nnz, int KP, void* work,
+                         CsrLongRows* out, hipStream_t st) {
+  *out = CsrLongRows{};
+  if (m <= 0 || nnz <= CSR_LONG) return hipSuccess;  // no row can be long
+  const int64_t cap = long_cap(nnz);
+  char* w = (char*)work;
+  unsigned long long* count = (unsigned long long*)w;
+  w += 256;
+  int64_t* ids = (int64_t*)w;
+  w += round_up((size_t)cap * 8, 256);
+  int64_t* off = (int64_t*)w;
+  w += round_up((size_t)(cap + 1) * 8, 256);
+  float* part = (float*)w;
+  hipError_t e = hipMemsetAsync(count, 0, sizeof(unsigned long long), st);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = cdiv(m, 256) < 4096 ? cdiv(m, 256) : 4096;
+  find_long_kernel<<<(unsigned)blocks, 256, 0, st>>>(rowptr, m, cap, ids, count);
+  unsigned long long nlong = 0;
+  if ((e = hipMemcpyAsync(&nlong, count, sizeof(nlong), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (nlong == 0) return hipSuccess;
+  if ((int64_t)nlong > cap) return hipErrorInvalidValue;  // a row longer than nnz allows
+  long_chunks_kernel<<<(unsigned)cdiv((int64_t)nlong + 1, 256), 256, 0, st>>>(
+      rowptr, ids, (int64_t)nlong, off);
+  scan_top_kernel<<<1, 256, 0, st>>>(off, (int64_t)nlong + 1);
+  int64_t nchunks = 0;
+  if ((e = hipMemcpyAsync(&nchunks, off + nlong, sizeof(nchunks), hipMemcpyDeviceToHost, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  if (nchunks > 2 * cap) return hipErrorInvalidValue;
+  out->nlong = (int64_t)nlong;
+  out->nchunks = nchunks;
+  out->ids = ids;
+  out->chunk_off = off;
+  out->part = part;
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -7,7 +7,8 @@ library consume what it returns (arrays, never code).
 Workload shapes follow the paper's synthetic data sets (Section 6.1.1, "Data
 Sets"): a dense low-rank matrix built as the product of two U(0,1) factors,
 and an Erdos-Renyi sparse matrix in which every entry is nonzero
-independently with a fixed probability. The dense generator adds
+independently with a fixed probability. For the shapes of its web-crawl
+data, a power-law sparsity generator stands in (powerlaw_csr_torch). The dense generator adds
 |N(0, sigma)| noise so that the planted factorisation is not exact; the
 initial factors are U(0,1) from their own seed, shared across the three
 algorithms as Section 6.1.3 asks ("the same random seed" for the initial H).
@@ -153,6 +154,57 @@ def erdos_renyi_csr(m: int, n: int, density: float, seed: int = DATA_SEED,
     np.cumsum(counts, out=rowptr[1:])
     vals = rng.random(flat.size, dtype=np.float64).astype(dtype)
     return CSR(m, n, rowptr, cols, vals)
+
+
+def powerlaw_csr_torch(m: int, n: int, nnz: int, seed: int = DATA_SEED, row_tail: float = 2.5,
+                       col_skew: float = 0.7, device="cpu"):
+    """Web-graph-like sparsity (a stand-in for the crawl matrices the paper
+    factorises, such as webbase-2001): row lengths and column popularity
+    both follow power laws.
+
+    - Row lengths: w_i = u_i^(-1 / (row_tail - 1)) for u_i ~ U(0, 1]
+      (a Pareto tail with exponent row_tail), scaled so that they sum to
+      ``nnz`` and rounded stochastically, at most n.
+    - Columns: each entry picks a popularity rank r in [0, n) from the
+      density proportional to (r + 1)^(-col_skew) by inverse-CDF sampling,
+      and the column is perm[r] for a seeded random permutation perm, so the
+      hub columns (the long rows of A^T) are scattered.
+    - A column drawn twice in one row is kept once, so the stored count is
+      a little below ``nnz``; columns are sorted within each row; values are
+      U(0, 1).
+
+    Drawn with torch's seeded generator on ``device`` (the same seed gives
+    the same matrix on one device type). Returns (rowptr int64 (m+1),
+    colidx int32, vals float32) as tensors on ``device``."""
+    import torch
+
+    dev = torch.device(device)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    u = 1.0 - torch.rand(m, generator=g, device=dev, dtype=torch.float64)      # (0, 1]
+    w = u.pow(-1.0 / (row_tail - 1.0))
+    want = w * (float(nnz) / float(w.sum()))
+    lengths = torch.floor(want + torch.rand(m, generator=g, device=dev, dtype=torch.float64))
+    lengths = lengths.clamp_(0, n).to(torch.int64)
+    total = int(lengths.sum())
+    rows = torch.repeat_interleave(torch.arange(m, device=dev, dtype=torch.int64), lengths)
+    v = torch.rand(total, generator=g, device=dev, dtype=torch.float64)
+    a = 1.0 - col_skew
+    span = float(n + 1) ** a - 1.0
+    rank = torch.floor((1.0 + v * span).pow(1.0 / a) - 1.0).clamp_(0, n - 1).to(torch.int64)
+    del v
+    perm = torch.randperm(n, generator=g, device=dev)
+    key = rows * n + perm[rank]
+    del rows, rank, perm
+    key = torch.unique(key, sorted=True)            # sorted by (row, column), duplicates gone
+    r = torch.div(key, n, rounding_mode="floor")
+    colidx = (key - r * n).to(torch.int32)
+    counts = torch.bincount(r, minlength=m)
+    del key, r
+    rowptr = torch.zeros(m + 1, dtype=torch.int64, device=dev)
+    torch.cumsum(counts, 0, out=rowptr[1:])
+    vals = torch.rand(colidx.numel(), generator=g, device=dev, dtype=torch.float32)
+    return rowptr, colidx, vals
 
 
 def csr_from_dense(D: np.ndarray, dtype=None) -> CSR:
