@@ -23,19 +23,15 @@ namespace nmfk {
 // it. G is staged in LDS with column i contiguous (Gs[i][j] = G[j][i]), so a
 // lane reads its R entries of the column with one vector load. Rows past the
 // end run on a clamped copy of the last row (every lane must join the group
-// sums) and store nothing.
-template <int KP> struct HalsGroup {
-  static constexpr int TPR = KP == 16 ? 4 : (KP == 32 ? 8 : 16);
-  static constexpr int R = KP / TPR;
-  static constexpr int ROWS = 256 / TPR;
-};
-
-template <typename T, int KP>
+// sums) and store nothing. TPR (4, 8 or 16 lanes per row) is chosen from the
+// number of rows: many rows fill the chip with small groups, which take fewer
+// permutation steps per column; few rows need larger groups to fill it.
+template <typename T, int KP, int TPR>
 __global__ __launch_bounds__(256) void hals_rows_grp_kernel(T* __restrict__ X,
                                                             const T* __restrict__ P,
                                                             const T* __restrict__ G,
                                                             int64_t rows, int k) {
-  constexpr int TPR = HalsGroup<KP>::TPR, R = HalsGroup<KP>::R, ROWS = HalsGroup<KP>::ROWS;
+  constexpr int R = KP / TPR, ROWS = 256 / TPR;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
   for (int e = threadIdx.x; e < KP * KP; e += 256) {
     const int i = e / KP, j = e - i * KP;
@@ -197,12 +193,23 @@ hipError_t mu_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, T 
   return NMF_LAUNCH_CHECK();
 }
 
+template <typename T, int KP>
+void launch_hals_grp(T* X, const T* P, const T* G, int64_t rows, int k, int tpr,
+                     hipStream_t st) {
+  if (tpr == 4)
+    hals_rows_grp_kernel<T, KP, 4><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(X, P, G, rows, k);
+  else if (tpr == 8)
+    hals_rows_grp_kernel<T, KP, 8><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(X, P, G, rows, k);
+  else
+    hals_rows_grp_kernel<T, KP, 16><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(X, P, G, rows, k);
+}
+
 template <typename T>
 hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
                      hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  KP_SWITCH(KP, (hals_rows_grp_kernel<T, KPc><<<(unsigned)cdiv(rows, HalsGroup<KPc>::ROWS), 256,
-                                                 0, st>>>(X, P, G, rows, k)),
+  const int tpr = rows >= 65536 ? 4 : (rows >= 16384 ? 8 : 16);
+  KP_SWITCH(KP, (launch_hals_grp<T, KPc>(X, P, G, rows, k, tpr, st)),
             (hals_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
                 X, P, G, rows, k, KP)));
   return NMF_LAUNCH_CHECK();
