@@ -3,8 +3,9 @@
 //     min_{x >= 0} 1/2 x^T G x - p^T x,    y = G x - p,
 // until x_F >= 0 and y off F >= 0 (F the passive set). All right-hand sides
 // share G (the Gram of the fixed factor), so one launch covers all of them:
-// one wavefront per right-hand side, lane i <-> index i (k <= 64), the
-// passive set a 64-bit mask and the infeasible set a ballot.
+// four right-hand sides per wavefront, one per 16-lane row, index j held by
+// lane j % 16 of its row in slot j / 16 (k <= 64), the passive set a 64-bit
+// mask and the infeasible set read from ballots.
 //
 // The exchange rule is Kim and Park's (the method the paper cites): swap all
 // of V while |V| keeps falling, at most three times without progress, then
@@ -13,6 +14,8 @@
 // entries whose exact value is zero flips their sign from one pivot to the
 // next and the pivoting can cycle. A non-positive pivot sets status |= 1;
 // reaching the pivot cap sets status |= 2.
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -23,62 +26,188 @@
 //     y = G x - p,  x_A = 0,  y_F = 0   =>   x = G^-1 (p + y),
 //     (G^-1)_AA y_A = -(G^-1 p)_A,       x_F = (G^-1 p)_F + (G^-1)_FA y_A.
 // With k <= 64 one of |F|, |A| is at most 32, so each solve eliminates at
-// most 32 pivots. The solved set S (F, or A) is moved to lanes 0..|S|-1 and
-// the other indices to the lanes after it (one cross-lane permute); every
-// lane c holds row c of [M_{.,S} | rhs] in double registers, and Gauss-Jordan
-// elimination over the pivots of S (pivot rows broadcast with readlane)
-// leaves the solution on S in lanes c < |S| and, in the other lanes, the
-// right-hand side with S eliminated: p - G_{.F} x_F = -y for the passive
-// system; for the active one, with right-hand side G^-1 p, the solution on
-// A is -y_A and the other lanes hold x_F. So one elimination gives both halves of
-// the KKT pair, with no LDS traffic and no waits inside the solve. Each
-// right-hand side starts from the support of the incoming X (warm start);
-// the solution is unique, so the start only changes how many exchanges are
-// needed.
+// most 32 pivots. The solved set S (F, or A) is listed in increasing index
+// order; lane i of a right-hand side's row holds rows i and i + 16 of
+// [M_SS | rhs_S] in double registers, and Gauss-Jordan elimination takes each
+// pivot row from its lane with a row broadcast (DPP row_newbcast, one move
+// per double, no LDS and no waits). The other half of the KKT pair follows
+// from the solution by one product with G (passive form: y off F) or G^-1
+// (active form: x_F). Each right-hand side starts from the support of the
+// incoming X (warm start); the solution is unique, so the start only changes
+// how many exchanges are needed. The four right-hand sides of a wavefront
+// eliminate together at the size of the largest of their systems.
 // ===========================================================================
 namespace nmfk {
 
-constexpr int BPP_WAVES = 4;   // right-hand sides in flight per workgroup
+constexpr int BPP_WAVES = 4;   // wavefronts per workgroup
+constexpr int BPP_RPW = 4;     // right-hand sides per wavefront (one per 16-lane row)
 constexpr int CNF = 32;        // largest eliminated set
 
-__device__ __forceinline__ double rdl(double v, int q) {
-  const unsigned long long b = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)(b & 0xffffffffu), q);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), q);
-  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+// v from lane L of this lane's 16-lane row
+template <int L> __device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + L, 0xf, 0xf, true);
 }
 
-// v from lane `src` (any lane, per-lane source).
-__device__ __forceinline__ double pull(double v, int src) {
-  const unsigned long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(b & 0xffffffffu));
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(b >> 32));
-  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+// Bits of this row's right-hand side from per-slot predicates: index
+// 16 s + i of row g is bit 16 g + i of the ballot of slot s.
+template <int JS>
+__device__ __forceinline__ uint64_t row_bits(const bool (&pr)[JS], int g) {
+  uint64_t m = 0;
+#pragma unroll
+  for (int s = 0; s < JS; ++s) m |= ((__ballot(pr[s]) >> (16 * g)) & 0xFFFFull) << (16 * s);
+  return m;
 }
 
-// Gauss-Jordan elimination of the first ns <= NS columns (lane c holds row c
-// of the matrix in a[] and its right-hand side b): returns the solution in
-// lanes c < ns and the eliminated right-hand side in the other lanes; a
-// non-positive pivot sets bad. Columns ns..NS-1 hold zeros, so the column
-// loops need no bounds tests.
-template <int NS>
-__device__ __forceinline__ double gj_eliminate(double (&a)[CNF], double b, int ns, int lane,
-                                               bool& bad) {
-  double dq = 1.0;
+// LDS written by some lanes of a wavefront and read by others of the same
+// wavefront: keep the accesses in program order.
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One Gauss-Jordan step on pivot Q of every row's system: the pivot row
+// comes from lane Q % 16, slot Q / 16. Systems smaller than NS are padded
+// with identity rows and columns, so their extra steps change nothing.
+// a[rs][c] is row i + 16 rs, column c.
+template <int NS, int Q>
+__device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], double (&dq)[2],
+                                        int nsm, int i, bool& bad) {
+  constexpr int RS = NS > 16 ? 2 : 1;
+  constexpr int QS = Q >> 4, QL = Q & 15;
+  if (Q >= nsm) return;
+  // the lane index is re-read per step, so the compiler keeps no lane
+  // masks for all steps at once
+  int li = i;
+  asm volatile("" : "+v"(li));
+  double pv = row_bcast<QL>(a[QS][Q]);
+  if (!(pv > 0.0)) { bad = true; pv = 1.0; }
+  const double rinv = 1.0 / pv;
+  double f[RS];
 #pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    if (q < ns) {
-      double pv = rdl(a[q], q);
-      if (!(pv > 0.0)) { bad = true; pv = 1.0; }
-      const double f = (lane == q) ? 0.0 : a[q] / pv;
-      if (lane == q) dq = pv;
-      b = fma(-f, rdl(b, q), b);
+  for (int rs = 0; rs < RS; ++rs) {
+    const bool piv = li + 16 * rs == Q;
+    f[rs] = piv ? 0.0 : a[rs][Q] * rinv;
+    if (piv) dq[rs] = pv;
+  }
+  const double pb = row_bcast<QL>(b[QS]);
 #pragma unroll
-      for (int j = q + 1; j < NS; ++j) a[j] = fma(-f, rdl(a[j], q), a[j]);
+  for (int rs = 0; rs < RS; ++rs) b[rs] = fma(-f[rs], pb, b[rs]);
+#pragma unroll
+  for (int c = Q + 1; c < NS; ++c) {
+    const double pr = row_bcast<QL>(a[QS][c]);
+#pragma unroll
+    for (int rs = 0; rs < RS; ++rs) a[rs][c] = fma(-f[rs], pr, a[rs][c]);
+  }
+}
+
+template <int NS, int... Q>
+__device__ __forceinline__ void gj_steps(std::integer_sequence<int, Q...>, double (&a)[2][CNF],
+                                         double (&b)[2], double (&dq)[2], int nsm, int i,
+                                         bool& bad) {
+  (gj_step<NS, Q>(a, b, dq, nsm, i, bad), ...);
+}
+
+// acc[s] += M[16 s + i][f] * x_T for the solution entry x_T of position T
+// (held by lane T % 16, slot T / 16) at index f.
+template <int T, bool ACTIVE, typename TS, int KP>
+__device__ __forceinline__ void product_step(const TS* __restrict__ Gs,
+                                             const double* __restrict__ Ginv, const int (&fi)[CNF],
+                                             const double (&xs)[2], int nsm, int i,
+                                             double (&acc)[KP / 16]) {
+  constexpr int LD = KP + 1;
+  if (T >= nsm) return;
+  const double v = row_bcast<T & 15>(xs[T >> 4]);
+  const int f = fi[T];
+#pragma unroll
+  for (int s = 0; s < KP / 16; ++s) {
+    const int jr = 16 * s + i;
+    const double mv = ACTIVE ? Ginv[jr * KP + f] : (double)Gs[jr * LD + f];
+    acc[s] = fma(mv, v, acc[s]);
+  }
+}
+
+template <bool ACTIVE, typename TS, int KP, int... T>
+__device__ __forceinline__ void product_steps(std::integer_sequence<int, T...>,
+                                              const TS* __restrict__ Gs,
+                                              const double* __restrict__ Ginv,
+                                              const int (&fi)[CNF], const double (&xs)[2], int nsm,
+                                              int i, double (&acc)[KP / 16]) {
+  (product_step<T, ACTIVE, TS, KP>(Gs, Ginv, fi, xs, nsm, i, acc), ...);
+}
+
+// Loads each row's system on its solved set (listed in il, right-hand side
+// in rl by index), eliminates, stores the solution by index in sl, and adds
+// the product of the same matrix's columns on the solved set with the
+// solution to acc (one entry per index of the row). The matrix comes from G
+// in LDS (passive form) or from G^-1 (ACTIVE); a row with ns = 0 takes no
+// part. Every load address is in range, so the loads are branch-free.
+template <int NS, bool ACTIVE, typename TS, int KP>
+__device__ __forceinline__ void solve_rows(const TS* __restrict__ Gs,
+                                           const double* __restrict__ Ginv, const int* il,
+                                           const double* rl, double* sl, int ns, int nsm, int i,
+                                           bool& bad, double (&acc)[KP / 16]) {
+  constexpr int RS = NS > 16 ? 2 : 1;
+  constexpr int LD = KP + 1;
+  double a[2][CNF], b[2], dq[2] = {1.0, 1.0};
+  int li = i;
+  asm volatile("" : "+v"(li));
+  int ri[RS];
+  bool rv[RS];
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs) {
+    const int t = li + 16 * rs;
+    rv[rs] = t < ns;
+    ri[rs] = rv[rs] ? min(il[t], KP - 1) : 0;
+    b[rs] = rv[rs] ? rl[ri[rs]] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < NS; ++c) {
+    const int cc = min(il[c], KP - 1);   // stale past ns, in range, masked below
+#pragma unroll
+    for (int rs = 0; rs < RS; ++rs) {
+      const double v = ACTIVE ? Ginv[ri[rs] * KP + cc] : (double)Gs[ri[rs] * LD + cc];
+      a[rs][c] = (rv[rs] && c < ns) ? v : (li + 16 * rs == c ? 1.0 : 0.0);   // identity padding
     }
   }
-  return lane < ns ? b / dq : b;
+  gj_steps<NS>(std::make_integer_sequence<int, NS>{}, a, b, dq, nsm, li, bad);
+  double xs[2] = {0.0, 0.0};
+#pragma unroll
+  for (int rs = 0; rs < RS; ++rs) {
+    const int t = li + 16 * rs;
+    if (t < ns) {
+      xs[rs] = b[rs] / dq[rs];
+      sl[ri[rs]] = xs[rs];
+    }
+  }
+  // positions past ns hold stale indices, all in range; their x_T is 0
+  int fi[CNF];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) fi[t] = min(il[t], KP - 1);
+  product_steps<ACTIVE, TS, KP>(std::make_integer_sequence<int, NS>{}, Gs, Ginv, fi, xs, nsm, li,
+                                acc);
 }
+
+// One elimination pass over the rows with ns > 0 at the size class of the
+// largest of them.
+template <bool ACTIVE, typename TS, int KP>
+__device__ __forceinline__ void solve_pass(const TS* __restrict__ Gs,
+                                           const double* __restrict__ Ginv, const int* il,
+                                           const double* rl, double* sl, int ns, int i,
+                                           bool& bad, double (&acc)[KP / 16]) {
+  const int nsm = max(max(__builtin_amdgcn_readlane(ns, 0), __builtin_amdgcn_readlane(ns, 16)),
+                      max(__builtin_amdgcn_readlane(ns, 32), __builtin_amdgcn_readlane(ns, 48)));
+  if (nsm == 0) return;
+  const int cls = (nsm + 7) >> 3;
+  if (cls == 1)
+    solve_rows<8, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  else if (cls == 2 || KP <= 16)
+    solve_rows<16, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  else if (cls == 3)
+    solve_rows<24, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  else
+    solve_rows<32, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+}
+
 
 // Ginv (KP x KP, double) = inverse of G restricted to the indices i < k with
 // G_ii > 0 (zero rows and columns elsewhere), by Gauss-Jordan elimination in
@@ -133,117 +262,178 @@ __global__ __launch_bounds__(256) void gram_inverse_kernel(const TS* __restrict_
 }
 
 template <typename TS, int KP>
-__global__ __launch_bounds__(64 * BPP_WAVES) void bpp_compact_kernel(
+__global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
     TS* __restrict__ X, const TS* __restrict__ P, const TS* __restrict__ G,
     const double* __restrict__ Ginv, const int* __restrict__ ginv_ok, int64_t rows, int k,
     int max_pivots, int warm, int* __restrict__ status, unsigned long long* __restrict__ pivots) {
-  static_assert(KP <= 64, "one lane per index");
+  static_assert(KP % 16 == 0 && KP <= 64, "16-lane rows over at most 64 indices");
+  constexpr int JS = KP / 16;   // index slots per lane
   constexpr int LD = KP + 1;
   __shared__ TS Gs[KP * LD];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double rhs_l[BPP_WAVES][BPP_RPW][KP];   // right-hand side of the solved system
+  __shared__ double sol_l[BPP_WAVES][BPP_RPW][KP];   // its solution, by index
+  __shared__ double p_l[BPP_WAVES][BPP_RPW][KP];     // the right-hand side p
+  __shared__ double cp_l[BPP_WAVES][BPP_RPW][KP];    // G^-1 p (active form)
+  __shared__ int idx_l[BPP_WAVES][BPP_RPW][CNF];     // the solved set, increasing
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
   for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) Gs[(e / KP) * LD + (e % KP)] = G[e];
+  for (int e = threadIdx.x; e < BPP_WAVES * BPP_RPW * CNF; e += blockDim.x)
+    (&idx_l[0][0][0])[e] = 0;
   __syncthreads();
+  double* rl = rhs_l[wv][g];
+  double* sl = sol_l[wv][g];
+  int* il = idx_l[wv][g];
+  double* pl = p_l[wv][g];
+  double* cpl = cp_l[wv][g];
   // live: index in range with a nonzero Gram diagonal (see gram_inverse_kernel)
-  const bool act = lane < k && Gs[lane * LD + lane] > TS(0);
-  const uint64_t all = __ballot(act);
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  bool act[JS];
+#pragma unroll
+  for (int s = 0; s < JS; ++s) {
+    const int j = 16 * s + i;
+    act[s] = j < k && Gs[j * LD + j] > TS(0);
+  }
+  const uint64_t all = row_bits<JS>(act, 0);   // the same for every row
   const bool have_ginv = k > CNF && *ginv_ok != 0;
   unsigned long long my_pivots = 0;
   int my_status = 0;
 
-  for (int64_t r = (int64_t)blockIdx.x * BPP_WAVES + wv; r < rows;
-       r += (int64_t)gridDim.x * BPP_WAVES) {
-    const double p = (lane < k) ? (double)P[r * KP + lane] : 0.0;
-    uint64_t F = 0;
-    if (warm) F = __ballot(act && X[r * KP + lane] > TS(0)) & all;
-    double x = 0.0, y = -p, cp = 0.0;
-    bool have_cp = false, bad = false;
-    int budget = 3, best = k + 1, npiv = 0;
-    bool first = F != 0;  // the warm-start set is solved before any test
+  const int64_t stride = (int64_t)gridDim.x * BPP_WAVES * BPP_RPW;
+  for (int64_t base = ((int64_t)blockIdx.x * BPP_WAVES + wv) * BPP_RPW; base < rows;
+       base += stride) {
+    const int64_t r = base + g;
+    const bool live = r < rows;
+    double x[JS], y[JS];
+    bool wpos[JS];
+#pragma unroll
+    for (int s = 0; s < JS; ++s) {
+      const int j = 16 * s + i;
+      const double pj = (live && j < k) ? (double)P[r * KP + j] : 0.0;
+      pl[j] = pj;
+      x[s] = 0.0;
+      y[s] = -pj;
+      wpos[s] = warm && live && act[s] && X[r * KP + j] > TS(0);
+    }
+    uint64_t F = row_bits<JS>(wpos, g) & all;
+    bool have_cp = false, bad = false, done = !live;
+    bool first = live && F != 0;   // the warm-start set is solved before any test
     const bool from_warm = first;
+    int budget = 3, best = k + 1, npiv = 0;
     for (;;) {
-      if (!first) {
-        const bool inF = (F >> lane) & 1ull;
-        const bool infeas = act && (inF ? (x < 0.0) : (y < 0.0));
-        const uint64_t V = __ballot(infeas);
-        if (V == 0) break;
-        if (npiv >= max_pivots) { my_status |= 2; break; }
-        const int nv = __popcll(V);
-        uint64_t E;
-        if (nv < best) { best = nv; budget = 3; E = V; }
-        else if (budget >= 1) { --budget; E = V; }
-        else { E = 1ull << (63 - __clzll(V)); }
-        F ^= E;
+      bool solve = false;
+      if (!done) {
+        if (!first) {
+          bool inf[JS];
+#pragma unroll
+          for (int s = 0; s < JS; ++s) {
+            const bool inF = (F >> (16 * s + i)) & 1ull;
+            inf[s] = act[s] && (inF ? (x[s] < 0.0) : (y[s] < 0.0));
+          }
+          const uint64_t V = row_bits<JS>(inf, g);
+          if (V == 0) {
+            done = true;
+          } else if (npiv >= max_pivots) {
+            my_status |= 2;
+            done = true;
+          } else {
+            const int nv = __popcll(V);
+            uint64_t E;
+            if (nv < best) { best = nv; budget = 3; E = V; }
+            else if (budget >= 1) { --budget; E = V; }
+            else { E = 1ull << (63 - __clzll(V)); }
+            F ^= E;
+            solve = true;
+          }
+        } else {
+          solve = true;
+        }
+        first = false;
       }
-      first = false;
-      ++npiv;
+      if (__ballot(solve) == 0) break;
       const int nf = __popcll(F);
-      const bool fi = (F >> lane) & 1ull;
-      if (nf == 0) { x = 0.0; y = -p; continue; }
+      if (solve) ++npiv;
+      if (solve && nf == 0) {
+#pragma unroll
+        for (int s = 0; s < JS; ++s) { x[s] = 0.0; y[s] = -pl[16 * s + i]; }
+        solve = false;
+      }
       const bool passive = nf <= CNF;
-      if (!passive && !have_ginv) { bad = true; break; }  // G^-1 unavailable (G singular)
-      if (!passive && !have_cp) {
+      if (solve && !passive && !have_ginv) {   // G^-1 unavailable (G singular)
+        bad = true;
+        done = true;
+        solve = false;
+      }
+      if (solve && !passive && !have_cp) {
         // cp = G^-1 p, once per right-hand side
-        double s = 0.0;
-        const int grow = act ? lane : 0;
-        for (int j = 0; j < k; ++j) s = fma(Ginv[grow * KP + j], rdl(p, j), s);
-        cp = act ? s : 0.0;
+#pragma unroll
+        for (int s = 0; s < JS; ++s) {
+          const int jr = act[s] ? 16 * s + i : 0;
+          double acc = 0.0;
+          for (int l = 0; l < k; ++l) acc = fma(Ginv[jr * KP + l], pl[l], acc);
+          cpl[16 * s + i] = act[s] ? acc : 0.0;
+        }
         have_cp = true;
       }
       const uint64_t S = passive ? F : (all & ~F);
-      const int ns = __popcll(S);
-      const bool si = (S >> lane) & 1ull;
-      // compact position: S in increasing index order, then the other lanes
-      const int pos = si ? __popcll(S & below) : ns + __popcll(~S & below);
-      const int ci0 = __builtin_amdgcn_ds_permute(pos << 2, lane);  // index held by lane
-      const int ci = ci0 < k ? ci0 : 0;
-      const double bv = pull(passive ? p : cp, ci0);
-      const double b = bv;
-      double a[CNF];
-      uint64_t bits = S;
+      const int ns = solve ? __popcll(S) : 0;   // 0 in the active form when F holds every index
+      if (__ballot(solve) == 0) continue;
+      if (solve) {
 #pragma unroll
-      for (int d = 0; d < CNF; ++d) {
-        double v = 0.0;
-        if (d < ns) {
-          const int j = __builtin_ctzll(bits);
-          bits &= bits - 1;
-          v = passive ? (double)Gs[ci * LD + j] : Ginv[ci * KP + j];
+        for (int s = 0; s < JS; ++s) {
+          const int j = 16 * s + i;
+          if ((S >> j) & 1ull) il[__popcll(S & ((1ull << j) - 1ull))] = j;
+          rl[j] = passive ? pl[j] : cpl[j];
         }
-        a[d] = v;
       }
-      double sol;
-      switch ((ns + 7) >> 3) {
-        case 1: sol = gj_eliminate<8>(a, b, ns, lane, bad); break;
-        case 2: sol = gj_eliminate<16>(a, b, ns, lane, bad); break;
-        case 3: sol = gj_eliminate<24>(a, b, ns, lane, bad); break;
-        default: sol = gj_eliminate<32>(a, b, ns, lane, bad); break;
-      }
-      if (bad && npiv == 1 && from_warm) {
-        // The warm-start set was not positive definite: start over from F = {}.
-        bad = false;
-        F = 0;
-        x = 0.0;
-        y = -p;
+      wave_lds_order();
+      bool sbad = false;
+      // the other half of the KKT pair comes with the solve: one product with
+      // G (passive form) or G^-1 over the solved set
+      double acc[JS];
+#pragma unroll
+      for (int s = 0; s < JS; ++s) acc[s] = 0.0;
+      solve_pass<false, TS, KP>(Gs, Ginv, il, rl, sl, passive ? ns : 0, i, sbad, acc);
+      if (KP > CNF)
+        solve_pass<true, TS, KP>(Gs, Ginv, il, rl, sl, passive ? 0 : ns, i, sbad, acc);
+      wave_lds_order();
+      if (!solve) continue;
+      if (sbad) {
+        if (npiv == 1 && from_warm) {
+          // The warm-start set was not positive definite: start over from F = {}.
+          F = 0;
+#pragma unroll
+          for (int s = 0; s < JS; ++s) { x[s] = 0.0; y[s] = -pl[16 * s + i]; }
+        } else {
+          bad = true;
+          done = true;
+        }
         continue;
       }
-      if (bad) break;
-      const double val = pull(sol, pos);
-      if (passive) {
-        x = fi ? val : 0.0;
-        y = (fi || !act) ? 0.0 : -val;
-      } else {
-        // (G^-1)_AA z = (G^-1 p)_A gives z = -y_A; the other lanes hold
-        // (G^-1 p)_F - (G^-1)_FA z = x_F
-        y = si ? -val : 0.0;
-        x = fi ? val : 0.0;
+#pragma unroll
+      for (int s = 0; s < JS; ++s) {
+        const int j = 16 * s + i;
+        const bool inF = (F >> j) & 1ull, inS = (S >> j) & 1ull;
+        if (passive) {
+          x[s] = inF ? sl[j] : 0.0;
+          y[s] = (inF || !act[s]) ? 0.0 : acc[s] - pl[j];
+        } else {
+          // (G^-1)_AA z = (G^-1 p)_A gives z = -y_A; x_F = (G^-1 p)_F - (G^-1)_FA z
+          y[s] = inS ? -sl[j] : 0.0;
+          x[s] = inF ? cpl[j] - acc[s] : 0.0;
+        }
       }
     }
     if (bad) my_status |= 1;
     my_pivots += (unsigned long long)npiv;
-    if (lane < KP) X[r * KP + lane] = (lane < k) ? (TS)(x > 0.0 ? x : 0.0) : TS(0);
+    if (live) {
+#pragma unroll
+      for (int s = 0; s < JS; ++s) {
+        const int j = 16 * s + i;
+        X[r * KP + j] = (j < k) ? (TS)(x[s] > 0.0 ? x[s] : 0.0) : TS(0);
+      }
+    }
   }
-  if (lane == 0) {
-    atomicAdd(pivots, my_pivots);
+  if (i == 0) {
+    if (my_pivots) atomicAdd(pivots, my_pivots);
     if (my_status) atomicOr(status, my_status);
   }
 }
@@ -254,11 +444,11 @@ hipError_t bpp_rows_compact(T* X, const T* P, const T* G, int64_t rows, int k, i
                             unsigned long long* pivots, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   const int64_t maxb = 256 * 16;
-  const unsigned blocks = (unsigned)std::min<int64_t>(maxb, cdiv(rows, BPP_WAVES));
+  const unsigned blocks = (unsigned)std::min<int64_t>(maxb, cdiv(rows, BPP_WAVES * BPP_RPW));
 #define CASE(K)                                                                          \
   case K:                                                                                \
     if (k > CNF) gram_inverse_kernel<T, K><<<1, 256, 0, st>>>(G, k, Ginv, ginv_ok);      \
-    bpp_compact_kernel<T, K><<<blocks, 64 * BPP_WAVES, 0, st>>>(                         \
+    bpp_quad_kernel<T, K><<<blocks, 64 * BPP_WAVES, 0, st>>>(                         \
         X, P, G, Ginv, ginv_ok, rows, k, max_pivots, warm, status, pivots);              \
     break;
   switch (KP) {
