@@ -65,13 +65,23 @@ __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// 1 / v for v > 0: the hardware estimate refined by two Newton steps
+// (r <- r + r (1 - v r)), within an ulp or two of the quotient.
+__device__ __forceinline__ double recip(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  r = fma(r, fma(-v, r, 1.0), r);
+  r = fma(r, fma(-v, r, 1.0), r);
+  return r;
+}
+
 // One Gauss-Jordan step on pivot Q of every row's system: the pivot row
 // comes from lane Q % 16, slot Q / 16. Systems smaller than NS are padded
-// with identity rows and columns, so their extra steps change nothing.
-// a[rs][c] is row i + 16 rs, column c.
+// with zero rows and columns; a zero pivot is replaced by 1, so their extra
+// steps change nothing. dq records each row's own pivot as found (its sign
+// is tested after the elimination). a[rs][c] is row i + 16 rs, column c.
 template <int NS, int Q>
 __device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], double (&dq)[2],
-                                        int nsm, int i, bool& bad) {
+                                        int nsm, int i) {
   constexpr int RS = NS > 16 ? 2 : 1;
   constexpr int QS = Q >> 4, QL = Q & 15;
   if (Q >= nsm) return;
@@ -79,15 +89,14 @@ __device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], dou
   // masks for all steps at once
   int li = i;
   asm volatile("" : "+v"(li));
-  double pv = row_bcast<QL>(a[QS][Q]);
-  if (!(pv > 0.0)) { bad = true; pv = 1.0; }
-  const double rinv = 1.0 / pv;
+  const double pr0 = row_bcast<QL>(a[QS][Q]);
+  const double rinv = recip(pr0 > 0.0 ? pr0 : 1.0);
   double f[RS];
 #pragma unroll
   for (int rs = 0; rs < RS; ++rs) {
     const bool piv = li + 16 * rs == Q;
     f[rs] = piv ? 0.0 : a[rs][Q] * rinv;
-    if (piv) dq[rs] = pv;
+    if (piv) dq[rs] = pr0;
   }
   const double pb = row_bcast<QL>(b[QS]);
 #pragma unroll
@@ -102,37 +111,33 @@ __device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], dou
 
 template <int NS, int... Q>
 __device__ __forceinline__ void gj_steps(std::integer_sequence<int, Q...>, double (&a)[2][CNF],
-                                         double (&b)[2], double (&dq)[2], int nsm, int i,
-                                         bool& bad) {
-  (gj_step<NS, Q>(a, b, dq, nsm, i, bad), ...);
+                                         double (&b)[2], double (&dq)[2], int nsm, int i) {
+  (gj_step<NS, Q>(a, b, dq, nsm, i), ...);
 }
 
 // acc[s] += M[16 s + i][f] * x_T for the solution entry x_T of position T
-// (held by lane T % 16, slot T / 16) at index f.
-template <int T, bool ACTIVE, typename TS, int KP>
-__device__ __forceinline__ void product_step(const TS* __restrict__ Gs,
+// (held by lane T % 16, slot T / 16) at index f. M is G (LDS, leading
+// dimension KP + 1) or G^-1 (ACTIVE, leading dimension KP).
+template <int T, bool ACTIVE, int KP>
+__device__ __forceinline__ void product_step(const double* __restrict__ Gs,
                                              const double* __restrict__ Ginv, const int (&fi)[CNF],
                                              const double (&xs)[2], int nsm, int i,
                                              double (&acc)[KP / 16]) {
-  constexpr int LD = KP + 1;
+  constexpr int LD = ACTIVE ? KP : KP + 1;
   if (T >= nsm) return;
   const double v = row_bcast<T & 15>(xs[T >> 4]);
-  const int f = fi[T];
+  const double* m = (ACTIVE ? Ginv : Gs) + i * LD + fi[T];
 #pragma unroll
-  for (int s = 0; s < KP / 16; ++s) {
-    const int jr = 16 * s + i;
-    const double mv = ACTIVE ? Ginv[jr * KP + f] : (double)Gs[jr * LD + f];
-    acc[s] = fma(mv, v, acc[s]);
-  }
+  for (int s = 0; s < KP / 16; ++s) acc[s] = fma(m[16 * s * LD], v, acc[s]);
 }
 
-template <bool ACTIVE, typename TS, int KP, int... T>
+template <bool ACTIVE, int KP, int... T>
 __device__ __forceinline__ void product_steps(std::integer_sequence<int, T...>,
-                                              const TS* __restrict__ Gs,
+                                              const double* __restrict__ Gs,
                                               const double* __restrict__ Ginv,
                                               const int (&fi)[CNF], const double (&xs)[2], int nsm,
                                               int i, double (&acc)[KP / 16]) {
-  (product_step<T, ACTIVE, TS, KP>(Gs, Ginv, fi, xs, nsm, i, acc), ...);
+  (product_step<T, ACTIVE, KP>(Gs, Ginv, fi, xs, nsm, i, acc), ...);
 }
 
 // Loads each row's system on its solved set (listed in il, right-hand side
@@ -140,9 +145,12 @@ __device__ __forceinline__ void product_steps(std::integer_sequence<int, T...>,
 // the product of the same matrix's columns on the solved set with the
 // solution to acc (one entry per index of the row). The matrix comes from G
 // in LDS (passive form) or from G^-1 (ACTIVE); a row with ns = 0 takes no
-// part. Every load address is in range, so the loads are branch-free.
-template <int NS, bool ACTIVE, typename TS, int KP>
-__device__ __forceinline__ void solve_rows(const TS* __restrict__ Gs,
+// part. Positions of il past a row's ns hold the index KP, whose row and
+// column of the LDS copy of G are zero, so the passive loads need no
+// masking; every load address is in range, so the loads are branch-free. A
+// non-positive pivot of a row's own system sets bad.
+template <int NS, bool ACTIVE, int KP>
+__device__ __forceinline__ void solve_rows(const double* __restrict__ Gs,
                                            const double* __restrict__ Ginv, const int* il,
                                            const double* rl, double* sl, int ns, int nsm, int i,
                                            bool& bad, double (&acc)[KP / 16]) {
@@ -152,60 +160,77 @@ __device__ __forceinline__ void solve_rows(const TS* __restrict__ Gs,
   int li = i;
   asm volatile("" : "+v"(li));
   int ri[RS];
-  bool rv[RS];
 #pragma unroll
   for (int rs = 0; rs < RS; ++rs) {
-    const int t = li + 16 * rs;
-    rv[rs] = t < ns;
-    ri[rs] = rv[rs] ? min(il[t], KP - 1) : 0;
-    b[rs] = rv[rs] ? rl[ri[rs]] : 0.0;
+    ri[rs] = il[li + 16 * rs];
+    b[rs] = rl[ri[rs]];   // rl[KP] is zero
   }
-#pragma unroll
-  for (int c = 0; c < NS; ++c) {
-    const int cc = min(il[c], KP - 1);   // stale past ns, in range, masked below
+  if (ACTIVE) {
+    bool rv[RS];
 #pragma unroll
     for (int rs = 0; rs < RS; ++rs) {
-      const double v = ACTIVE ? Ginv[ri[rs] * KP + cc] : (double)Gs[ri[rs] * LD + cc];
-      a[rs][c] = (rv[rs] && c < ns) ? v : (li + 16 * rs == c ? 1.0 : 0.0);   // identity padding
+      rv[rs] = ri[rs] < KP;
+      ri[rs] = min(ri[rs], KP - 1);
+    }
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      const int cc = il[c];
+#pragma unroll
+      for (int rs = 0; rs < RS; ++rs) {
+        const double v = Ginv[ri[rs] * KP + min(cc, KP - 1)];
+        a[rs][c] = (rv[rs] && cc < KP) ? v : 0.0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      const int cc = il[c];
+#pragma unroll
+      for (int rs = 0; rs < RS; ++rs) a[rs][c] = Gs[ri[rs] * LD + cc];
     }
   }
-  gj_steps<NS>(std::make_integer_sequence<int, NS>{}, a, b, dq, nsm, li, bad);
+  gj_steps<NS>(std::make_integer_sequence<int, NS>{}, a, b, dq, nsm, li);
   double xs[2] = {0.0, 0.0};
+  bool lbad = false;
 #pragma unroll
   for (int rs = 0; rs < RS; ++rs) {
-    const int t = li + 16 * rs;
-    if (t < ns) {
+    if (li + 16 * rs < ns) {
+      if (!(dq[rs] > 0.0)) lbad = true;
       xs[rs] = b[rs] / dq[rs];
       sl[ri[rs]] = xs[rs];
     }
   }
-  // positions past ns hold stale indices, all in range; their x_T is 0
+  // a bad pivot in any lane of the row marks the whole row
+  if ((__ballot(lbad) >> (16 * (__lane_id() >> 4))) & 0xFFFFull) bad = true;
+  // positions past ns hold the index KP; their x_T is 0
   int fi[CNF];
 #pragma unroll
-  for (int t = 0; t < NS; ++t) fi[t] = min(il[t], KP - 1);
-  product_steps<ACTIVE, TS, KP>(std::make_integer_sequence<int, NS>{}, Gs, Ginv, fi, xs, nsm, li,
-                                acc);
+  for (int t = 0; t < NS; ++t) fi[t] = ACTIVE ? min(il[t], KP - 1) : il[t];
+  product_steps<ACTIVE, KP>(std::make_integer_sequence<int, NS>{}, Gs, Ginv, fi, xs, nsm, li, acc);
 }
 
 // One elimination pass over the rows with ns > 0 at the size class of the
 // largest of them.
-template <bool ACTIVE, typename TS, int KP>
-__device__ __forceinline__ void solve_pass(const TS* __restrict__ Gs,
+template <bool ACTIVE, int KP>
+__device__ __forceinline__ void solve_pass(const double* __restrict__ Gs,
                                            const double* __restrict__ Ginv, const int* il,
                                            const double* rl, double* sl, int ns, int i,
                                            bool& bad, double (&acc)[KP / 16]) {
   const int nsm = max(max(__builtin_amdgcn_readlane(ns, 0), __builtin_amdgcn_readlane(ns, 16)),
                       max(__builtin_amdgcn_readlane(ns, 32), __builtin_amdgcn_readlane(ns, 48)));
   if (nsm == 0) return;
-  const int cls = (nsm + 7) >> 3;
-  if (cls == 1)
-    solve_rows<8, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
-  else if (cls == 2 || KP <= 16)
-    solve_rows<16, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
-  else if (cls == 3)
-    solve_rows<24, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  if (nsm <= 8)
+    solve_rows<8, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  else if (nsm <= 16 || KP <= 16)
+    solve_rows<16, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  else if (nsm <= 20)
+    solve_rows<20, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  else if (nsm <= 24)
+    solve_rows<24, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+  else if (nsm <= 28)
+    solve_rows<28, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
   else
-    solve_rows<32, ACTIVE, TS, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+    solve_rows<32, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
 }
 
 
@@ -269,16 +294,22 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
   static_assert(KP % 16 == 0 && KP <= 64, "16-lane rows over at most 64 indices");
   constexpr int JS = KP / 16;   // index slots per lane
   constexpr int LD = KP + 1;
-  __shared__ TS Gs[KP * LD];
-  __shared__ double rhs_l[BPP_WAVES][BPP_RPW][KP];   // right-hand side of the solved system
+  // G in double with a zero row and column at index KP (the padding index)
+  __shared__ double Gs[(KP + 1) * LD];
+  __shared__ double rhs_l[BPP_WAVES][BPP_RPW][KP + 1];   // right-hand side of the solved system
   __shared__ double sol_l[BPP_WAVES][BPP_RPW][KP];   // its solution, by index
   __shared__ double p_l[BPP_WAVES][BPP_RPW][KP];     // the right-hand side p
   __shared__ double cp_l[BPP_WAVES][BPP_RPW][KP];    // G^-1 p (active form)
   __shared__ int idx_l[BPP_WAVES][BPP_RPW][CNF];     // the solved set, increasing
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
-  for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) Gs[(e / KP) * LD + (e % KP)] = G[e];
+  for (int e = threadIdx.x; e < (KP + 1) * LD; e += blockDim.x) {
+    const int r = e / LD, c = e % LD;
+    Gs[e] = (r < KP && c < KP) ? (double)G[r * KP + c] : 0.0;
+  }
   for (int e = threadIdx.x; e < BPP_WAVES * BPP_RPW * CNF; e += blockDim.x)
-    (&idx_l[0][0][0])[e] = 0;
+    (&idx_l[0][0][0])[e] = KP;
+  for (int e = threadIdx.x; e < BPP_WAVES * BPP_RPW; e += blockDim.x)
+    (&rhs_l[0][0][0])[e * (KP + 1) + KP] = 0.0;
   __syncthreads();
   double* rl = rhs_l[wv][g];
   double* sl = sol_l[wv][g];
@@ -290,145 +321,161 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
 #pragma unroll
   for (int s = 0; s < JS; ++s) {
     const int j = 16 * s + i;
-    act[s] = j < k && Gs[j * LD + j] > TS(0);
+    act[s] = j < k && Gs[j * LD + j] > 0.0;
   }
   const uint64_t all = row_bits<JS>(act, 0);   // the same for every row
   const bool have_ginv = k > CNF && *ginv_ok != 0;
   unsigned long long my_pivots = 0;
   int my_status = 0;
 
+  // Each 16-lane row works through its own sequence of right-hand sides
+  // (r, r + stride, ...): a row that finishes one starts the next in the
+  // same round, so the four rows of a wavefront stay busy until their
+  // sequences run out.
   const int64_t stride = (int64_t)gridDim.x * BPP_WAVES * BPP_RPW;
-  for (int64_t base = ((int64_t)blockIdx.x * BPP_WAVES + wv) * BPP_RPW; base < rows;
-       base += stride) {
-    const int64_t r = base + g;
-    const bool live = r < rows;
-    double x[JS], y[JS];
-    bool wpos[JS];
-#pragma unroll
-    for (int s = 0; s < JS; ++s) {
-      const int j = 16 * s + i;
-      const double pj = (live && j < k) ? (double)P[r * KP + j] : 0.0;
-      pl[j] = pj;
-      x[s] = 0.0;
-      y[s] = -pj;
-      wpos[s] = warm && live && act[s] && X[r * KP + j] > TS(0);
-    }
-    uint64_t F = row_bits<JS>(wpos, g) & all;
-    bool have_cp = false, bad = false, done = !live;
-    bool first = live && F != 0;   // the warm-start set is solved before any test
-    const bool from_warm = first;
-    int budget = 3, best = k + 1, npiv = 0;
-    for (;;) {
-      bool solve = false;
-      if (!done) {
-        if (!first) {
-          bool inf[JS];
+  int64_t r = ((int64_t)blockIdx.x * BPP_WAVES + wv) * BPP_RPW + g - stride;
+  double x[JS], y[JS];
+  uint64_t F = 0;
+  bool live = true, done = true, have_cp = false, bad = false, first = false, from_warm = false;
+  int budget = 3, best = k + 1, npiv = 0;
+  for (;;) {
+    bool solve = false;
+    while (live && !solve) {
+      if (done) {
+        // store the finished right-hand side and start the next one
+        if (r >= 0) {
+          if (bad) my_status |= 1;
+          my_pivots += (unsigned long long)npiv;
 #pragma unroll
           for (int s = 0; s < JS; ++s) {
-            const bool inF = (F >> (16 * s + i)) & 1ull;
-            inf[s] = act[s] && (inF ? (x[s] < 0.0) : (y[s] < 0.0));
+            const int j = 16 * s + i;
+            X[r * KP + j] = (j < k) ? (TS)(x[s] > 0.0 ? x[s] : 0.0) : TS(0);
           }
-          const uint64_t V = row_bits<JS>(inf, g);
-          if (V == 0) {
-            done = true;
-          } else if (npiv >= max_pivots) {
-            my_status |= 2;
-            done = true;
-          } else {
-            const int nv = __popcll(V);
-            uint64_t E;
-            if (nv < best) { best = nv; budget = 3; E = V; }
-            else if (budget >= 1) { --budget; E = V; }
-            else { E = 1ull << (63 - __clzll(V)); }
-            F ^= E;
-            solve = true;
-          }
-        } else {
-          solve = true;
         }
-        first = false;
-      }
-      if (__ballot(solve) == 0) break;
-      const int nf = __popcll(F);
-      if (solve) ++npiv;
-      if (solve && nf == 0) {
-#pragma unroll
-        for (int s = 0; s < JS; ++s) { x[s] = 0.0; y[s] = -pl[16 * s + i]; }
-        solve = false;
-      }
-      const bool passive = nf <= CNF;
-      if (solve && !passive && !have_ginv) {   // G^-1 unavailable (G singular)
-        bad = true;
-        done = true;
-        solve = false;
-      }
-      if (solve && !passive && !have_cp) {
-        // cp = G^-1 p, once per right-hand side
-#pragma unroll
-        for (int s = 0; s < JS; ++s) {
-          const int jr = act[s] ? 16 * s + i : 0;
-          double acc = 0.0;
-          for (int l = 0; l < k; ++l) acc = fma(Ginv[jr * KP + l], pl[l], acc);
-          cpl[16 * s + i] = act[s] ? acc : 0.0;
-        }
-        have_cp = true;
-      }
-      const uint64_t S = passive ? F : (all & ~F);
-      const int ns = solve ? __popcll(S) : 0;   // 0 in the active form when F holds every index
-      if (__ballot(solve) == 0) continue;
-      if (solve) {
+        r += stride;
+        live = r < rows;
+        if (!live) break;
+        bool wpos[JS];
 #pragma unroll
         for (int s = 0; s < JS; ++s) {
           const int j = 16 * s + i;
-          if ((S >> j) & 1ull) il[__popcll(S & ((1ull << j) - 1ull))] = j;
-          rl[j] = passive ? pl[j] : cpl[j];
+          const double pj = j < k ? (double)P[r * KP + j] : 0.0;
+          pl[j] = pj;
+          x[s] = 0.0;
+          y[s] = -pj;
+          wpos[s] = warm && act[s] && X[r * KP + j] > TS(0);
         }
+        F = row_bits<JS>(wpos, g) & all;
+        done = false;
+        have_cp = false;
+        bad = false;
+        first = F != 0;   // the warm-start set is solved before any test
+        from_warm = first;
+        budget = 3;
+        best = k + 1;
+        npiv = 0;
       }
-      wave_lds_order();
-      bool sbad = false;
-      // the other half of the KKT pair comes with the solve: one product with
-      // G (passive form) or G^-1 over the solved set
-      double acc[JS];
+      if (!first) {
+        bool inf[JS];
 #pragma unroll
-      for (int s = 0; s < JS; ++s) acc[s] = 0.0;
-      solve_pass<false, TS, KP>(Gs, Ginv, il, rl, sl, passive ? ns : 0, i, sbad, acc);
-      if (KP > CNF)
-        solve_pass<true, TS, KP>(Gs, Ginv, il, rl, sl, passive ? 0 : ns, i, sbad, acc);
-      wave_lds_order();
-      if (!solve) continue;
-      if (sbad) {
-        if (npiv == 1 && from_warm) {
-          // The warm-start set was not positive definite: start over from F = {}.
-          F = 0;
-#pragma unroll
-          for (int s = 0; s < JS; ++s) { x[s] = 0.0; y[s] = -pl[16 * s + i]; }
-        } else {
-          bad = true;
-          done = true;
+        for (int s = 0; s < JS; ++s) {
+          const bool inF = (F >> (16 * s + i)) & 1ull;
+          inf[s] = act[s] && (inF ? (x[s] < 0.0) : (y[s] < 0.0));
         }
+        const uint64_t V = row_bits<JS>(inf, g);
+        if (V == 0) {
+          done = true;
+          continue;
+        }
+        if (npiv >= max_pivots) {
+          my_status |= 2;
+          done = true;
+          continue;
+        }
+        const int nv = __popcll(V);
+        uint64_t E;
+        if (nv < best) { best = nv; budget = 3; E = V; }
+        else if (budget >= 1) { --budget; E = V; }
+        else { E = 1ull << (63 - __clzll(V)); }
+        F ^= E;
+      }
+      first = false;
+      ++npiv;
+      if (F == 0) {
+        // x = 0 solves the empty passive set
+#pragma unroll
+        for (int s = 0; s < JS; ++s) { x[s] = 0.0; y[s] = -pl[16 * s + i]; }
         continue;
       }
-#pragma unroll
-      for (int s = 0; s < JS; ++s) {
-        const int j = 16 * s + i;
-        const bool inF = (F >> j) & 1ull, inS = (S >> j) & 1ull;
-        if (passive) {
-          x[s] = inF ? sl[j] : 0.0;
-          y[s] = (inF || !act[s]) ? 0.0 : acc[s] - pl[j];
-        } else {
-          // (G^-1)_AA z = (G^-1 p)_A gives z = -y_A; x_F = (G^-1 p)_F - (G^-1)_FA z
-          y[s] = inS ? -sl[j] : 0.0;
-          x[s] = inF ? cpl[j] - acc[s] : 0.0;
-        }
+      if (__popcll(F) > CNF && !have_ginv) {   // G^-1 unavailable (G singular)
+        bad = true;
+        done = true;
+        continue;
       }
+      solve = true;
     }
-    if (bad) my_status |= 1;
-    my_pivots += (unsigned long long)npiv;
-    if (live) {
+    if (__ballot(live) == 0) break;
+    const int nf = __popcll(F);
+    const bool passive = nf <= CNF;
+    if (solve && !passive && !have_cp) {
+      // cp = G^-1 p, once per right-hand side
+#pragma unroll
+      for (int s = 0; s < JS; ++s) {
+        const int jr = act[s] ? 16 * s + i : 0;
+        double acc = 0.0;
+        for (int l = 0; l < k; ++l) acc = fma(Ginv[jr * KP + l], pl[l], acc);
+        cpl[16 * s + i] = act[s] ? acc : 0.0;
+      }
+      have_cp = true;
+    }
+    const uint64_t S = passive ? F : (all & ~F);
+    const int ns = solve ? __popcll(S) : 0;   // 0 in the active form when F holds every index
+    if (__ballot(solve) == 0) continue;
+    if (solve) {
+      // the solved set in increasing order, then the padding index KP
 #pragma unroll
       for (int s = 0; s < JS; ++s) {
         const int j = 16 * s + i;
-        X[r * KP + j] = (j < k) ? (TS)(x[s] > 0.0 ? x[s] : 0.0) : TS(0);
+        if ((S >> j) & 1ull) il[__popcll(S & ((1ull << j) - 1ull))] = j;
+        rl[j] = passive ? pl[j] : cpl[j];
+      }
+      if (i >= ns) il[i] = KP;
+      if (i + 16 >= ns) il[i + 16] = KP;
+    }
+    wave_lds_order();
+    bool sbad = false;
+    // the other half of the KKT pair comes with the solve: one product with
+    // G (passive form) or G^-1 over the solved set
+    double acc[JS];
+#pragma unroll
+    for (int s = 0; s < JS; ++s) acc[s] = 0.0;
+    solve_pass<false, KP>(Gs, Ginv, il, rl, sl, passive ? ns : 0, i, sbad, acc);
+    if (KP > CNF) solve_pass<true, KP>(Gs, Ginv, il, rl, sl, passive ? 0 : ns, i, sbad, acc);
+    wave_lds_order();
+    if (!solve) continue;
+    if (sbad) {
+      if (npiv == 1 && from_warm) {
+        // The warm-start set was not positive definite: start over from F = {}.
+        F = 0;
+#pragma unroll
+        for (int s = 0; s < JS; ++s) { x[s] = 0.0; y[s] = -pl[16 * s + i]; }
+      } else {
+        bad = true;
+        done = true;
+      }
+      continue;
+    }
+#pragma unroll
+    for (int s = 0; s < JS; ++s) {
+      const int j = 16 * s + i;
+      const bool inF = (F >> j) & 1ull, inS = (S >> j) & 1ull;
+      if (passive) {
+        x[s] = inF ? sl[j] : 0.0;
+        y[s] = (inF || !act[s]) ? 0.0 : acc[s] - pl[j];
+      } else {
+        // (G^-1)_AA z = (G^-1 p)_A gives z = -y_A; x_F = (G^-1 p)_F - (G^-1)_FA z
+        y[s] = inS ? -sl[j] : 0.0;
+        x[s] = inF ? cpl[j] - acc[s] : 0.0;
       }
     }
   }
