@@ -75,13 +75,16 @@ __device__ __forceinline__ double recip(double v) {
 }
 
 // One Gauss-Jordan step on pivot Q of every row's system: the pivot row
-// comes from lane Q % 16, slot Q / 16. Systems smaller than NS are padded
-// with zero rows and columns; a zero pivot is replaced by 1, so their extra
-// steps change nothing. dq records each row's own pivot as found (its sign
-// is tested after the elimination). a[rs][c] is row i + 16 rs, column c.
+// comes from lane Q % 16, slot Q / 16, and its pivot is recorded in pvl[Q]
+// (the row's own pivots; their signs are tested after the elimination). The
+// pivot row's entry in column Q is cleared, so it takes no multiple of
+// itself (column Q is not read again). Systems smaller than NS are padded
+// with zero rows and columns: the zero pivots of their extra steps are
+// raised to 1e-300, which leaves every multiplier of a zero column zero.
+// a[rs][c] is row i + 16 rs, column c.
 template <int NS, int Q>
-__device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], double (&dq)[2],
-                                        int nsm, int i) {
+__device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], double* pvl, int nsm,
+                                        int i) {
   constexpr int RS = NS > 16 ? 2 : 1;
   constexpr int QS = Q >> 4, QL = Q & 15;
   if (Q >= nsm) return;
@@ -90,14 +93,12 @@ __device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], dou
   int li = i;
   asm volatile("" : "+v"(li));
   const double pr0 = row_bcast<QL>(a[QS][Q]);
-  const double rinv = recip(pr0 > 0.0 ? pr0 : 1.0);
+  pvl[Q] = pr0;
+  if (li == QL) a[QS][Q] = 0.0;
+  const double rinv = recip(fmax(pr0, 1e-300));
   double f[RS];
 #pragma unroll
-  for (int rs = 0; rs < RS; ++rs) {
-    const bool piv = li + 16 * rs == Q;
-    f[rs] = piv ? 0.0 : a[rs][Q] * rinv;
-    if (piv) dq[rs] = pr0;
-  }
+  for (int rs = 0; rs < RS; ++rs) f[rs] = a[rs][Q] * rinv;
   const double pb = row_bcast<QL>(b[QS]);
 #pragma unroll
   for (int rs = 0; rs < RS; ++rs) b[rs] = fma(-f[rs], pb, b[rs]);
@@ -111,8 +112,8 @@ __device__ __forceinline__ void gj_step(double (&a)[2][CNF], double (&b)[2], dou
 
 template <int NS, int... Q>
 __device__ __forceinline__ void gj_steps(std::integer_sequence<int, Q...>, double (&a)[2][CNF],
-                                         double (&b)[2], double (&dq)[2], int nsm, int i) {
-  (gj_step<NS, Q>(a, b, dq, nsm, i), ...);
+                                         double (&b)[2], double* pvl, int nsm, int i) {
+  (gj_step<NS, Q>(a, b, pvl, nsm, i), ...);
 }
 
 // acc[s] += M[16 s + i][f] * x_T for the solution entry x_T of position T
@@ -152,11 +153,11 @@ __device__ __forceinline__ void product_steps(std::integer_sequence<int, T...>,
 template <int NS, bool ACTIVE, int KP>
 __device__ __forceinline__ void solve_rows(const double* __restrict__ Gs,
                                            const double* __restrict__ Ginv, const int* il,
-                                           const double* rl, double* sl, int ns, int nsm, int i,
-                                           bool& bad, double (&acc)[KP / 16]) {
+                                           const double* rl, double* sl, double* pvl, int ns,
+                                           int nsm, int i, bool& bad, double (&acc)[KP / 16]) {
   constexpr int RS = NS > 16 ? 2 : 1;
   constexpr int LD = KP + 1;
-  double a[2][CNF], b[2], dq[2] = {1.0, 1.0};
+  double a[2][CNF], b[2];
   int li = i;
   asm volatile("" : "+v"(li));
   int ri[RS];
@@ -189,14 +190,15 @@ __device__ __forceinline__ void solve_rows(const double* __restrict__ Gs,
       for (int rs = 0; rs < RS; ++rs) a[rs][c] = Gs[ri[rs] * LD + cc];
     }
   }
-  gj_steps<NS>(std::make_integer_sequence<int, NS>{}, a, b, dq, nsm, li);
+  gj_steps<NS>(std::make_integer_sequence<int, NS>{}, a, b, pvl, nsm, li);
   double xs[2] = {0.0, 0.0};
   bool lbad = false;
 #pragma unroll
   for (int rs = 0; rs < RS; ++rs) {
     if (li + 16 * rs < ns) {
-      if (!(dq[rs] > 0.0)) lbad = true;
-      xs[rs] = b[rs] / dq[rs];
+      const double dq = pvl[li + 16 * rs];
+      if (!(dq > 0.0)) lbad = true;
+      xs[rs] = b[rs] / dq;
       sl[ri[rs]] = xs[rs];
     }
   }
@@ -214,23 +216,23 @@ __device__ __forceinline__ void solve_rows(const double* __restrict__ Gs,
 template <bool ACTIVE, int KP>
 __device__ __forceinline__ void solve_pass(const double* __restrict__ Gs,
                                            const double* __restrict__ Ginv, const int* il,
-                                           const double* rl, double* sl, int ns, int i,
-                                           bool& bad, double (&acc)[KP / 16]) {
+                                           const double* rl, double* sl, double* pvl, int ns,
+                                           int i, bool& bad, double (&acc)[KP / 16]) {
   const int nsm = max(max(__builtin_amdgcn_readlane(ns, 0), __builtin_amdgcn_readlane(ns, 16)),
                       max(__builtin_amdgcn_readlane(ns, 32), __builtin_amdgcn_readlane(ns, 48)));
   if (nsm == 0) return;
   if (nsm <= 8)
-    solve_rows<8, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+    solve_rows<8, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
   else if (nsm <= 16 || KP <= 16)
-    solve_rows<16, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+    solve_rows<16, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
   else if (nsm <= 20)
-    solve_rows<20, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+    solve_rows<20, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
   else if (nsm <= 24)
-    solve_rows<24, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+    solve_rows<24, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
   else if (nsm <= 28)
-    solve_rows<28, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+    solve_rows<28, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
   else
-    solve_rows<32, ACTIVE, KP>(Gs, Ginv, il, rl, sl, ns, nsm, i, bad, acc);
+    solve_rows<32, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
 }
 
 
@@ -301,6 +303,7 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
   __shared__ double p_l[BPP_WAVES][BPP_RPW][KP];     // the right-hand side p
   __shared__ double cp_l[BPP_WAVES][BPP_RPW][KP];    // G^-1 p (active form)
   __shared__ int idx_l[BPP_WAVES][BPP_RPW][CNF];     // the solved set, increasing
+  __shared__ double piv_l[BPP_WAVES][BPP_RPW][CNF];  // pivots of the last elimination
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
   for (int e = threadIdx.x; e < (KP + 1) * LD; e += blockDim.x) {
     const int r = e / LD, c = e % LD;
@@ -316,6 +319,7 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
   int* il = idx_l[wv][g];
   double* pl = p_l[wv][g];
   double* cpl = cp_l[wv][g];
+  double* pvl = piv_l[wv][g];
   // live: index in range with a nonzero Gram diagonal (see gram_inverse_kernel)
   bool act[JS];
 #pragma unroll
@@ -449,8 +453,8 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
     double acc[JS];
 #pragma unroll
     for (int s = 0; s < JS; ++s) acc[s] = 0.0;
-    solve_pass<false, KP>(Gs, Ginv, il, rl, sl, passive ? ns : 0, i, sbad, acc);
-    if (KP > CNF) solve_pass<true, KP>(Gs, Ginv, il, rl, sl, passive ? 0 : ns, i, sbad, acc);
+    solve_pass<false, KP>(Gs, Ginv, il, rl, sl, pvl, passive ? ns : 0, i, sbad, acc);
+    if (KP > CNF) solve_pass<true, KP>(Gs, Ginv, il, rl, sl, pvl, passive ? 0 : ns, i, sbad, acc);
     wave_lds_order();
     if (!solve) continue;
     if (sbad) {
