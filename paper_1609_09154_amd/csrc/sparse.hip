@@ -164,13 +164,42 @@ hipError_t csr_spmm(const int64_t* rowptr, const int32_t* colidx, const float* v
 }
 
 // ---------------------------------------------------------------------------
-// CSR transpose: count entries per column, exclusive scan into the new row
-// pointers, then a stable radix sort of the entries by column.
+// CSR transpose: a stable radix sort of the entries by column, then the new
+// row pointers from the sorted column ids (the first position of each
+// column; a column without entries starts where the next column with
+// entries does).
 // ---------------------------------------------------------------------------
-__global__ void count_cols_kernel(const int32_t* __restrict__ colidx, int64_t nnz,
-                                  int32_t* __restrict__ counts) {
+__global__ void fill_i64_kernel(int64_t* __restrict__ p, int64_t n, int64_t v) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) p[q] = v;
+}
+
+// rowptr_t[c] = first position of column c in the sorted ids, for every
+// column with entries (the others keep -1).
+__global__ void column_starts_kernel(const uint32_t* __restrict__ keys, int64_t nnz,
+                                     int64_t* __restrict__ rowptr_t) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < nnz) atomicAdd(&counts[colidx[p]], 1);
+  if (p < nnz && (p == 0 || keys[p] != keys[p - 1])) rowptr_t[keys[p]] = p;
+}
+
+// Columns without entries: the first position whose id exceeds c (binary
+// search over the sorted ids); rowptr_t[n] = nnz.
+__global__ void empty_column_starts_kernel(const uint32_t* __restrict__ keys, int64_t nnz,
+                                           int64_t n, int64_t* __restrict__ rowptr_t) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > n) return;
+  if (c == n) {
+    rowptr_t[n] = nnz;
+    return;
+  }
+  if (rowptr_t[c] >= 0) return;
+  int64_t lo = 0, hi = nnz;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if ((int64_t)keys[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  rowptr_t[c] = lo;
 }
 
 constexpr int SCAN_BLOCK = 1024;  // elements per block (256 threads x 4)
@@ -201,17 +230,6 @@ __device__ int64_t block_exclusive_scan4(int64_t (&v)[4]) {
   return total;
 }
 
-__global__ __launch_bounds__(256) void scan_block_sums_kernel(const int32_t* __restrict__ counts,
-                                                              int64_t n,
-                                                              int64_t* __restrict__ bsum) {
-  int64_t v[4];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + 4 * threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = base + q < n ? counts[base + q] : 0;
-  const int64_t tot = block_exclusive_scan4(v);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
 // Single block: exclusive scan of nb block sums, in place.
 __global__ __launch_bounds__(256) void scan_top_kernel(int64_t* __restrict__ bsum, int64_t nb) {
   __shared__ int64_t carry;
@@ -231,23 +249,6 @@ __global__ __launch_bounds__(256) void scan_top_kernel(int64_t* __restrict__ bsu
     if (threadIdx.x == 0) carry = cy + tot;
     __syncthreads();
   }
-}
-
-__global__ __launch_bounds__(256) void scan_apply_kernel(const int32_t* __restrict__ counts,
-                                                         int64_t n,
-                                                         const int64_t* __restrict__ bsum,
-                                                         int64_t nnz,
-                                                         int64_t* __restrict__ out) {
-  int64_t v[4];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + 4 * threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = base + q < n ? counts[base + q] : 0;
-  block_exclusive_scan4(v);
-  const int64_t off = bsum[blockIdx.x];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (base + q < n) out[base + q] = v[q] + off;
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = nnz;
 }
 
 // One wave per source row: each stored entry's payload is its row id (high
@@ -291,9 +292,8 @@ static size_t sort_temp_bytes(int64_t n, int64_t nnz) {
 
 size_t csr_transpose_work_bytes(int64_t m, int64_t n, int64_t nnz) {
   (void)m;
-  const size_t nb = (size_t)cdiv(n, SCAN_BLOCK);
-  return round_up((size_t)n * 4, 256) + round_up(nb * 8, 256) + round_up((size_t)nnz * 4, 256) +
-         2 * round_up((size_t)nnz * 8, 256) + round_up(sort_temp_bytes(n, nnz), 256);
+  return round_up((size_t)nnz * 4, 256) + 2 * round_up((size_t)nnz * 8, 256) +
+         round_up(sort_temp_bytes(n, nnz), 256);
 }
 
 // Counts per column and their exclusive scan give the new row pointers; a
@@ -304,11 +304,6 @@ hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const flo
                          int64_t m, int64_t n, int64_t nnz, int64_t* rowptr_t,
                          int32_t* colidx_t, float* vals_t, void* work, hipStream_t st) {
   char* w = (char*)work;
-  int32_t* counts = (int32_t*)w;
-  w += round_up((size_t)n * 4, 256);
-  const int64_t nb = cdiv(n, SCAN_BLOCK);
-  int64_t* bsum = (int64_t*)w;
-  w += round_up((size_t)nb * 8, 256);
   uint32_t* keys_out = (uint32_t*)w;
   w += round_up((size_t)nnz * 4, 256);
   uint64_t* pay_in = (uint64_t*)w;
@@ -316,20 +311,22 @@ hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const flo
   uint64_t* pay_out = (uint64_t*)w;
   w += round_up((size_t)nnz * 8, 256);
   void* temp = w;
-  hipError_t e = hipMemsetAsync(counts, 0, (size_t)n * 4, st);
-  if (e != hipSuccess) return e;
-  if (nnz > 0) count_cols_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(colidx, nnz, counts);
-  scan_block_sums_kernel<<<(unsigned)nb, 256, 0, st>>>(counts, n, bsum);
-  scan_top_kernel<<<1, 256, 0, st>>>(bsum, nb);
-  scan_apply_kernel<<<(unsigned)nb, 256, 0, st>>>(counts, n, bsum, nnz, rowptr_t);
-  if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
-  if (nnz == 0) return hipSuccess;
+  hipError_t e;
+  if (nnz == 0) {
+    fill_i64_kernel<<<(unsigned)cdiv(n + 1, 256), 256, 0, st>>>(rowptr_t, n + 1, 0);
+    return NMF_LAUNCH_CHECK();
+  }
   entry_payload_kernel<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(rowptr, m, vals, pay_in);
   if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
   size_t temp_bytes = sort_temp_bytes(n, nnz);
   e = rocprim::radix_sort_pairs(temp, temp_bytes, (const uint32_t*)colidx, keys_out, pay_in,
                                 pay_out, (size_t)nnz, 0u, col_bits(n), st);
   if (e != hipSuccess) return e;
+  fill_i64_kernel<<<(unsigned)cdiv(n + 1, 256), 256, 0, st>>>(rowptr_t, n + 1, -1);
+  column_starts_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(keys_out, nnz, rowptr_t);
+  empty_column_starts_kernel<<<(unsigned)cdiv(n + 1, 256), 256, 0, st>>>(keys_out, nnz, n,
+                                                                         rowptr_t);
+  if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
   unpack_payload_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(pay_out, nnz, colidx_t,
                                                                   vals_t);
   return NMF_LAUNCH_CHECK();
