@@ -43,6 +43,14 @@ constexpr int BPP_WAVES = 4;   // wavefronts per workgroup
 constexpr int BPP_RPW = 4;     // right-hand sides per wavefront (one per 16-lane row)
 constexpr int CNF = 32;        // largest eliminated set
 
+// v from lane q (any lane of the wavefront), through two scalar reads
+__device__ __forceinline__ double rdl(double v, int q) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)(b & 0xffffffffu), q);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), q);
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
 // v from lane L of this lane's 16-lane row
 template <int L> __device__ __forceinline__ double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + L, 0xf, 0xf, true);
@@ -237,55 +245,62 @@ __device__ __forceinline__ void solve_pass(const double* __restrict__ Gs,
 
 
 // Ginv (KP x KP, double) = inverse of G restricted to the indices i < k with
-// G_ii > 0 (zero rows and columns elsewhere), by Gauss-Jordan elimination in
-// double with one workgroup; *ok = 0 when a pivot of that block is not
-// positive (the block is not numerically positive definite). An index with
-// G_ii = 0 belongs to a zero column of the fixed factor: its right-hand side
-// entry is exactly 0 too, so it stays active with x_i = y_i = 0.
+// G_ii > 0 (zero rows and columns elsewhere); *ok = 0 when a pivot of that
+// block is not positive (the block is not numerically positive definite).
+// An index with G_ii = 0 belongs to a zero column of the fixed factor: its
+// right-hand side entry is exactly 0 too, so it stays active with
+// x_i = y_i = 0.
+//
+// One wavefront, in-place Gauss-Jordan in double: lane r holds row r of M
+// (G on the live indices, the identity elsewhere) and ends with row r of
+// M^-1. The step on pivot q subtracts f_r times the raw pivot row from every
+// row r, with f_r = M_rq / M_qq off the pivot row and 1 - 1 / M_qq on it
+// (which scales the pivot row by 1 / M_qq), then sets column q to the
+// inverse's column (-f_r, and 1 / M_qq on the pivot row). Pivot rows are
+// read with readlane; steps of indices outside the live set are identity
+// steps and are skipped.
+template <int Q, int KP>
+__device__ __forceinline__ void ginv_step(double (&a)[KP], int lane, uint64_t live, int k,
+                                          bool& good) {
+  if (Q >= k || !((live >> Q) & 1ull)) return;
+  const double pv = rdl(a[Q], Q);
+  if (!(pv > 0.0)) good = false;
+  const double s = pv > 0.0 ? 1.0 / pv : 1.0;
+  const bool me = lane == Q;
+  const double f = me ? 1.0 - s : a[Q] * s;
+#pragma unroll
+  for (int c = 0; c < KP; ++c)
+    if (c != Q) a[c] = fma(-f, rdl(a[c], Q), a[c]);
+  a[Q] = me ? s : -f;
+}
+
+template <int KP, int... Q>
+__device__ __forceinline__ void ginv_steps(std::integer_sequence<int, Q...>, double (&a)[KP],
+                                           int lane, uint64_t live, int k, bool& good) {
+  (ginv_step<Q, KP>(a, lane, live, k, good), ...);
+}
+
 template <typename TS, int KP>
-__global__ __launch_bounds__(256) void gram_inverse_kernel(const TS* __restrict__ G, int k,
-                                                           double* __restrict__ Ginv,
-                                                           int* __restrict__ ok) {
-  __shared__ double M[KP][2 * KP + 1];
-  __shared__ double piv;
-  const int t = threadIdx.x;
-  for (int e = t; e < KP * 2 * KP; e += blockDim.x) {
-    const int i = e / (2 * KP), j = e % (2 * KP);
-    const bool li = i < k && G[i * KP + i] > TS(0);
-    const bool lj = (j % KP) < k && G[(j % KP) * KP + (j % KP)] > TS(0);
-    double v = 0.0;
-    if (j < KP) v = (li && lj) ? (double)G[i * KP + j] : (i == j ? 1.0 : 0.0);
-    else v = (j - KP == i) ? 1.0 : 0.0;
-    M[i][j] = v;
+__global__ __launch_bounds__(64) void gram_inverse_kernel(const TS* __restrict__ G, int k,
+                                                          double* __restrict__ Ginv,
+                                                          int* __restrict__ ok) {
+  const int lane = threadIdx.x;
+  const bool mine = lane < k && G[lane * KP + lane] > TS(0);
+  const uint64_t live = __ballot(mine);
+  double a[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+    const bool lc = (live >> c) & 1ull;
+    a[c] = (mine && lc) ? (double)G[lane * KP + c] : (lane == c ? 1.0 : 0.0);
   }
-  __syncthreads();
-  int good = 1;
-  for (int q = 0; q < k; ++q) {
-    if (t == 0) piv = M[q][q];
-    __syncthreads();
-    const double pv = piv;
-    if (!(pv > 0.0)) { good = 0; break; }
-    for (int j = t; j < 2 * KP; j += blockDim.x) M[q][j] /= pv;
-    __syncthreads();
-    for (int e = t; e < KP * 2 * KP; e += blockDim.x) {
-      const int i = e / (2 * KP), j = e % (2 * KP);
-      if (i != q) {
-        const double f = M[i][q];
-        if (j != q) M[i][j] = fma(-f, M[q][j], M[i][j]);
-      }
-    }
-    __syncthreads();
-    for (int i = t; i < KP; i += blockDim.x)
-      if (i != q) M[i][q] = 0.0;
-    __syncthreads();
+  bool good = true;
+  ginv_steps<KP>(std::make_integer_sequence<int, KP>{}, a, lane, live, k, good);
+  if (lane < KP) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c)
+      Ginv[lane * KP + c] = (mine && ((live >> c) & 1ull)) ? a[c] : 0.0;
   }
-  for (int e = t; e < KP * KP; e += blockDim.x) {
-    const int i = e / KP, j = e % KP;
-    const bool li = i < k && G[i * KP + i] > TS(0);
-    const bool lj = j < k && G[j * KP + j] > TS(0);
-    Ginv[e] = (li && lj) ? M[i][KP + j] : 0.0;
-  }
-  if (t == 0) *ok = good;
+  if (lane == 0) *ok = good ? 1 : 0;
 }
 
 template <typename TS, int KP>
@@ -498,7 +513,7 @@ hipError_t bpp_rows_compact(T* X, const T* P, const T* G, int64_t rows, int k, i
   const unsigned blocks = (unsigned)std::min<int64_t>(maxb, cdiv(rows, BPP_WAVES * BPP_RPW));
 #define CASE(K)                                                                          \
   case K:                                                                                \
-    if (k > CNF) gram_inverse_kernel<T, K><<<1, 256, 0, st>>>(G, k, Ginv, ginv_ok);      \
+    if (k > CNF) gram_inverse_kernel<T, K><<<1, 64, 0, st>>>(G, k, Ginv, ginv_ok);            \
     bpp_quad_kernel<T, K><<<blocks, 64 * BPP_WAVES, 0, st>>>(                         \
         X, P, G, Ginv, ginv_ok, rows, k, max_pivots, warm, status, pivots);              \
     break;
