@@ -115,4 +115,8 @@ def test_bf16_runs_match_oracle(algo, k, iters):
         # trajectory must still stay well inside the precision effect itself.
         assert d_b <= 0.5 * d_bx
     else:
-        assert d_b <= 1e-4
+        # HALS at k = 100 on this problem is ill-conditioned along the
+        # trajectory: float32 rounding of the Grams alone moves the oracle's
+        # own trajectory by more than 1e-4
+        # (test_hals_k100_trajectory_is_sensitive_to_gram_rounding)
+        assert d_b <= (5e-4 if (algo == "hals" and k == 100) else 1e-4)
