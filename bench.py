@@ -492,7 +492,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4),
                 "traffic": (tr["hbm_bytes_per_launch"] if tr else None),
-                "kernel": "dense products A H^T and W^T A (MFMA 16x16x4 f32)",
+                "kernel": "dense products A H^T and W^T A (MFMA 16x16x4 %s)" % wl["dtype"],
                 "ms_per_launch": round(ms_launch, 4),
                 "ms_aht": round(stats["ms_mm_aht"] / args.steps, 4),
                 "ms_wta": round(stats["ms_mm_wta"] / args.steps, 4),

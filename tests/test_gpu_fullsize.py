@@ -153,6 +153,34 @@ def test_csr_2e20_abpp_sampled_parity():
     assert errs[1] < errs[0]
 
 
+def test_csr_scaled_copy_abpp_20_iterations():
+    """The sparse workload scaled down to 8192 x 8192 at the same mean row
+    length (about 105 stored entries per row), k = 50, all 20 ABPP iterations
+    of a run against the FP64 oracle's relative error per iteration."""
+    m = n = 8192
+    k, iters = 50, 20
+    csr = erdos_renyi_csr(m, n, 104.9 / n, seed=1609)
+    A = scipy.sparse.csr_matrix((csr.vals.astype(np.float64), csr.colidx, csr.rowptr),
+                                shape=(m, n))
+    W0, H0 = init_factors(m, n, k, seed=9154)
+    W0, H0 = W0.astype(np.float32), H0.astype(np.float32)
+    import torch
+
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(csr.rowptr).to(dev)
+    ci = torch.from_numpy(csr.colidx).to(dev)
+    cv = torch.from_numpy(csr.vals.astype(np.float32)).to(dev)
+    W = torch.from_numpy(W0).to(dev)
+    H = torch.from_numpy(H0).to(dev)
+    step("scaled csr 8192^2: 20 ABPP iterations on the GPU")
+    errs, _ = nmf.nmf_csr(rp, ci, cv, n, W, H, algo="abpp", iters=iters, objective=True)
+    step("scaled csr 8192^2: oracle")
+    _, _, er = oracle.run(A, k, "abpp", iters, W0.astype(np.float64), H0.astype(np.float64))
+    d = rel_diff(errs, er)
+    print("scaled csr ABPP 20 iterations: max rel objective diff %.3e; e_T %.6f" % (d, errs[-1]))
+    assert d <= 1e-5, (errs, er)
+
+
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
 def test_lowp_131072x65536_k100_hals_one_iteration_full_parity(fmt):
     """Precision workloads at full size: A = W0 H0 + |N(0, 0.01)| stored in
