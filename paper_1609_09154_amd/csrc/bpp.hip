@@ -51,7 +51,7 @@ __device__ __forceinline__ double rdl(double v, int q) {
   return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
-// v from lane L of this lane's 16-lane row
+// v from lane L of this lane's 16-lane row (DPP row_newbcast: one v_mov_b64_dpp)
 template <int L> __device__ __forceinline__ double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + L, 0xf, 0xf, true);
 }

@@ -141,6 +141,56 @@ def test_update_abpp(dt, rows, k):
     assert piv >= rows  # at least one passive-set solve per row (x = 0 is infeasible here)
 
 
+@pytest.mark.parametrize("dt,rows,k", [("f32", 200003, 20), ("f64", 200003, 20),
+                                       ("f32", 70001, 50)])
+def test_update_abpp_many_rows(dt, rows, k):
+    """More right-hand sides than the solver holds at once (65,536: 4096
+    workgroups of four wavefronts, four right-hand sides each), so 16-lane
+    rows go on to further right-hand sides; a ragged count; every row checked
+    against the oracle."""
+    npdt, u = DT[dt]
+    G, P, X = _update_inputs(rows, k, 4 * k + 7, rows + 3 * k, npdt)
+    Xd = to_dev(X, npdt)
+    step("update abpp many rows %s rows=%d k=%d" % (dt, rows, k))
+    piv = nmf.nmf_update("abpp", to_dev(G, npdt), to_dev(P, npdt), Xd)
+    ref = oracle.abpp_update_W(G.astype(np.float64), P.astype(np.float64))
+    got = host(Xd).astype(np.float64)
+    cond = np.linalg.cond(G.astype(np.float64))
+    tol = 1e-9 if dt == "f64" else min(1e-2, 50 * cond * u)
+    assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), cond
+    assert piv >= rows
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+@pytest.mark.parametrize("k,zero", [(10, (3,)), (50, (0, 17, 49)), (40, tuple(range(20, 40)))])
+def test_update_abpp_zero_factor_rows(dt, k, zero):
+    """A zero row of the fixed factor H makes the Gram's row and column and
+    P's column zero (the NNLS is not unique there): those indices stay at 0
+    (read off the paper's problem with x_i = y_i = 0 feasible), from a warm
+    start that is positive everywhere; the rest matches the oracle. With
+    k = 40 and half the indices dead, the active form's inverse Gram covers
+    only the live block; the warm start holds every live index, so the
+    first solve takes the active form."""
+    npdt, u = DT[dt]
+    rows, n = 900, 4 * k + 7
+    H = uniform((k, n), seed=k)
+    H[list(zero)] = 0.0
+    A = uniform((rows, n), seed=k + 1)
+    G = (H @ H.T).astype(npdt)
+    P = (A @ H.T).astype(npdt)
+    X = np.ones((rows, k), dtype=npdt)
+    Xd = to_dev(X, npdt)
+    step("update abpp zero factor rows %s k=%d" % (dt, k))
+    nmf.nmf_update("abpp", to_dev(G, npdt), to_dev(P, npdt), Xd)
+    got = host(Xd).astype(np.float64)
+    ref = oracle.abpp_update_W(G.astype(np.float64), P.astype(np.float64))
+    live = [i for i in range(k) if i not in zero]
+    cond = np.linalg.cond(G.astype(np.float64)[np.ix_(live, live)])
+    tol = 1e-9 if dt == "f64" else min(1e-2, 50 * cond * u)
+    assert not np.any(got[:, list(zero)])
+    assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), cond
+
+
 @pytest.mark.parametrize("start", ["zeros", "ones", "random"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("k", [10, 33, 50, 64])
