@@ -92,11 +92,15 @@ int kp_sparse(int k) {
 }
 
 // Slabs of the k x k Gram products: one wavefront per slab of at least 32
-// rows (a slab of 32 rows is 128 MFMAs, about 2 us), at most 1024 slabs. The
-// slabs are summed in a fixed order afterwards.
+// rows (a slab of 32 rows is 128 MFMAs, about 2 us), at most 1024 slabs; past
+// 2^20 rows up to 4096 slabs of at least 1024 rows, so more than one
+// wavefront per SIMD shares the long slabs' latency. The slabs are summed in
+// a fixed order afterwards.
 int64_t gram_splits(int64_t rows) {
   int64_t s = cdiv(rows, 32);
-  return s < 1 ? 1 : (s > 1024 ? 1024 : s);
+  if (s <= 1024) return s < 1 ? 1 : s;
+  const int64_t big = cdiv(rows, 1024);
+  return big <= 1024 ? 1024 : (big > 4096 ? 4096 : big);
 }
 
 nmf_status bind_device(nmf_ctx* ctx) {

@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 DT = {"f32": (np.float32, U32), "f64": (np.float64, U64)}
 
-GRAM_SHAPES = [(1, 1), (37, 7), (1000, 10), (4099, 50), (2500, 64), (777, 100), (300, 128), (5, 16)]
+GRAM_SHAPES = [(1, 1), (37, 7), (1000, 10), (4099, 50), (2500, 64), (777, 100), (300, 128), (5, 16),
+               (40000, 50), (3000001, 50)]  # the last two: 1024 slabs, and the tall-factor slabs
 PROD_SHAPES = [(1, 1, 1), (37, 53, 7), (300, 1000, 10), (1000, 777, 50), (513, 4099, 64),
                (257, 300, 100), (64, 64, 16), (1030, 2051, 33)]
 
