@@ -70,10 +70,6 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(T* __restrict__ X,
   }
 }
 
-// Ranks above 64: the same updates with each thread's row kept in LDS
-// (column tid of a [KP][64] array, so accesses are bank-conflict free) and
-// runtime loops, instead of fully unrolled register code. G is symmetric, so
-// G[i*KP + j] is read along j with uniform loads.
 // MU with several threads per row: the KP outputs of a row are split over
 // TPR threads of RPT outputs each, and a block of 256 threads covers 256 / TPR
 // rows. G and the block's rows of x are staged in LDS first (so the in-place
@@ -130,6 +126,10 @@ __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(T* __restrict__ X,
   }
 }
 
+// MU at ranks above 64: each thread's row kept in LDS (column tid of a
+// [KP][64] array, so accesses are bank-conflict free) and runtime loops,
+// instead of fully unrolled register code. G is symmetric, so G[i*KP + j] is
+// read along j with uniform loads.
 constexpr int LDS_ROWS = 64;
 template <typename T>
 __global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(T* __restrict__ X,
@@ -147,28 +147,6 @@ __global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(T* __restrict__ X
     for (int j = 0; j < k; ++j) d = fma(xs[j * LDS_ROWS + t], G[i * KP + j], d);
     X[r * KP + i] = xs[i * LDS_ROWS + t] * P[r * KP + i] / (d + eps);
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(LDS_ROWS) void hals_rows_lds_kernel(T* __restrict__ X,
-                                                                 const T* __restrict__ P,
-                                                                 const T* __restrict__ G,
-                                                                 int64_t rows, int k, int KP) {
-  __shared__ T xs[NMF_MAX_K * LDS_ROWS];
-  const int t = threadIdx.x;
-  const int64_t r = (int64_t)blockIdx.x * LDS_ROWS + t;
-  if (r >= rows) return;
-  for (int j = 0; j < KP; ++j) xs[j * LDS_ROWS + t] = X[r * KP + j];
-  for (int i = 0; i < k; ++i) {
-    const T gii = G[i * KP + i];
-    if (gii > T(0)) {
-      T s = T(0);
-      for (int j = 0; j < k; ++j) s = fma(xs[j * LDS_ROWS + t], G[i * KP + j], s);
-      const T v = xs[i * LDS_ROWS + t] + (P[r * KP + i] - s) / gii;
-      xs[i * LDS_ROWS + t] = v > T(0) ? v : T(0);
-    }
-  }
-  for (int j = 0; j < KP; ++j) X[r * KP + j] = xs[j * LDS_ROWS + t];
 }
 
 #define KP_SWITCH(KPV, CALL, FALLBACK)                         \
@@ -209,9 +187,19 @@ hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
                      hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   const int tpr = rows >= 65536 ? 4 : (rows >= 16384 ? 8 : 16);
-  KP_SWITCH(KP, (launch_hals_grp<T, KPc>(X, P, G, rows, k, tpr, st)),
-            (hals_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
-                X, P, G, rows, k, KP)));
+  // every padded rank up to NMF_MAX_K takes the grouped sweep; G (KP x KP)
+  // is staged in LDS, at most 64 KB (float) or 128 KB (double) at KP = 128
+  switch (KP) {
+    case 16: launch_hals_grp<T, 16>(X, P, G, rows, k, tpr, st); break;
+    case 32: launch_hals_grp<T, 32>(X, P, G, rows, k, tpr, st); break;
+    case 48: launch_hals_grp<T, 48>(X, P, G, rows, k, tpr, st); break;
+    case 64: launch_hals_grp<T, 64>(X, P, G, rows, k, tpr, st); break;
+    case 80: launch_hals_grp<T, 80>(X, P, G, rows, k, tpr, st); break;
+    case 96: launch_hals_grp<T, 96>(X, P, G, rows, k, tpr, st); break;
+    case 112: launch_hals_grp<T, 112>(X, P, G, rows, k, tpr, st); break;
+    case 128: launch_hals_grp<T, 128>(X, P, G, rows, k, tpr, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return NMF_LAUNCH_CHECK();
 }
 

@@ -88,7 +88,8 @@ def gamma_like(K, u):
 
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("m,n,k", [(1, 5, 1), (400, 300, 10), (1000, 700, 50), (300, 200, 64),
-                                   (150, 120, 100)])
+                                   (150, 120, 100), (700, 500, 72), (333, 301, 96),
+                                   (20000, 300, 128)])
 def test_update_hals_with_normalisation(dt, m, n, k):
     """W sweep (nmf_update) + normalisation (nmf_hals_normalize) against the
     oracle's HALS W step, which normalises column by column."""
