@@ -25,8 +25,9 @@ template <typename T> struct GemmArgs {
 
 // `part` must hold splits * M * N elements when splits > 1. splits <= 0 picks
 // the split count automatically (gemm_auto_splits, at most
-// MAX_PRODUCT_SPLITS for the products).
-constexpr int64_t MAX_PRODUCT_SPLITS = 16;
+// MAX_PRODUCT_SPLITS for the products: 32, so that products with few output
+// rows still fill the chip).
+constexpr int64_t MAX_PRODUCT_SPLITS = 32;
 template <typename T>
 hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a, int64_t splits, T* part,
                     hipStream_t st);
