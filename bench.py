@@ -40,6 +40,7 @@ TRAFFIC_FILE_CSR = os.path.join(ROOT, "profiles", "traffic_csr_spmm_1048576_d1e-
 SPARSE_SOURCES = ("sparse.hip", "common.h")
 LOWP_SOURCES = ("gemm_bf16.hip", "common.h")
 TRAFFIC_FILE_FP8 = os.path.join(ROOT, "profiles", "traffic_fp8_131072x65536_k100.json")
+TRAFFIC_FILE_BF16 = os.path.join(ROOT, "profiles", "traffic_bf16_131072x65536_k100.json")
 COPY_CAL_BYTES = 3 << 30
 
 WORKLOADS = {
@@ -305,8 +306,8 @@ def run_lowp(args, wl):
     b = res[lp]
     ms_launch = 0.5 * (b["stats"]["ms_mm_aht"] + b["stats"]["ms_mm_wta"]) / args.steps
     bytes_launch = float(esize) * m * n
-    tr = (load_traffic(kernel_source_hash(LOWP_SOURCES), TRAFFIC_FILE_FP8, args.workload)
-          if lp == "fp8" else None)
+    tr = load_traffic(kernel_source_hash(LOWP_SOURCES),
+                      TRAFFIC_FILE_FP8 if lp == "fp8" else TRAFFIC_FILE_BF16, args.workload)
     traffic = tr["hbm_bytes_per_launch"] if tr else None
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     f = res["f32"]
