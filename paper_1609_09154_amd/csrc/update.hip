@@ -315,13 +315,43 @@ __global__ void transpose_out_kernel(const T* __restrict__ Ht, int k, int64_t n,
 
 // Full transpose of a dense matrix (A, m x n, lda) into At (n x m, ld m),
 // 64 x 64 tiles through LDS so both the reads and the writes are 256-byte
-// row segments.
+// row segments. With vec set (16-byte aligned A and At, lda and ldt
+// multiples of the 16-byte element count) a tile that lies wholly inside the
+// matrix moves as 16-byte runs both ways: each lane reads one run of a row of
+// A, and writes one run of a row of At gathered from the tile's column.
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_full_kernel(const T* __restrict__ A,
                                                              int64_t lda, int64_t m, int64_t n,
-                                                             T* __restrict__ At, int64_t ldt) {
+                                                             T* __restrict__ At, int64_t ldt,
+                                                             int vec) {
   __shared__ T tile[64][65];
   const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+  if constexpr (sizeof(T) >= 4) {
+  constexpr int VEC = Tr<T>::VEC;        // elements per 16 bytes
+  constexpr int CPR = 64 / VEC;          // 16-byte runs per 64-element row
+  constexpr int RPP = 256 / CPR;         // rows per pass
+  if (vec && r0 + 64 <= m && c0 + 64 <= n) {
+    const int q = threadIdx.x % CPR, rr = threadIdx.x / CPR;
+#pragma unroll
+    for (int i = rr; i < 64; i += RPP) {
+      const V16<T> v = load16_stream<T>(A + (r0 + i) * lda + c0 + VEC * q);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) tile[i][VEC * q + e] = v.v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = rr; i < 64; i += RPP) {
+      T* dst = At + (c0 + i) * ldt + r0 + VEC * q;
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(dst) = make_float4(tile[4 * q][i], tile[4 * q + 1][i],
+                                                      tile[4 * q + 2][i], tile[4 * q + 3][i]);
+      } else {
+        *reinterpret_cast<double2*>(dst) = make_double2(tile[2 * q][i], tile[2 * q + 1][i]);
+      }
+    }
+    return;
+  }
+  }
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int i = ty; i < 64; i += 4) {
     const int64_t r = r0 + i, c = c0 + tx;
@@ -396,8 +426,11 @@ hipError_t transpose_full(const T* A, int64_t lda, int64_t m, int64_t n, T* At, 
       return NMF_LAUNCH_CHECK();
     }
   }
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const int vec = sizeof(T) >= 4 && lda % VEC == 0 && ldt % VEC == 0 &&
+                  (uintptr_t)A % 16 == 0 && (uintptr_t)At % 16 == 0;
   dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(m, 64));
-  transpose_full_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, At, ldt);
+  transpose_full_kernel<T><<<grid, 256, 0, st>>>(A, lda, m, n, At, ldt, vec);
   return NMF_LAUNCH_CHECK();
 }
 
