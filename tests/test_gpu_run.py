@@ -201,6 +201,29 @@ def test_csr_runs(algo, iters):
     assert d <= 1e-5, (errs, er)
 
 
+@pytest.mark.parametrize("algo", ["abpp", "hals", "mu"])
+def test_csr_runs_with_empty_rows_and_columns(algo):
+    """About one stored entry per row: a third of the rows and columns of A are
+    empty, so P and R have zero rows (zero right-hand sides for the BPP
+    solves, zero numerators for MU and HALS)."""
+    m, n, k = 1500, 1200, 16
+    csr = erdos_renyi_csr(m, n, 1.0 / n, seed=11)
+    assert (np.diff(csr.rowptr) == 0).sum() > m // 4
+    assert (np.bincount(csr.colidx, minlength=n) == 0).sum() > n // 4
+    W0, H0 = init_factors(m, n, k, seed=12)
+    W0 = W0.astype(np.float32)
+    H0 = H0.astype(np.float32)
+    Wd, Hd = to_dev(W0, np.float32), to_dev(H0, np.float32)
+    step("csr %s with empty rows and columns %dx%d k=%d" % (algo, m, n, k))
+    errs, _ = nmf.nmf_csr(*csr_dev(csr), n, Wd, Hd, algo=algo, iters=8, objective=True)
+    _, _, er = oracle.run(scipy_csr(csr), k, algo, 8, W0.astype(np.float64),
+                          H0.astype(np.float64))
+    d = rel_diff(errs, er)
+    print("csr %s (empty rows/columns) max rel objective diff %.3e" % (algo, d))
+    assert np.isfinite(host(Wd)).all() and np.isfinite(host(Hd)).all()
+    assert d <= 1e-5, (errs, er)
+
+
 def test_csr_relerr_matches_oracle():
     csr = erdos_renyi_csr(900, 700, 0.03, seed=5)
     W, H = init_factors(900, 700, 20, seed=6)
