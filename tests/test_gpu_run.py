@@ -72,6 +72,34 @@ def test_f32_runs(algo, m, n, k, iters):
     assert (W >= 0).all() and (H >= 0).all()
 
 
+@pytest.mark.parametrize("algo,npdt", [("mu", np.float64), ("hals", np.float64),
+                                       ("abpp", np.float64), ("mu", np.float32),
+                                       ("hals", np.float32)])
+def test_dense_runs_with_zero_rows_and_columns(algo, npdt):
+    """Every third row and every fourth column of A zero. The matching rows of
+    A H^T and columns of W^T A are zero, and so is the minimiser of each
+    update there: MU multiplies by a zero numerator and the NNLS solution of a
+    zero right-hand side is 0, both exactly. HALS takes Section 4.2's update
+    w_i + (p_i - (W Q)_i) / Q_ii, whose rounding can leave a residue of a few
+    units in the last place where the exact value is 0."""
+    m, n, k = 700, 500, 12
+    A = planted_dense(m, n, k, sigma=0.01, seed=21)
+    A[::3, :] = 0.0
+    A[:, ::4] = 0.0
+    W0, H0 = init_factors(m, n, k, seed=22)
+    step("%s %s with zero rows and columns %dx%d k=%d" % (algo, npdt.__name__, m, n, k))
+    W, H, e, _ = run_dense(A.astype(npdt), W0.astype(npdt), H0.astype(npdt), algo, 10, npdt)
+    _, _, er = oracle.run(A.astype(npdt).astype(np.float64), k, algo, 10,
+                          W0.astype(npdt).astype(np.float64), H0.astype(npdt).astype(np.float64))
+    d = rel_diff(e, er)
+    print("%s %s zero rows/columns: max rel objective diff %.3e" % (algo, npdt.__name__, d))
+    assert d <= (1e-10 if npdt == np.float64 else 1e-5), (e, er)
+    tiny = 4 * np.finfo(npdt).eps if algo == "hals" else 0.0
+    assert np.abs(W[::3]).max() <= tiny * np.abs(W).max()
+    assert np.abs(H[:, ::4]).max() <= tiny * np.abs(H).max()
+    assert (W >= 0).all() and (H >= 0).all()
+
+
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_without_transposed_copy(dt):
     """transpose_a=False keeps A H^T on the NN kernel; same bar as above."""
