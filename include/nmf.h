@@ -50,8 +50,10 @@
  *   448 s_j (1 for a zero column), rounded to E4M3 (nearest even), and the
  *   output column is multiplied by s_j. Any scaling of A itself is the
  *   caller's: the factorisation of c A is c times that of A.
- * - 1 <= k <= NMF_MAX_K and k <= min(m, n) is not required, but k must not
- *   exceed NMF_MAX_K. m, n >= 1.
+ * - m, n >= 1 and 1 <= k <= NMF_MAX_K; k may exceed min(m, n). NMF_ABPP and
+ *   the unrolled-iteration gradients take k <= 64 (NMF_EINVAL otherwise).
+ *   With k > min(m, n) a Gram is singular, so ABPP can return NMF_ENUMERIC
+ *   or NMF_ENOTCONV there; MU and HALS are defined for any k.
  * - Calls on one context must not overlap (one stream, shared workspace).
  */
 #ifndef NMF_MI355X_H

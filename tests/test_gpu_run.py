@@ -100,6 +100,20 @@ def test_dense_runs_with_zero_rows_and_columns(algo, npdt):
     assert (W >= 0).all() and (H >= 0).all()
 
 
+@pytest.mark.parametrize("algo", ["mu", "hals"])
+@pytest.mark.parametrize("m,n,k", [(40, 30, 50), (300, 200, 128)])
+def test_f64_runs_rank_above_dimensions_and_at_the_maximum(algo, m, n, k):
+    """k > min(m, n), where both Grams are singular (MU and HALS need no
+    inverse), and k = NMF_MAX_K."""
+    A = planted_dense(m, n, min(k, 20), sigma=0.01, seed=31)
+    W0, H0 = init_factors(m, n, k, seed=32)
+    step("%s f64 %dx%d k=%d" % (algo, m, n, k))
+    W, H, e, _ = run_dense(A, W0, H0, algo, 6, np.float64)
+    _, _, er = oracle.run(A, k, algo, 6, W0, H0)
+    assert rel_diff(e, er) <= 1e-10, (e, er)
+    assert (W >= 0).all() and (H >= 0).all()
+
+
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_without_transposed_copy(dt):
     """transpose_a=False keeps A H^T on the NN kernel; same bar as above."""

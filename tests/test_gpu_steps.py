@@ -193,6 +193,37 @@ def test_update_abpp_zero_factor_rows(dt, k, zero):
     assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), cond
 
 
+@pytest.mark.parametrize("start", ["zeros", "ones"])
+def test_update_abpp_singular_gram_solves_or_reports(start):
+    """k = 50 from a fixed factor with n = 30 columns: G = H H^T has rank 30.
+    The NNLS still has solutions, but not a unique one. The call either
+    returns one, checked by Section 4.3's optimality conditions (x >= 0,
+    y = G x - p >= 0, x_i y_i = 0), or reports the singular system
+    (NMF_ENUMERIC) or the pivot cap (NMF_ENOTCONV)."""
+    k, n, rows = 50, 30, 400
+    H = uniform((k, n), seed=5)
+    A = uniform((rows, n), seed=6)
+    G = H @ H.T
+    P = A @ H.T
+    X = np.zeros((rows, k)) if start == "zeros" else np.ones((rows, k))
+    Xd = to_dev(X, np.float64)
+    step("update abpp singular gram start=%s" % start)
+    try:
+        nmf.nmf_update("abpp", to_dev(G, np.float64), to_dev(P, np.float64), Xd)
+    except nmf.NMFError as e:
+        print("abpp singular gram start=%s: status %d" % (start, e.status))
+        assert e.status in (4, 5)
+        return
+    x = host(Xd)
+    y = x @ G - P
+    tol = 1e-8 * np.abs(P).max()
+    print("abpp singular gram start=%s: solved, max |y| on the support %.3e, min y off it %.3e"
+          % (start, np.abs(y[x > 0]).max(initial=0.0), y[x == 0].min(initial=0.0)))
+    assert (x >= 0).all()
+    assert np.abs(y[x > 0]).max(initial=0.0) <= tol
+    assert y[x == 0].min(initial=0.0) >= -tol
+
+
 @pytest.mark.parametrize("start", ["zeros", "ones", "random"])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("k", [10, 33, 50, 64])
