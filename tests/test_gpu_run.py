@@ -243,6 +243,25 @@ def test_csr_runs(algo, iters):
     assert d <= 1e-5, (errs, er)
 
 
+@pytest.mark.parametrize("algo,k", [("mu", 128), ("hals", 128), ("abpp", 64), ("hals", 1)])
+def test_csr_runs_at_the_rank_limits(algo, k):
+    """The largest rank each update takes on the sparse path (NMF_MAX_K for
+    MU and HALS, 64 for ABPP) and k = 1, with ragged sizes."""
+    m, n = 1001, 799
+    csr = erdos_renyi_csr(m, n, 0.05, seed=k + 3)
+    W0, H0 = init_factors(m, n, k, seed=k + 4)
+    W0 = W0.astype(np.float32)
+    H0 = H0.astype(np.float32)
+    Wd, Hd = to_dev(W0, np.float32), to_dev(H0, np.float32)
+    step("csr %s at the rank limit %dx%d k=%d" % (algo, m, n, k))
+    errs, _ = nmf.nmf_csr(*csr_dev(csr), n, Wd, Hd, algo=algo, iters=5, objective=True)
+    _, _, er = oracle.run(scipy_csr(csr), k, algo, 5, W0.astype(np.float64),
+                          H0.astype(np.float64))
+    d = rel_diff(errs, er)
+    print("csr %s k=%d max rel objective diff %.3e" % (algo, k, d))
+    assert d <= 1e-5, (errs, er)
+
+
 @pytest.mark.parametrize("algo", ["abpp", "hals", "mu"])
 def test_csr_runs_with_empty_rows_and_columns(algo):
     """About one stored entry per row: a third of the rows and columns of A are
