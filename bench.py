@@ -46,6 +46,12 @@ COPY_CAL_BYTES = 3 << 30
 WORKLOADS = {
     "dense-65536x65536-k50-hals-f32": dict(m=65536, n=65536, k=50, k_true=50, algo="hals",
                                            dtype="f32"),
+    # the same matrix under the other two local updates (Section 6.3 compares
+    # the time per iteration of MU, HALS and ABPP)
+    "dense-65536x65536-k50-mu-f32": dict(m=65536, n=65536, k=50, k_true=50, algo="mu",
+                                         dtype="f32"),
+    "dense-65536x65536-k50-abpp-f32": dict(m=65536, n=65536, k=50, k_true=50, algo="abpp",
+                                           dtype="f32"),
     "dense-2000x1000-k10-mu-f64": dict(m=2000, n=1000, k=10, k_true=10, algo="mu", dtype="f64"),
     "csr-1048576x1048576-d1e-4-k50-abpp-f32": dict(m=1 << 20, n=1 << 20, k=50, density=1e-4,
                                                    algo="abpp", dtype="f32", sparse=True),
