@@ -246,6 +246,30 @@ nmf_status nmf_update(nmf_ctx* ctx, nmf_algo algo, nmf_dtype dtype,
                       int64_t rows, int k, const void* G, const void* P,
                       void* X, const nmf_opts* opts, long long* pivots);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update as nmf_update, with the same arguments, kernels and results, whose
+ * scratch (padded copies of G, P and X, the ABPP counters and inverse Gram)
+ * lives in a fixed device array of NMF_NOALLOC_SCRATCH_BYTES that each GPU
+ * holds from the first context created on it until the process ends. The
+ * call never allocates or frees memory and issues no hipMemset; the caller
+ * still owns G, P and X.
+ *   Size limit: with KP = k rounded up to 16 and e = sizeof(element), the
+ *   call needs 2 rows KP e + KP^2 (e + 8) bytes plus at most 1024 of
+ *   alignment, which must not exceed NMF_NOALLOC_SCRATCH_BYTES (F32,
+ *   k <= 64: about 130,000 rows; F64, k = 128: about 32,600); larger calls
+ *   return NMF_EINVAL before any device work.
+ *   Sharing: every call on one GPU, from any context or stream, uses that
+ *   GPU's one array, which keeps the last call's contents (each call clears
+ *   what must start at zero). Calls that overlap on one GPU race; serialise
+ *   them.
+ *   Synchronisation: as nmf_update (MU and HALS only enqueue work; ABPP
+ *   synchronises the stream to read its status and pivot count). */
+#define NMF_NOALLOC_SCRATCH_BYTES (64u << 20)
+nmf_status nmf_update_noalloc(nmf_ctx* ctx, nmf_algo algo, nmf_dtype dtype,
+                              int64_t rows, int k, const void* G, const void* P,
+                              void* X, const nmf_opts* opts, long long* pivots);
+
 /* HALS column normalisation with compensation (Section 4.2): for every
  * i < k with s_i = ||w^i||_2 > 0, w^i <- w^i / s_i and h_i <- s_i h_i, so
  * W H is unchanged. W is m x k, Ht = H^T is n x k (both leading dimension

@@ -19,7 +19,7 @@ __all__ = ["Context", "NMFError", "nmf_dense", "nmf_csr", "nmf_gram", "nmf_dense
            "nmf_mu_unrolled_forward", "nmf_mu_unrolled_backward", "mu_unrolled",
            "nmf_hals_unrolled_forward", "nmf_hals_unrolled_backward", "hals_unrolled",
            "nmf_projected_gradient_sq",
-           "nmf_dense_AtF", "nmf_csr_AF", "nmf_csr_transpose", "nmf_update",
+           "nmf_dense_AtF", "nmf_csr_AF", "nmf_csr_transpose", "nmf_update", "nmf_update_noalloc",
            "nmf_hals_normalize", "nmf_dense_relerr", "nmf_csr_relerr", "library_path"]
 
 
@@ -272,6 +272,23 @@ def nmf_update(algo, G, P, X, eps_mu=1e-16, max_pivots=0, ctx=None):
     code = _lib.ALGOS[algo.lower()] if isinstance(algo, str) else int(algo)
     c.check(_lib.lib().nmf_update(c.handle, code, _dtype_code(X), rows, k, _dev(G, "G"),
                                 _dev(P, "P"), _dev(X, "X"), ctypes.byref(o), ctypes.byref(piv)))
+    return piv.value
+
+
+def nmf_update_noalloc(algo, G, P, X, eps_mu=1e-16, max_pivots=0, ctx=None):
+    """nmf_update on the library's fixed device scratch (no allocation);
+    rejects sizes past NMF_NOALLOC_SCRATCH_BYTES with NMFError."""
+    rows, k = X.shape
+    dt = X.dtype
+    _dev(G, "G", dtype=dt, shape=(k, k))
+    _dev(P, "P", dtype=dt, shape=(rows, k))
+    c = _ctx(ctx, X.device.index or 0)
+    o = default_opts(algo=algo, eps_mu=eps_mu, max_pivots=max_pivots)
+    piv = ctypes.c_longlong(0)
+    code = _lib.ALGOS[algo.lower()] if isinstance(algo, str) else int(algo)
+    c.check(_lib.lib().nmf_update_noalloc(c.handle, code, _dtype_code(X), rows, k, _dev(G, "G"),
+                                          _dev(P, "P"), _dev(X, "X"), ctypes.byref(o),
+                                          ctypes.byref(piv)))
     return piv.value
 
 

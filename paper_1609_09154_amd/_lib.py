@@ -16,6 +16,7 @@ NMF_OK, NMF_EINVAL, NMF_ENOMEM, NMF_EDEVICE, NMF_ENUMERIC, NMF_ENOTCONV = range(
 NMF_MU, NMF_HALS, NMF_ABPP = 0, 1, 2
 NMF_F64, NMF_F32, NMF_BF16, NMF_FP8_E4M3 = 0, 1, 2, 3
 NMF_OBJ_NONE, NMF_OBJ_DIRECT = 0, 1
+NMF_NOALLOC_SCRATCH_BYTES = 64 << 20
 ALGOS = {"mu": NMF_MU, "hals": NMF_HALS, "abpp": NMF_ABPP}
 
 # Every function the header declares, with its ctypes signature.
@@ -65,6 +66,8 @@ SIGNATURES = {
     "nmf_csr_transpose": (_int, [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "nmf_update": (_int, [_vp, _int, _int, _i64, _int, _vp, _vp, _vp, ctypes.POINTER(NmfOpts),
                           ctypes.POINTER(ctypes.c_longlong)]),
+    "nmf_update_noalloc": (_int, [_vp, _int, _int, _i64, _int, _vp, _vp, _vp,
+                                  ctypes.POINTER(NmfOpts), ctypes.POINTER(ctypes.c_longlong)]),
     "nmf_hals_normalize": (_int, [_vp, _int, _i64, _i64, _int, _vp, _vp, _vp, _vp]),
     "nmf_dense_relerr": (_int, [_vp, _int, _i64, _i64, _vp, _i64, _int, _vp, _vp, _dp]),
     "nmf_csr_relerr": (_int, [_vp, _i64, _i64, _i64, _vp, _vp, _vp, _int, _vp, _vp, _dp]),

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,7 +31,51 @@ struct nmf_ctx {
   size_t ws_bytes = 0;
   void* at = nullptr;    // transposed copy of a dense A (see nmf_opts.transpose_a)
   size_t at_bytes = 0;
+  void* scratch = nullptr;  // this device's address of the fixed scratch array (below)
 };
+
+// Fixed device scratch of the allocation-free update (nmf_update_noalloc).
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code the name is only a host-side stand-in: kernels and copies are
+// given the per-device address that hipGetSymbolAddress returns, never the
+// name itself.
+static __device__ __align__(256) unsigned char scratch[NMF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// The scratch array's address on `device` (which must be current), looked
+// up once per device; null when the lookup failed (*err says why).
+void* scratch_address(int device, hipError_t* err) {
+  *err = hipSuccess;
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch_done[device] = true;
+  }
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
+
+__global__ void zero_words_kernel(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+}  // namespace
 
 namespace {
 
@@ -807,6 +852,11 @@ nmf_status nmf_create(nmf_ctx** out, int device, void* hip_stream) {
   nmf_ctx* c = new nmf_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  // Set-up of the allocation-free update: this device's address of the
+  // fixed scratch array. A failed lookup leaves it null; only
+  // nmf_update_noalloc needs it, and it reports the failure.
+  hipError_t se;
+  c->scratch = scratch_address(device, &se);
   *out = c;
   return NMF_OK;
 }
@@ -1063,6 +1113,57 @@ nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, 
   return NMF_OK;
 }
 
+// Slices of the fixed scratch array for update_noalloc_impl: status and
+// pivot counters first (cleared together), then the inverse Gram of ABPP's
+// active form and the padded G, P and X.
+struct NoallocPlan { size_t oS, oV, oI, oG, oP, oX, total; };
+template <typename T> NoallocPlan noalloc_plan(int64_t rows, int KP) {
+  Carve cv;
+  NoallocPlan p;
+  p.oS = cv.take<int>(4);
+  p.oV = cv.take<unsigned long long>(2);
+  p.oI = cv.take<double>((size_t)KP * KP);
+  p.oG = cv.take<T>((size_t)KP * KP);
+  p.oP = cv.take<T>((size_t)rows * KP);
+  p.oX = cv.take<T>((size_t)rows * KP);
+  p.total = cv.off;
+  return p;
+}
+
+// update_impl on the fixed scratch array: the same kernels and launch
+// shapes, no allocation, and fill kernels instead of hipMemsetAsync.
+template <typename T>
+nmf_status update_noalloc_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G,
+                               const T* Pm, T* X, const nmf_opts* o, long long* pivots) {
+  const int KP = kp_dense(k);
+  const NoallocPlan pl = noalloc_plan<T>(rows, KP);
+  char* base = (char*)ctx->scratch;
+  T* Gp = (T*)(base + pl.oG);
+  T* Pp = (T*)(base + pl.oP);
+  T* Xp = (T*)(base + pl.oX);
+  int* dst = (int*)(base + pl.oS);
+  unsigned long long* dpv = (unsigned long long*)(base + pl.oV);
+  hipStream_t st = ctx->stream;
+  // counters: the words from the status slice up to the inverse Gram
+  const int64_t nz = (int64_t)(pl.oI - pl.oS) / 4;
+  zero_words_kernel<<<(unsigned)cdiv(nz, 256), 256, 0, st>>>((uint32_t*)dst, nz);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(nmfk::pad_rows<T>(G, k, k, Gp, KP, st));
+  if (KP > k) {
+    const int64_t nw = (int64_t)(KP - k) * KP * (int64_t)sizeof(T) / 4;
+    zero_words_kernel<<<(unsigned)cdiv(nw, 256), 256, 0, st>>>((uint32_t*)(Gp + (size_t)k * KP), nw);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(nmfk::pad_rows<T>(Pm, rows, k, Pp, KP, st));
+  HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
+  nmf_status s = local_update<T>(ctx, algo, Xp, Pp, Gp, rows, k, KP, o, dst, dpv,
+                                 (double*)(base + pl.oI));
+  if (s != NMF_OK) return s;
+  HIP_TRY(nmfk::unpad_rows<T>(Xp, rows, k, KP, X, st));
+  if (algo == NMF_ABPP) return read_status(ctx, dst, dpv, pivots);
+  return NMF_OK;
+}
+
 template <typename T>
 nmf_status normalize_impl(nmf_ctx* ctx, int64_t m, int64_t n, int k, T* W, T* Ht, T* S,
                           T* norms) {
@@ -1225,6 +1326,42 @@ nmf_status nmf_update(nmf_ctx* ctx, nmf_algo algo, nmf_dtype dtype, int64_t rows
     return update_impl<double>(ctx, algo, rows, k, (const double*)G, (const double*)P,
                                (double*)X, &o, pivots);
   return fail(ctx, NMF_EINVAL, "unknown dtype");
+}
+
+nmf_status nmf_update_noalloc(nmf_ctx* ctx, nmf_algo algo, nmf_dtype dtype, int64_t rows, int k,
+                              const void* G, const void* P, void* X, const nmf_opts* opts,
+                              long long* pivots) {
+  nmf_status s = check_common(ctx, rows, 1, k);
+  if (s != NMF_OK) return s;
+  if (!G || !P || !X) return fail(ctx, NMF_EINVAL, "null G, P or X");
+  if (dtype != NMF_F32 && dtype != NMF_F64) return fail(ctx, NMF_EINVAL, "unknown dtype");
+  nmf_opts o;
+  nmf_default_opts(&o);
+  if (opts) o = *opts;
+  o.algo = algo;
+  if ((s = check_opts(ctx, &o, k, false)) != NMF_OK) return s;
+  const int KP = kp_dense(k);
+  const size_t need = dtype == NMF_F32 ? noalloc_plan<float>(rows, KP).total
+                                       : noalloc_plan<double>(rows, KP).total;
+  if (need > (size_t)NMF_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, NMF_EINVAL,
+                "nmf_update_noalloc: " + std::to_string(rows) + " rows at k = " +
+                    std::to_string(k) + " need " + std::to_string(need) +
+                    " bytes of scratch, more than the fixed " +
+                    std::to_string((size_t)NMF_NOALLOC_SCRATCH_BYTES) + " (use nmf_update)");
+  if ((s = bind_device(ctx)) != NMF_OK) return s;
+  if (!ctx->scratch) {
+    hipError_t e;
+    ctx->scratch = scratch_address(ctx->device, &e);
+    if (!ctx->scratch)
+      return fail(ctx, NMF_EDEVICE,
+                  std::string("scratch array address lookup failed: ") + hipGetErrorString(e));
+  }
+  if (dtype == NMF_F32)
+    return update_noalloc_impl<float>(ctx, algo, rows, k, (const float*)G, (const float*)P,
+                                      (float*)X, &o, pivots);
+  return update_noalloc_impl<double>(ctx, algo, rows, k, (const double*)G, (const double*)P,
+                                     (double*)X, &o, pivots);
 }
 
 nmf_status nmf_hals_normalize(nmf_ctx* ctx, nmf_dtype dtype, int64_t m, int64_t n, int k,

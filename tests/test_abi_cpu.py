@@ -132,6 +132,18 @@ def test_step_argument_errors(hctx):
     assert L.nmf_update(hctx, 2, 1, 10, 80, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
     assert L.nmf_update(hctx, 1, 1, 10, 3, None, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
     assert L.nmf_update(hctx, 1, 1, 10, 3, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EDEVICE
+    # the allocation-free form: same checks, plus its fixed scratch size
+    upd = L.nmf_update_noalloc
+    assert upd(hctx, 9, 1, 10, 3, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
+    assert upd(hctx, 2, 1, 10, 80, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
+    assert upd(hctx, 1, 7, 10, 3, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
+    # float32, k = 64: 2 rows 64 4 + 64^2 (4 + 8) + at most 1024 bytes
+    too_many = _lib.NMF_NOALLOC_SCRATCH_BYTES // (2 * 64 * 4) + 1
+    assert upd(hctx, 1, 1, too_many, 64, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EINVAL
+    assert b"scratch" in L.nmf_last_error(hctx)
+    fits = (_lib.NMF_NOALLOC_SCRATCH_BYTES - 1024 - 64 * 64 * 12) // (2 * 64 * 4)
+    assert upd(hctx, 1, 1, fits, 64, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EDEVICE
+    assert upd(hctx, 1, 0, 32000, 128, P, P, P, ctypes.byref(o), ctypes.byref(piv)) == EDEVICE
     out = ctypes.c_double()
     assert L.nmf_dense_relerr(hctx, 1, 10, 8, P, 8, 3, P, P, None) == EINVAL
     assert L.nmf_dense_relerr(hctx, 1, 10, 8, P, 8, 3, P, P, ctypes.byref(out)) == EDEVICE
