@@ -113,7 +113,9 @@ def test_powerlaw_abpp_run():
     _, _, er = oracle.run(S, k, "abpp", 4, W0.astype(np.float64), H0.astype(np.float64))
     d = rel_diff(errs, er)
     print("powerlaw abpp max rel objective diff %.3e" % d)
-    assert d <= 5e-5, (errs, er)
+    # float32 storage moves this trajectory by about 6e-9
+    # (test_parity_bars_cpu.py::test_powerlaw_abpp_case_stays_below_the_stated_tolerance)
+    assert d <= 1e-5, (errs, er)
 
 
 def test_generator_on_device_matches_its_recipe():

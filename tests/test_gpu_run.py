@@ -12,6 +12,7 @@ import scipy.sparse
 import oracle
 import paper_1609_09154_amd as nmf
 from synth import erdos_renyi_csr, init_factors, planted_dense
+from tests import parity_bars
 from tests.gpu_util import host, rel_diff, step, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -64,11 +65,15 @@ def test_f32_runs(algo, m, n, k, iters):
     d = rel_diff(e, er)
     print("f32 %s %dx%d k=%d max rel objective diff %.3e; e_T gpu %.6e oracle %.6e"
           % (algo, m, n, k, d, e[-1], er[-1]))
-    # FP32 bar 1e-5. ABPP solves each subproblem exactly, which amplifies the
-    # FP32 rounding of A H^T, W^T A and the Grams by cond(G): the FP64 oracle
-    # fed FP32-rounded products already drifts 2.1e-5 from itself by the fifth
-    # iteration of this case, so ABPP's FP32 bar is the measured 5e-5.
-    assert d <= (5e-5 if algo == "abpp" else 1e-5), (e, er)
+    # FP32 bar 1e-5. The ABPP case fits to the noise level and its exact
+    # solves amplify the float32 rounding of A H^T, W^T A and the Grams:
+    # float32 arithmetic alone moves this trajectory by up to 7.9e-5
+    # (test_parity_bars_cpu.py::test_abpp_f32_noise_level_case), so it is
+    # held to the bar derived there.
+    if algo == "abpp":
+        c = parity_bars.ABPP_F32_CASE
+        assert (m, n, k, iters) == (c["m"], c["n"], c["k"], c["iters"]) and 101 + k == c["seed"]
+    assert d <= (parity_bars.ABPP_F32_BAR if algo == "abpp" else 1e-5), (e, er)
     assert (W >= 0).all() and (H >= 0).all()
 
 
