@@ -11,6 +11,7 @@
 // accumulates dL/dA, and the small row-times-matrix update; and the pieces of
 // the HALS adjoint (reverse column sweep, Gram gradient, normalisation).
 #include "common.h"
+#include "grid.h"
 #include "kernels.h"
 
 namespace nmfk {
@@ -155,8 +156,9 @@ __global__ void symmetrize_kernel(const T* __restrict__ G, int KP, T* __restrict
 // Y += X elementwise (n elements).
 template <typename T>
 __global__ void add_kernel(T* __restrict__ Y, const T* __restrict__ X, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) Y[e] += X[e];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+    Y[e] += X[e];
 }
 
 // D (m x n, ld ldd) += X1 Y1^T + X2 Y2^T with X* m x KP and Y* n x KP (row
@@ -424,23 +426,24 @@ __global__ void hals_norm_adjoint_kernel(const T* __restrict__ gWn, const T* __r
                                          const T* __restrict__ norms,
                                          const double* __restrict__ dots, int k, int KP,
                                          T* __restrict__ gWp, T* __restrict__ gHt) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (m + n) * KP) return;
-  const int64_t r = e / KP;
-  const int c = (int)(e - r * KP);
-  const T s = norms[c];
-  const bool scaled = c < k && s > T(0);
-  if (r < m) {
-    const int64_t q = r * KP + c;
-    if (scaled) {
-      const double ds = -dots[c] / (double)s + dots[KP + c];
-      gWp[q] = (T)((double)gWn[q] / (double)s + ds * (double)Wn[q]);
+  const int64_t total = (m + n) * KP, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t r = e / KP;
+    const int c = (int)(e - r * KP);
+    const T s = norms[c];
+    const bool scaled = c < k && s > T(0);
+    if (r < m) {
+      const int64_t q = r * KP + c;
+      if (scaled) {
+        const double ds = -dots[c] / (double)s + dots[KP + c];
+        gWp[q] = (T)((double)gWn[q] / (double)s + ds * (double)Wn[q]);
+      } else {
+        gWp[q] = gWn[q];
+      }
     } else {
-      gWp[q] = gWn[q];
+      const int64_t q = (r - m) * KP + c;
+      gHt[q] = scaled ? s * gHc[q] : gHc[q];
     }
-  } else {
-    const int64_t q = (r - m) * KP + c;
-    gHt[q] = scaled ? s * gHc[q] : gHc[q];
   }
 }
 
@@ -489,7 +492,7 @@ hipError_t symmetrize(const T* G, int KP, T* M, hipStream_t st) {
 template <typename T>
 hipError_t add_to(T* Y, const T* X, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  add_kernel<T><<<(unsigned)cdiv(n, 256), 256, 0, st>>>(Y, X, n);
+  add_kernel<T><<<capped_grid(cdiv(n, 256)), 256, 0, st>>>(Y, X, n);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -550,7 +553,7 @@ hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc,
                              hipStream_t st) {
   const int64_t total = (m + n) * KP;
   if (total == 0) return hipSuccess;
-  hals_norm_adjoint_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(
+  hals_norm_adjoint_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(
       gWn, Wn, m, gHc, n, norms, dots, k, KP, gWp, gHt);
   return NMF_LAUNCH_CHECK();
 }

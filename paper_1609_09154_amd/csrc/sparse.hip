@@ -14,6 +14,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
+#include "grid.h"
 #include "kernels.h"
 
 namespace nmfk {
@@ -80,12 +81,13 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(const int64_t* __restrict
   constexpr int LPN = KP / 4;
   const int lane = threadIdx.x & 63;
   const int grp = lane / LPN, sub = lane % LPN;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= m) return;
-  const int64_t b = rowptr[row], e = rowptr[row + 1];
-  if (e - b > long_limit) return;
-  const float4 acc = segment_sum<KP>(colidx, vals, F, b, e, grp, sub);
-  if (grp == 0) *reinterpret_cast<float4*>(P + row * KP + 4 * sub) = acc;
+  const int64_t wpb = blockDim.x >> 6, stride = (int64_t)gridDim.x * wpb;
+  for (int64_t row = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); row < m; row += stride) {
+    const int64_t b = rowptr[row], e = rowptr[row + 1];
+    if (e - b > long_limit) continue;
+    const float4 acc = segment_sum<KP>(colidx, vals, F, b, e, grp, sub);
+    if (grp == 0) *reinterpret_cast<float4*>(P + row * KP + 4 * sub) = acc;
+  }
 }
 
 // Long rows (power-law sparsity puts much of the work in a few of them): each
@@ -144,7 +146,7 @@ hipError_t csr_spmm(const int64_t* rowptr, const int32_t* colidx, const float* v
   if (m <= 0) return hipSuccess;
   const bool split = lr != nullptr && lr->nlong > 0;
   const int64_t limit = split ? CSR_LONG : INT64_MAX;
-  const unsigned blocks = (unsigned)cdiv(m, 4);
+  const unsigned blocks = capped_grid(cdiv(m, 4));
 #define CASE(K)                                                                               \
   case K:                                                                                     \
     csr_spmm_kernel<K><<<blocks, 256, 0, st>>>(rowptr, colidx, vals, m, F, P, limit);         \
@@ -178,8 +180,9 @@ __global__ void fill_i64_kernel(int64_t* __restrict__ p, int64_t n, int64_t v) {
 // column with entries (the others keep -1).
 __global__ void column_starts_kernel(const uint32_t* __restrict__ keys, int64_t nnz,
                                      int64_t* __restrict__ rowptr_t) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < nnz && (p == 0 || keys[p] != keys[p - 1])) rowptr_t[keys[p]] = p;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride)
+    if (p == 0 || keys[p] != keys[p - 1]) rowptr_t[keys[p]] = p;
 }
 
 // Columns without entries: the first position whose id exceeds c (binary
@@ -258,20 +261,22 @@ __global__ __launch_bounds__(256) void entry_payload_kernel(const int64_t* __res
                                                             const float* __restrict__ vals,
                                                             uint64_t* __restrict__ pay) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= m) return;
-  const uint64_t hi = (uint64_t)i << 32;
-  for (int64_t p = rowptr[i] + lane; p < rowptr[i + 1]; p += 64)
-    pay[p] = hi | (uint64_t)__float_as_uint(vals[p]);
+  const int64_t wpb = blockDim.x >> 6, stride = (int64_t)gridDim.x * wpb;
+  for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < m; i += stride) {
+    const uint64_t hi = (uint64_t)i << 32;
+    for (int64_t p = rowptr[i] + lane; p < rowptr[i + 1]; p += 64)
+      pay[p] = hi | (uint64_t)__float_as_uint(vals[p]);
+  }
 }
 
 __global__ void unpack_payload_kernel(const uint64_t* __restrict__ pay, int64_t nnz,
                                       int32_t* __restrict__ colidx_t, float* __restrict__ vals_t) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nnz) return;
-  const uint64_t v = pay[q];
-  colidx_t[q] = (int32_t)(v >> 32);
-  vals_t[q] = __uint_as_float((unsigned)(v & 0xffffffffu));
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += stride) {
+    const uint64_t v = pay[q];
+    colidx_t[q] = (int32_t)(v >> 32);
+    vals_t[q] = __uint_as_float((unsigned)(v & 0xffffffffu));
+  }
 }
 
 // Key bits of the column ids (enough for n - 1).
@@ -316,18 +321,18 @@ hipError_t csr_transpose(const int64_t* rowptr, const int32_t* colidx, const flo
     fill_i64_kernel<<<(unsigned)cdiv(n + 1, 256), 256, 0, st>>>(rowptr_t, n + 1, 0);
     return NMF_LAUNCH_CHECK();
   }
-  entry_payload_kernel<<<(unsigned)cdiv(m, 4), 256, 0, st>>>(rowptr, m, vals, pay_in);
+  entry_payload_kernel<<<capped_grid(cdiv(m, 4)), 256, 0, st>>>(rowptr, m, vals, pay_in);
   if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
   size_t temp_bytes = sort_temp_bytes(n, nnz);
   e = rocprim::radix_sort_pairs(temp, temp_bytes, (const uint32_t*)colidx, keys_out, pay_in,
                                 pay_out, (size_t)nnz, 0u, col_bits(n), st);
   if (e != hipSuccess) return e;
   fill_i64_kernel<<<(unsigned)cdiv(n + 1, 256), 256, 0, st>>>(rowptr_t, n + 1, -1);
-  column_starts_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(keys_out, nnz, rowptr_t);
+  column_starts_kernel<<<capped_grid(cdiv(nnz, 256)), 256, 0, st>>>(keys_out, nnz, rowptr_t);
   empty_column_starts_kernel<<<(unsigned)cdiv(n + 1, 256), 256, 0, st>>>(keys_out, nnz, n,
                                                                          rowptr_t);
   if ((e = NMF_LAUNCH_CHECK()) != hipSuccess) return e;
-  unpack_payload_kernel<<<(unsigned)cdiv(nnz, 256), 256, 0, st>>>(pay_out, nnz, colidx_t,
+  unpack_payload_kernel<<<capped_grid(cdiv(nnz, 256)), 256, 0, st>>>(pay_out, nnz, colidx_t,
                                                                   vals_t);
   return NMF_LAUNCH_CHECK();
 }

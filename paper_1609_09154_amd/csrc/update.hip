@@ -12,6 +12,7 @@
 //
 // Padding entries k..KP-1 of x are zero on entry and stay zero.
 #include "common.h"
+#include "grid.h"
 #include "kernels.h"
 
 namespace nmfk {
@@ -227,16 +228,16 @@ __global__ void hals_norms_kernel(T* __restrict__ S, T* __restrict__ norms, int 
 template <typename T>
 __global__ void hals_scale_kernel(T* __restrict__ W, int64_t m, T* __restrict__ Ht, int64_t n,
                                   const T* __restrict__ norms, int k, int KP) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (m + n) * KP;
-  if (e >= total) return;
-  const int64_t r = e / KP;
-  const int i = (int)(e - r * KP);
-  if (i >= k) return;
-  const T s = norms[i];
-  if (!(s > T(0))) return;
-  if (r < m) W[r * KP + i] = W[r * KP + i] / s;
-  else Ht[(r - m) * KP + i] = Ht[(r - m) * KP + i] * s;
+  const int64_t total = (m + n) * KP, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t r = e / KP;
+    const int i = (int)(e - r * KP);
+    if (i >= k) continue;
+    const T s = norms[i];
+    if (!(s > T(0))) continue;
+    if (r < m) W[r * KP + i] = W[r * KP + i] / s;
+    else Ht[(r - m) * KP + i] = Ht[(r - m) * KP + i] * s;
+  }
 }
 
 template <typename T>
@@ -247,7 +248,7 @@ hipError_t hals_normalize(T* W, int64_t m, T* Ht, int64_t n, T* S, T* norms, int
   if (e != hipSuccess) return e;
   const int64_t total = (m + n) * KP;
   if (total == 0) return hipSuccess;
-  hals_scale_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(W, m, Ht, n, norms, k, KP);
+  hals_scale_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(W, m, Ht, n, norms, k, KP);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -255,21 +256,23 @@ hipError_t hals_normalize(T* W, int64_t m, T* Ht, int64_t n, T* S, T* norms, int
 template <typename T>
 __global__ void pad_rows_kernel(const T* __restrict__ src, int64_t rows, int k,
                                 T* __restrict__ dst, int KP) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= rows * KP) return;
-  const int64_t r = e / KP;
-  const int i = (int)(e - r * KP);
-  dst[e] = i < k ? src[r * k + i] : T(0);
+  const int64_t total = rows * KP, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t r = e / KP;
+    const int i = (int)(e - r * KP);
+    dst[e] = i < k ? src[r * k + i] : T(0);
+  }
 }
 
 template <typename T>
 __global__ void unpad_rows_kernel(const T* __restrict__ src, int64_t rows, int k, int KP,
                                   T* __restrict__ dst) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= rows * k) return;
-  const int64_t r = e / k;
-  const int i = (int)(e - r * k);
-  dst[e] = src[r * KP + i];
+  const int64_t total = rows * k, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t r = e / k;
+    const int i = (int)(e - r * k);
+    dst[e] = src[r * KP + i];
+  }
 }
 
 // Ht[j][i] = H[i][j] (i < k), 0 for k <= i < KP. Tiled through LDS.
@@ -445,7 +448,7 @@ template <typename T>
 hipError_t pad_rows(const T* src, int64_t rows, int k, T* dst, int KP, hipStream_t st) {
   const int64_t total = rows * KP;
   if (total == 0) return hipSuccess;
-  pad_rows_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(src, rows, k, dst, KP);
+  pad_rows_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(src, rows, k, dst, KP);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -453,7 +456,7 @@ template <typename T>
 hipError_t unpad_rows(const T* src, int64_t rows, int k, int KP, T* dst, hipStream_t st) {
   const int64_t total = rows * k;
   if (total == 0) return hipSuccess;
-  unpad_rows_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(src, rows, k, KP, dst);
+  unpad_rows_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(src, rows, k, KP, dst);
   return NMF_LAUNCH_CHECK();
 }
 
