@@ -449,10 +449,25 @@ template <typename T> static constexpr Shape tn_shape(int NT) {
 constexpr int WAVES = 4;  // waves per workgroup of the product kernels
 
 // Split the reduction until the grid has about one workgroup per CU, keeping
-// every split at least 256 long.
-static int64_t auto_splits(int64_t wgs, int64_t K) {
+// every split at least 256 long. A small product (under 2^26 multiply-adds,
+// such as a 2000 x 1000 matrix at k = 10) may split down to slabs of 64: its
+// few output rows would otherwise leave most of the chip idle while each
+// wavefront walks a long reduction, and at that size the partials cost
+// little. No split is longer than MAX_SPLIT_LEN: the matrix cores add a
+// split's products into one float32 accumulator, one rounding per four
+// terms, and over 32768 terms (65536^2 at k = 50 with two splits) that
+// rounding moved a HALS trajectory by 1.1e-5 relative at its second
+// iteration, against 2.4e-7 with splits of 8192 (whose partials are summed in
+// double) at 2.6% more time per product. Those extra splits are taken only
+// while the partials stay under 2^28 elements (out_elems per split).
+constexpr int64_t MAX_SPLIT_LEN = 8192;
+static int64_t auto_splits(int64_t wgs, int64_t K, int64_t macs, int64_t out_elems) {
+  const int64_t minlen = macs < ((int64_t)1 << 26) ? 64 : 256;
   int64_t s = 1;
-  while (wgs * s < 256 && K / (2 * s) >= 256 && s < MAX_PRODUCT_SPLITS) s *= 2;
+  while (wgs * s < 256 && K / (2 * s) >= minlen && s < MAX_PRODUCT_SPLITS) s *= 2;
+  while (K > s * MAX_SPLIT_LEN && s < MAX_PRODUCT_SPLITS &&
+         2 * s * out_elems <= ((int64_t)1 << 28))
+    s *= 2;
   return s;
 }
 
@@ -523,7 +538,7 @@ static int64_t rows_per_wg(GemmKind kind, int NT) {
 template <typename T>
 int64_t gemm_auto_splits(GemmKind kind, int64_t M, int64_t N, int64_t K) {
   if (kind == GemmKind::TN_GRAM) return 0;
-  return auto_splits(cdiv(M, rows_per_wg<T>(kind, (int)(N / 16))), K);
+  return auto_splits(cdiv(M, rows_per_wg<T>(kind, (int)(N / 16))), K, M * N * K, M * N);
 }
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
