@@ -18,9 +18,10 @@ reported only while the product kernel source is unchanged since the counters
 were taken.
 
 cpu_baseline: the FP64 oracle (tests only, never the product path) timed on
-the host for a few iterations of the same algorithm on a square sample of
-the same planted matrix family, scaled by (m n) / (sample rows)^2 to the
-full workload's iterations per second.
+the host for three iterations of the same algorithm on the workload's own
+matrix (copied to the host and upcast to float64 before timing); where the
+host lacks the memory, or with --cpu-sample, on a square sample of the same
+planted matrix family, scaled by (m n) / (sample rows)^2.
 """
 import argparse
 import hashlib
@@ -37,7 +38,7 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dense_65536x65536_k50.json")
 TRAFFIC_FILE_CSR = os.path.join(ROOT, "profiles", "traffic_csr_spmm_1048576_d1e-4_k50.json")
-SPARSE_SOURCES = ("sparse.hip", "common.h")
+SPARSE_SOURCES = ("sparse.hip", "common.h", "grid.h")
 LOWP_SOURCES = ("gemm_bf16.hip", "common.h")
 TRAFFIC_FILE_FP8 = os.path.join(ROOT, "profiles", "traffic_fp8_131072x65536_k100.json")
 TRAFFIC_FILE_BF16 = os.path.join(ROOT, "profiles", "traffic_bf16_131072x65536_k100.json")
@@ -137,6 +138,61 @@ def cpu_baseline(wl, sample_rows, iters=6):
             "sample": "%d iterations of FP64 %s on a %dx%d planted matrix (k=%d), %.3f s/iter, "
                       "scaled by %.1f to %dx%d" % (iters, wl["algo"].upper(), s, s, wl["k"], dt,
                                                    scale, wl["m"], wl["n"])}
+
+
+def cpu_baseline_full(A_dev, wl, W0n, H0n, iters=3):
+    """Time the FP64 oracle on the workload itself: `iters` iterations of the
+    same algorithm on the full matrix, after one untimed iteration, with A
+    copied to the host and upcast to float64 once before timing (the
+    oracle's products then read it in place)."""
+    import oracle
+
+    cores = len(os.sched_getaffinity(0))
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ.setdefault(var, str(cores))
+    A64 = A_dev.cpu().double().numpy()
+    k = wl["k"]
+    oracle.run(A64, k, wl["algo"], 1, W0n, H0n, track_error=False)  # warm-up
+    t0 = time.perf_counter()
+    oracle.run(A64, k, wl["algo"], iters, W0n, H0n, track_error=False)
+    dt = (time.perf_counter() - t0) / iters
+    try:
+        from threadpoolctl import threadpool_info
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        used = cores
+    return {"value": 1.0 / dt, "unit": "iters/s", "cores": int(used), "kind": "oracle",
+            "sample": "%d iterations of FP64 %s on the full %dx%d matrix of this workload "
+                      "(k=%d; A upcast to float64 on the host before timing, one untimed "
+                      "iteration first), %.3f s/iter" % (iters, wl["algo"].upper(), wl["m"],
+                                                         wl["n"], k, dt)}
+
+
+def host_bytes_free():
+    try:
+        import psutil
+        return psutil.virtual_memory().available
+    except Exception:
+        return 0
+
+
+def bpp_report(st, steps, rhs_per_iter):
+    """ABPP solver work per iteration from the library's tallies: the
+    eliminations' algorithmic FP64 flops against the FP64 vector peak (the
+    solver runs on the vector ALUs in double), and how much of each
+    elimination's size is its own (size / largest size in its wavefront)."""
+    ms = st["ms_luc"] / steps
+    fl = st["bpp_flops"] / steps
+    tf = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    mx = st["bpp_size_max_mean"]
+    return {"ms_per_iter": round(ms, 4), "rhs_per_iter": rhs_per_iter,
+            "solves_per_rhs": round(st["bpp_solves"] / float(steps * rhs_per_iter), 3),
+            "algorithmic_flops_per_iter": fl,
+            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4)},
+            "size_mean": round(st["bpp_size_mean"], 3), "size_wave_max_mean": round(mx, 3),
+            "size_class_mean": round(st["bpp_size_class_mean"], 3),
+            "size_mean_over_wave_max": round(st["bpp_size_mean"] / mx, 4) if mx > 0 else None}
 
 
 def add_paper_context(out, wl):
@@ -253,6 +309,7 @@ def run_sparse(args, wl):
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "csr_spmm (A H^T and A^T W)", "ms_per_launch": round(ms_spmm, 4),
                      "algorithmic_bytes_per_launch": comp_bytes,
+                     "useful_gbs": round(achieved, 1),
                      "traffic_gbs": (round(traffic / (ms_spmm * 1e-3) / 1e9, 1) if traffic
                                      else None),
                      "traffic_frac": (round(traffic / (ms_spmm * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
@@ -261,6 +318,7 @@ def run_sparse(args, wl):
     if wl["algo"] == "abpp":
         out["bpp_pivots_per_rhs"] = round(st["bpp_pivots"] / float(args.steps * (m + n)), 3)
         out["nnls_solves_per_s"] = round(args.steps * (m + n) / (st["ms_luc"] * 1e-3), 1)
+        out["bpp"] = bpp_report(st, args.steps, m + n)
     if args.copy_calibration:
         copy_calibration(dev)
     add_paper_context(out, wl)
@@ -441,6 +499,9 @@ def main():
     ap.add_argument("--workload", default="dense-65536x65536-k50-hals-f32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample-rows", type=int, default=16384)
+    ap.add_argument("--cpu-sample", action="store_true",
+                    help="time the CPU baseline on a square sample of the matrix family "
+                         "instead of the workload's own matrix")
     ap.add_argument("--check", action="store_true", help="also report the final relative error")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 3 GiB device buffer once (reference kernel "
@@ -518,17 +579,24 @@ def main():
                               (("mm", "ms_mm"), ("luc", "ms_luc"), ("gram", "ms_gram"))},
         "roofline": roofline,
     }
+    if wl["algo"] == "abpp":
+        out["bpp"] = bpp_report(stats, args.steps, m + n)
     if args.check:
         rel = nmf.nmf_dense_relerr(A, W, H.t().contiguous())
         out["final_rel_err"] = rel
     if args.copy_calibration:
         copy_calibration(dev)
     add_paper_context(out, wl)
-    del A
-    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, min(args.sample_rows, m))
+        esize = 4 if wl["dtype"] == "f32" else 8
+        if host_bytes_free() > (8 + esize) * m * n * 1.25 and not args.cpu_sample:
+            # the oracle on the workload's own matrix (host copy in float64)
+            out["cpu_baseline"] = cpu_baseline_full(A, wl, W0n, H0n)
+        else:
+            out["cpu_baseline"] = cpu_baseline(wl, min(args.sample_rows, m))
+    del A
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

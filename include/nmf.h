@@ -54,7 +54,9 @@
  *   the unrolled-iteration gradients take k <= 64 (NMF_EINVAL otherwise).
  *   With k > min(m, n) a Gram is singular, so ABPP can return NMF_ENUMERIC
  *   or NMF_ENOTCONV there; MU and HALS are defined for any k.
- * - Calls on one context must not overlap (one stream, shared workspace).
+ * - Calls on one context must not overlap: they share its workspace. A
+ *   context runs on one stream at a time; nmf_set_stream orders the new
+ *   stream after the work already enqueued on the old one.
  */
 #ifndef NMF_MI355X_H
 #define NMF_MI355X_H
@@ -135,6 +137,20 @@ typedef struct {
   long long iters_done; /* iterations performed (< iters when a stop fired)  */
   double pgrad_ratio;   /* NMF_STOP_PGRAD: ||pg(W,H)|| / ||pg(W_0,H_0)|| at the */
                         /* returned factors; otherwise NaN                    */
+  /* ABPP (Section 4.3) work, summed over both half-steps of every iteration.
+   * Each passive-set solve eliminates the smaller of two equivalent systems
+   * (ns unknowns, ns <= 32); four right-hand sides share a wavefront and
+   * eliminate together at the size of the largest of them, rounded up to a
+   * size class (8, 12, 16, 18, 20, ..., 30 or 32). */
+  long long bpp_solves;       /* eliminations performed                    */
+  double bpp_flops;           /* their algorithmic flops: ns^3 - ns (Gauss- */
+                              /* Jordan, one right-hand side) + 2 k ns (the */
+                              /* other half of the KKT pair) each, plus     */
+                              /* 2 k^2 per right-hand side forming G^-1 p   */
+  double bpp_size_mean;       /* mean ns                                    */
+  double bpp_size_max_mean;   /* mean over the same eliminations of the     */
+                              /* largest ns of the wavefront                */
+  double bpp_size_class_mean; /* mean size the eliminations ran at          */
 } nmf_stats;
 
 typedef struct nmf_ctx nmf_ctx;
@@ -151,7 +167,10 @@ void nmf_default_opts(nmf_opts* opts);
  * machine without a GPU). */
 nmf_status nmf_create(nmf_ctx** out, int device, void* hip_stream);
 void nmf_destroy(nmf_ctx* ctx);
-/* Rebinds the context to another stream on the same device. */
+/* Rebinds the context to another stream on the same device. Work the
+ * context has already enqueued on the old stream may still be using its
+ * workspace, so the new stream is made to wait for it (an event recorded on
+ * the old stream) before anything enqueued on it later. */
 nmf_status nmf_set_stream(nmf_ctx* ctx, void* hip_stream);
 
 const char* nmf_status_str(nmf_status s);

@@ -42,7 +42,9 @@ class NmfStats(ctypes.Structure):
                 ("ms_obj", ctypes.c_double), ("ms_setup", ctypes.c_double),
                 ("bpp_pivots", ctypes.c_longlong), ("ms_mm_aht", ctypes.c_double),
                 ("ms_mm_wta", ctypes.c_double), ("iters_done", ctypes.c_longlong),
-                ("pgrad_ratio", ctypes.c_double)]
+                ("pgrad_ratio", ctypes.c_double), ("bpp_solves", ctypes.c_longlong),
+                ("bpp_flops", ctypes.c_double), ("bpp_size_mean", ctypes.c_double),
+                ("bpp_size_max_mean", ctypes.c_double), ("bpp_size_class_mean", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

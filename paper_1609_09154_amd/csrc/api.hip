@@ -32,6 +32,7 @@ struct nmf_ctx {
   void* at = nullptr;    // transposed copy of a dense A (see nmf_opts.transpose_a)
   size_t at_bytes = 0;
   void* scratch = nullptr;  // this device's address of the fixed scratch array (below)
+  hipEvent_t switch_event = nullptr;  // orders a new stream after the old (nmf_set_stream)
 };
 
 // Fixed device scratch of the allocation-free update (nmf_update_noalloc).
@@ -283,9 +284,10 @@ nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part) {
 template <typename T>
 size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_t extra_part,
                  Carve& cv, size_t off[17], bool sparse = false) {
-  const int64_t ps_p = std::max(nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
-                                nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n));
-  const int64_t ps_r = nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m);
+  // split partials of the dense products (the sparse products use none)
+  const int64_t ps_p = sparse ? 1 : std::max(nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
+                                             nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n));
+  const int64_t ps_r = sparse ? 1 : nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, n, KP, m);
   int64_t part = ps_p > 1 ? ps_p * m * KP : 0;
   part = std::max<int64_t>(part, ps_r > 1 ? ps_r * n * KP : 0);
   part = std::max<int64_t>(part, gram_splits(std::max(m, n)) * KP * KP);
@@ -301,7 +303,7 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[8] = cv.take<double>(obj_np + 1);
   off[9] = cv.take<double>(iters + 2);
   off[10] = cv.take<int>(4);
-  off[11] = cv.take<unsigned long long>(2);
+  off[11] = cv.take<unsigned long long>(nmfk::BPP_TALLIES);
   // transposed factor copies for the dense products (unused for sparse A)
   off[12] = cv.take<T>(sparse ? 0 : m * KP);
   off[13] = cv.take<T>(sparse ? 0 : n * KP);
@@ -336,14 +338,17 @@ Work<T> bind_work(nmf_ctx* ctx, const size_t off[17], int64_t obj_np) {
   return w;
 }
 
+// Reads the status flags and the BPP tallies (nmfk::BPP_T_*; tallies_out,
+// nullable, receives all of them).
 nmf_status read_status(nmf_ctx* ctx, const int* dstatus, const unsigned long long* dpiv,
-                       long long* pivots_out) {
+                       long long* pivots_out, unsigned long long* tallies_out = nullptr) {
   int s[2] = {0, 0};
-  unsigned long long pv = 0;
+  unsigned long long pv[nmfk::BPP_TALLIES] = {};
   HIP_TRY(hipMemcpyAsync(s, dstatus, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(hipMemcpyAsync(&pv, dpiv, sizeof(pv), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(pv, dpiv, sizeof(pv), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  if (pivots_out) *pivots_out = (long long)pv;
+  if (pivots_out) *pivots_out = (long long)pv[nmfk::BPP_T_PIVOTS];
+  if (tallies_out) std::memcpy(tallies_out, pv, sizeof(pv));
   if (s[1]) return fail(ctx, NMF_ENUMERIC, "input contains NaN, Inf, negative or malformed entries");
   if (s[0] & 1) return fail(ctx, NMF_ENUMERIC, "ABPP: passive-set system not positive definite");
   if (s[0] & 2) return fail(ctx, NMF_ENOTCONV, "ABPP: pivot cap reached before the KKT conditions held");
@@ -556,9 +561,12 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     RUN(pg_half<T>(ctx, w.Ht, w.R, w.S, n, k, KP, w, 0));
   }
   // Transposed factor copies for the dense products (read with 16-byte loads,
-  // so their rows must stay 16-byte aligned).
-  const bool tH = !pb.sparse && !pb.lp && (n * (int64_t)sizeof(T)) % 16 == 0;
-  const bool tW = !pb.sparse && !pb.lp && (m * (int64_t)sizeof(T)) % 16 == 0;
+  // so their rows must stay 16-byte aligned). Below 2^22 entries of A the
+  // products read the factors in place: the copy's launch would cost more
+  // than its loads save.
+  const bool big = m * n >= ((int64_t)1 << 22);
+  const bool tH = big && !pb.sparse && !pb.lp && (n * (int64_t)sizeof(T)) % 16 == 0;
+  const bool tW = big && !pb.sparse && !pb.lp && (m * (int64_t)sizeof(T)) % 16 == 0;
   if (tH && o->iters > 0) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
@@ -631,9 +639,10 @@ nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_ob
                        double* rel_err, nmf_stats* stats, Timers& tm, hipEvent_t t0,
                        hipEvent_t t1, const StopInfo& si) {
   long long piv = 0;
+  unsigned long long tl[nmfk::BPP_TALLIES] = {};
   const bool need_status = o->algo == NMF_ABPP || o->check_input;
   if (need_status) {
-    nmf_status s = read_status(ctx, w.status, w.pivots, &piv);
+    nmf_status s = read_status(ctx, w.status, w.pivots, &piv, tl);
     if (s != NMF_OK) return s;
   }
   if (rel_err && want_obj) {
@@ -651,6 +660,12 @@ nmf_status finish_call(nmf_ctx* ctx, const nmf_opts* o, Work<T>& w, bool want_ob
     stats->bpp_pivots = piv;
     stats->iters_done = si.iters_done;
     stats->pgrad_ratio = si.ratio;
+    stats->bpp_solves = (long long)tl[nmfk::BPP_T_SOLVES];
+    stats->bpp_flops = (double)tl[nmfk::BPP_T_FLOPS];
+    const double nsol = (double)tl[nmfk::BPP_T_SOLVES];
+    stats->bpp_size_mean = nsol > 0 ? (double)tl[nmfk::BPP_T_SIZE] / nsol : 0.0;
+    stats->bpp_size_max_mean = nsol > 0 ? (double)tl[nmfk::BPP_T_SIZE_MAX] / nsol : 0.0;
+    stats->bpp_size_class_mean = nsol > 0 ? (double)tl[nmfk::BPP_T_SIZE_CLASS] / nsol : 0.0;
   }
   if (rel_err || stats) HIP_TRY(hipStreamSynchronize(ctx->stream));
   return NMF_OK;
@@ -760,7 +775,7 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int lp, co
   Work<T> w = bind_work<T>(ctx, off, obj_np);
   hipStream_t st = ctx->stream;
   HIP_TRY(hipMemsetAsync(w.status, 0, 4 * sizeof(int), st));
-  HIP_TRY(hipMemsetAsync(w.pivots, 0, 2 * sizeof(unsigned long long), st));
+  HIP_TRY(hipMemsetAsync(w.pivots, 0, nmfk::BPP_TALLIES * sizeof(unsigned long long), st));
   if (o->check_input) {
     if (lp == NMF_BF16)
       HIP_TRY(nmfk::check_dense<uint16_t>((const uint16_t*)Alp, lda, m, n, w.status + 1, st));
@@ -863,18 +878,33 @@ nmf_status nmf_create(nmf_ctx** out, int device, void* hip_stream) {
 
 void nmf_destroy(nmf_ctx* ctx) {
   if (!ctx) return;
-  if ((ctx->ws || ctx->at) && ctx->device >= 0) {
+  if ((ctx->ws || ctx->at || ctx->switch_event) && ctx->device >= 0) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->at) (void)hipFree(ctx->at);
+    if (ctx->switch_event) (void)hipEventDestroy(ctx->switch_event);
   }
   delete ctx;
 }
 
 nmf_status nmf_set_stream(nmf_ctx* ctx, void* hip_stream) {
   if (!ctx) return NMF_EINVAL;
-  ctx->stream = (hipStream_t)hip_stream;
+  const hipStream_t next = (hipStream_t)hip_stream;
+  if (next != ctx->stream && ctx->device >= 0 && (ctx->ws || ctx->at)) {
+    // Work already enqueued on the old stream may still use the workspace:
+    // the new stream waits for it before any later call's work starts.
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NMF_EDEVICE, "hipSetDevice failed");
+    if (!ctx->switch_event &&
+        hipEventCreateWithFlags(&ctx->switch_event, hipEventDisableTiming) != hipSuccess) {
+      ctx->switch_event = nullptr;
+      return fail(ctx, NMF_EDEVICE, "hipEventCreateWithFlags failed");
+    }
+    if (hipEventRecord(ctx->switch_event, ctx->stream) != hipSuccess ||
+        hipStreamWaitEvent(next, ctx->switch_event, 0) != hipSuccess)
+      return fail(ctx, NMF_EDEVICE, "ordering the new stream after the old one failed");
+  }
+  ctx->stream = next;
   return NMF_OK;
 }
 
@@ -934,7 +964,7 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   Work<T> w = bind_work<T>(ctx, off, obj_np);
   hipStream_t st = ctx->stream;
   HIP_TRY(hipMemsetAsync(w.status, 0, 4 * sizeof(int), st));
-  HIP_TRY(hipMemsetAsync(w.pivots, 0, 2 * sizeof(unsigned long long), st));
+  HIP_TRY(hipMemsetAsync(w.pivots, 0, nmfk::BPP_TALLIES * sizeof(unsigned long long), st));
   if (opts->check_input) {
     HIP_TRY(nmfk::check_csr(rowptr, colidx, vals, m, n, nnz, w.status + 1, st));
     // Structure must be valid before the transpose and SpMM read it.
@@ -1089,7 +1119,7 @@ nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, 
   const size_t oP = cv.take<T>(rows * KP);
   const size_t oX = cv.take<T>(rows * KP);
   const size_t oS = cv.take<int>(4);
-  const size_t oV = cv.take<unsigned long long>(2);
+  const size_t oV = cv.take<unsigned long long>(nmfk::BPP_TALLIES);
   const size_t oI = cv.take<double>(KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
@@ -1100,7 +1130,7 @@ nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, 
   unsigned long long* dpv = at<unsigned long long>(ctx, oV);
   hipStream_t st = ctx->stream;
   HIP_TRY(hipMemsetAsync(dst, 0, 4 * sizeof(int), st));
-  HIP_TRY(hipMemsetAsync(dpv, 0, 2 * sizeof(unsigned long long), st));
+  HIP_TRY(hipMemsetAsync(dpv, 0, nmfk::BPP_TALLIES * sizeof(unsigned long long), st));
   HIP_TRY(nmfk::pad_rows<T>(G, k, k, Gp, KP, st));
   if (KP > k) HIP_TRY(hipMemsetAsync(Gp + (size_t)k * KP, 0, sizeof(T) * (KP - k) * KP, st));
   HIP_TRY(nmfk::pad_rows<T>(Pm, rows, k, Pp, KP, st));
@@ -1121,7 +1151,7 @@ template <typename T> NoallocPlan noalloc_plan(int64_t rows, int KP) {
   Carve cv;
   NoallocPlan p;
   p.oS = cv.take<int>(4);
-  p.oV = cv.take<unsigned long long>(2);
+  p.oV = cv.take<unsigned long long>(nmfk::BPP_TALLIES);
   p.oI = cv.take<double>((size_t)KP * KP);
   p.oG = cv.take<T>((size_t)KP * KP);
   p.oP = cv.take<T>((size_t)rows * KP);
@@ -1201,7 +1231,7 @@ nmf_status relerr_impl(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, in
                                               nmfk::sumsq_partials<T>(m, n));
   Carve cv;
   size_t off[17];
-  plan_work<T>(m, n, KP, 0, obj_np, 0, cv, off);
+  plan_work<T>(m, n, KP, 0, obj_np, 0, cv, off, pb.sparse);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   Work<T> w = bind_work<T>(ctx, off, obj_np);

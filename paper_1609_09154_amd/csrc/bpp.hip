@@ -219,6 +219,14 @@ __device__ __forceinline__ void solve_rows(const double* __restrict__ Gs,
   product_steps<ACTIVE, KP>(std::make_integer_sequence<int, NS>{}, Gs, Ginv, fi, xs, nsm, li, acc);
 }
 
+// The size an elimination of at most nsm unknowns runs at (solve_pass).
+__device__ __forceinline__ int bpp_size_class(int nsm, int KP) {
+  if (nsm <= 8) return 8;
+  if (nsm <= 12) return 12;
+  if (nsm <= 16 || KP <= 16) return 16;
+  return (nsm + 1) & ~1;   // 18, 20, ..., 32
+}
+
 // One elimination pass over the rows with ns > 0 at the size class of the
 // largest of them.
 template <bool ACTIVE, int KP>
@@ -229,18 +237,19 @@ __device__ __forceinline__ void solve_pass(const double* __restrict__ Gs,
   const int nsm = max(max(__builtin_amdgcn_readlane(ns, 0), __builtin_amdgcn_readlane(ns, 16)),
                       max(__builtin_amdgcn_readlane(ns, 32), __builtin_amdgcn_readlane(ns, 48)));
   if (nsm == 0) return;
-  if (nsm <= 8)
-    solve_rows<8, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
-  else if (nsm <= 16 || KP <= 16)
-    solve_rows<16, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
-  else if (nsm <= 20)
-    solve_rows<20, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
-  else if (nsm <= 24)
-    solve_rows<24, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
-  else if (nsm <= 28)
-    solve_rows<28, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
-  else
-    solve_rows<32, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc);
+#define NMF_BPP_CLASS(C) solve_rows<C, ACTIVE, KP>(Gs, Ginv, il, rl, sl, pvl, ns, nsm, i, bad, acc)
+  if (nsm <= 8) NMF_BPP_CLASS(8);
+  else if (nsm <= 12) NMF_BPP_CLASS(12);
+  else if (nsm <= 16 || KP <= 16) NMF_BPP_CLASS(16);
+  else if (nsm <= 18) NMF_BPP_CLASS(18);
+  else if (nsm <= 20) NMF_BPP_CLASS(20);
+  else if (nsm <= 22) NMF_BPP_CLASS(22);
+  else if (nsm <= 24) NMF_BPP_CLASS(24);
+  else if (nsm <= 26) NMF_BPP_CLASS(26);
+  else if (nsm <= 28) NMF_BPP_CLASS(28);
+  else if (nsm <= 30) NMF_BPP_CLASS(30);
+  else NMF_BPP_CLASS(32);
+#undef NMF_BPP_CLASS
 }
 
 
@@ -319,6 +328,9 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
   __shared__ double cp_l[BPP_WAVES][BPP_RPW][KP];    // G^-1 p (active form)
   __shared__ int idx_l[BPP_WAVES][BPP_RPW][CNF];     // the solved set, increasing
   __shared__ double piv_l[BPP_WAVES][BPP_RPW][CNF];  // pivots of the last elimination
+  // per right-hand-side row of a wavefront: eliminations, their algorithmic
+  // flops, sizes, wavefront-maximum sizes and size classes (BPP_T_* order)
+  __shared__ unsigned long long tally_l[BPP_WAVES][BPP_RPW][BPP_TALLIES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
   for (int e = threadIdx.x; e < (KP + 1) * LD; e += blockDim.x) {
     const int r = e / LD, c = e % LD;
@@ -328,6 +340,8 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
     (&idx_l[0][0][0])[e] = KP;
   for (int e = threadIdx.x; e < BPP_WAVES * BPP_RPW; e += blockDim.x)
     (&rhs_l[0][0][0])[e * (KP + 1) + KP] = 0.0;
+  for (int e = threadIdx.x; e < BPP_WAVES * BPP_RPW * BPP_TALLIES; e += blockDim.x)
+    (&tally_l[0][0][0])[e] = 0ull;
   __syncthreads();
   double* rl = rhs_l[wv][g];
   double* sl = sol_l[wv][g];
@@ -374,15 +388,16 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
         r += stride;
         live = r < rows;
         if (!live) break;
+        const int64_t ro = r * KP;
         bool wpos[JS];
 #pragma unroll
         for (int s = 0; s < JS; ++s) {
           const int j = 16 * s + i;
-          const double pj = j < k ? (double)P[r * KP + j] : 0.0;
+          const double pj = j < k ? (double)P[ro + j] : 0.0;
           pl[j] = pj;
           x[s] = 0.0;
           y[s] = -pj;
-          wpos[s] = warm && act[s] && X[r * KP + j] > TS(0);
+          wpos[s] = warm && act[s] && X[ro + j] > TS(0);
         }
         F = row_bits<JS>(wpos, g) & all;
         done = false;
@@ -446,10 +461,30 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
         cpl[16 * s + i] = act[s] ? acc : 0.0;
       }
       have_cp = true;
+      if (i == 0) tally_l[wv][g][BPP_T_FLOPS] += 2ull * k * k;
     }
     const uint64_t S = passive ? F : (all & ~F);
     const int ns = solve ? __popcll(S) : 0;   // 0 in the active form when F holds every index
     if (__ballot(solve) == 0) continue;
+    if (solve && ns > 0) {
+      // the system size this row's elimination runs at: the largest of its
+      // form in the wavefront, then that size's class
+      const int nf_p = passive ? ns : 0, nf_a = passive ? 0 : ns;
+      const int mp = max(max(__builtin_amdgcn_readlane(nf_p, 0), __builtin_amdgcn_readlane(nf_p, 16)),
+                         max(__builtin_amdgcn_readlane(nf_p, 32), __builtin_amdgcn_readlane(nf_p, 48)));
+      const int ma = max(max(__builtin_amdgcn_readlane(nf_a, 0), __builtin_amdgcn_readlane(nf_a, 16)),
+                         max(__builtin_amdgcn_readlane(nf_a, 32), __builtin_amdgcn_readlane(nf_a, 48)));
+      if (i == 0) {
+        const unsigned long long n3 = (unsigned long long)ns;
+        const int mx = passive ? mp : ma;
+        unsigned long long* t = tally_l[wv][g];
+        t[BPP_T_SOLVES] += 1ull;
+        t[BPP_T_FLOPS] += n3 * n3 * n3 - n3 + 2ull * k * n3;
+        t[BPP_T_SIZE] += n3;
+        t[BPP_T_SIZE_MAX] += (unsigned long long)mx;
+        t[BPP_T_SIZE_CLASS] += (unsigned long long)bpp_size_class(mx, KP);
+      }
+    }
     if (solve) {
       // the solved set in increasing order, then the padding index KP
 #pragma unroll
@@ -499,8 +534,15 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
     }
   }
   if (i == 0) {
-    if (my_pivots) atomicAdd(pivots, my_pivots);
+    tally_l[wv][g][BPP_T_PIVOTS] = my_pivots;
     if (my_status) atomicOr(status, my_status);
+  }
+  wave_lds_order();
+  // one set of atomics per wavefront: lane c adds tally c of its four rows
+  if (lane < BPP_TALLIES) {
+    const unsigned long long v = tally_l[wv][0][lane] + tally_l[wv][1][lane] +
+                                 tally_l[wv][2][lane] + tally_l[wv][3][lane];
+    if (v) atomicAdd(pivots + lane, v);
   }
 }
 

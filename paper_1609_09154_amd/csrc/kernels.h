@@ -210,7 +210,17 @@ hipError_t check_csr(const int64_t* rowptr, const int32_t* colidx, const float* 
 // becomes argmin_{x>=0} 1/2 x^T G x - p^T x. With warm set, the support of
 // the incoming row starts the pivoting. Ginv: KP*KP doubles of scratch,
 // ginv_ok: one device int. status (device int) |= 1 on a singular system,
-// |= 2 on pivot-cap exhaustion; pivots (device) accumulates the solves.
+// |= 2 on pivot-cap exhaustion. pivots (device, BPP_TALLIES counters) adds
+// up, over all right-hand sides: [BPP_T_PIVOTS] passive sets tried (the
+// pivot cap counts these); [BPP_T_SOLVES] eliminations; [BPP_T_FLOPS] their
+// algorithmic flops (ns^3 - ns for Gauss-Jordan on ns unknowns and one
+// right-hand side, 2 k ns for the other half of the optimality pair, 2 k^2
+// per right-hand side that forms G^-1 p); [BPP_T_SIZE] the sizes ns;
+// [BPP_T_SIZE_MAX] the largest size of the same form in the wavefront at
+// that elimination (the four right-hand sides of a wavefront eliminate
+// together); [BPP_T_SIZE_CLASS] the size the elimination ran at.
+enum { BPP_T_PIVOTS = 0, BPP_T_SOLVES, BPP_T_FLOPS, BPP_T_SIZE, BPP_T_SIZE_MAX,
+       BPP_T_SIZE_CLASS, BPP_TALLIES = 8 };
 template <typename T>
 hipError_t bpp_rows_compact(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
                             int max_pivots, int warm, double* Ginv, int* ginv_ok, int* status,

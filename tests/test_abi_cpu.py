@@ -42,7 +42,7 @@ def test_status_strings_and_defaults():
     assert o.max_pivots == 0 and o.objective == 0 and o.transpose_a == 0
     # the ctypes mirrors must be at least as large as the C structs they stand for
     assert o.tol == 0.0 and o.stop == 0
-    assert ctypes.sizeof(_lib.NmfOpts) == 8 * 7 and ctypes.sizeof(_lib.NmfStats) == 8 * 11
+    assert ctypes.sizeof(_lib.NmfOpts) == 8 * 7 and ctypes.sizeof(_lib.NmfStats) == 8 * 16
 
 
 @pytest.fixture

@@ -267,3 +267,42 @@ def test_dense_relerr(dt, m, n, k):
     ref = oracle.relative_error(A.astype(np.float64), W.astype(np.float64), H.astype(np.float64))
     tol = 1e-12 if dt == "f64" else 20 * k * u / max(ref, 1e-3)
     assert abs(got - ref) <= tol * ref
+
+
+def test_context_follows_stream_changes_in_order():
+    """One context used on two streams in turn: nmf_set_stream makes the new
+    stream wait for the work already enqueued on the old one, so a call on
+    the second stream cannot overwrite the shared workspace while the first
+    stream's update still reads it. Results equal those of the same calls on
+    one stream."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    rows, k = 200003, 50
+    X0 = to_dev(uniform((rows, k), seed=71), np.float32)
+    P = to_dev(uniform((rows, k), seed=72) * 30.0, np.float32)
+    F = uniform((3 * k, k), seed=73)
+    G = to_dev(F.T @ F, np.float32)
+    Y = to_dev(uniform((4099, k), seed=74), np.float32)
+    ctx = nmf.Context(0)
+    step("stream switch: reference on one stream")
+    Xa = X0.clone()
+    nmf.nmf_update("abpp", G, P, Xa, ctx=ctx)
+    Ga = nmf.nmf_gram(Y, ctx=ctx)
+    torch.cuda.synchronize()
+    step("stream switch: the same calls on two streams")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    Xb = X0.clone()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        nmf.nmf_update("hals", G, P, Xb, ctx=ctx)     # enqueued, not waited for
+    with torch.cuda.stream(s2):
+        Gb = nmf.nmf_gram(Y, ctx=ctx)
+    torch.cuda.synchronize()
+    Xc = X0.clone()
+    nmf.nmf_update("hals", G, P, Xc, ctx=ctx)
+    torch.cuda.synchronize()
+    assert torch.equal(Gb, Ga)
+    assert torch.equal(Xb, Xc)
+    assert torch.isfinite(Xa).all()
+    ctx.close()
