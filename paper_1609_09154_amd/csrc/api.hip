@@ -261,7 +261,9 @@ nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, i
                         int k, int KP, const nmf_opts* o, int* status,
                         unsigned long long* pivots, double* ginv) {
   hipStream_t st = ctx->stream;
-  if (algo == NMF_MU) HIP_TRY(nmfk::mu_rows<T>(X, Pm, G, rows, k, KP, (T)o->eps_mu, st));
+  if (algo == NMF_MU)
+    HIP_TRY(nmfk::mu_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, (T)o->eps_mu,
+                             nullptr, nullptr, st));
   else if (algo == NMF_HALS) HIP_TRY(nmfk::hals_rows<T>(X, Pm, G, rows, k, KP, st));
   else {
     const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
@@ -273,12 +275,12 @@ nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, i
 }
 
 template <typename T>
-nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part) {
-  nmfk::GemmArgs<T> a{X, KP, X, KP, G, KP, KP, KP, rows, false, 0};
+nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part,
+                T* Gt = nullptr) {
+  nmfk::GemmArgs<T> a{X, KP, X, KP, G, KP, KP, KP, rows, false, 0, Gt};
   HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(rows), part, ctx->stream));
   return NMF_OK;
 }
-
 
 // Workspace offsets for an AU-NMF call on an m x n problem.
 template <typename T>
@@ -404,7 +406,8 @@ nmf_status lp_product(nmf_ctx* ctx, const Prob<float>& pb, const void* X, int64_
 // the rank-side operand with 16-byte loads.
 template <typename T>
 nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F,
-                      const T* Ft, int k, int KP, T* Pout, T* part) {
+                      const T* Ft, int k, int KP, T* Pout, T* part, int* nsplit = nullptr) {
+  if (nsplit) *nsplit = 1;
   if (pb.sparse) {
     if constexpr (sizeof(T) == 4) {
       HIP_TRY(nmfk::csr_spmm(pb.rp, pb.ci, pb.cv, m, F, KP, Pout, pb.lra, ctx->stream));
@@ -421,18 +424,19 @@ nmf_status product_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, con
     // A H^T = (A^T)^T H^T: the TN kernel streaming A^T row by row.
     nmfk::GemmArgs<T> a{pb.At, m, Ft ? Ft : F, Ft ? n : (int64_t)KP, Pout, KP, m, KP, n,
                         Ft != nullptr, k};
-    HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, 0, part, ctx->stream));
+    HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, 0, part, ctx->stream, nsplit));
     return NMF_OK;
   }
   nmfk::GemmArgs<T> a{pb.A, pb.lda, Ft ? Ft : F, Ft ? n : (int64_t)KP, Pout, KP, m, KP, n,
                       Ft != nullptr, k};
-  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::NN, a, 0, part, ctx->stream));
+  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::NN, a, 0, part, ctx->stream, nsplit));
   return NMF_OK;
 }
 
 template <typename T>
 nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F,
-                       const T* Ft, int k, int KP, T* Rout, T* part) {
+                       const T* Ft, int k, int KP, T* Rout, T* part, int* nsplit = nullptr) {
+  if (nsplit) *nsplit = 1;
   if (pb.sparse) {
     if constexpr (sizeof(T) == 4) {
       HIP_TRY(nmfk::csr_spmm(pb.rpt, pb.cit, pb.cvt, n, F, KP, Rout, pb.lrat, ctx->stream));
@@ -449,7 +453,7 @@ nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, co
   }
   nmfk::GemmArgs<T> a{pb.A, pb.lda, Ft ? Ft : F, Ft ? m : (int64_t)KP, Rout, KP, n, KP, m,
                       Ft != nullptr, k};
-  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, 0, part, ctx->stream));
+  HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN, a, 0, part, ctx->stream, nsplit));
   return NMF_OK;
 }
 
@@ -1498,39 +1502,68 @@ MuWork<T> mu_bind(nmf_ctx* ctx, const size_t off[8]) {
 }
 
 // Rank-side operands of the dense products are read from a transposed copy
-// when its rows are 16-byte aligned.
+// (w.Ft) when its rows are 16-byte aligned. ft_ready: the producer of F has
+// already written that copy. With parts set, a split product stays in its
+// slabs (in w.part) for the consumer to sum; otherwise Out receives it.
 template <typename T>
 nmf_status mu_prod_AF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int k,
-                      int KP, T* Out, MuWork<T>& w) {
+                      int KP, T* Out, MuWork<T>& w, bool ft_ready = false,
+                      nmfk::Split<T>* parts = nullptr) {
   const bool tf = (n * (int64_t)sizeof(T)) % 16 == 0;
-  if (tf) HIP_TRY(nmfk::transpose_rows<T>(F, n, KP, w.Ft, ctx->stream));
-  return product_AF<T>(ctx, pb, m, n, F, tf ? w.Ft : nullptr, k, KP, Out, w.part);
+  if (tf && !ft_ready) HIP_TRY(nmfk::transpose_rows<T>(F, n, KP, w.Ft, ctx->stream));
+  int ns = 1;
+  nmf_status s = product_AF<T>(ctx, pb, m, n, F, tf ? w.Ft : nullptr, k, KP, Out, w.part,
+                               parts ? &ns : nullptr);
+  if (parts) *parts = nmfk::Split<T>{ns > 1 ? w.part : Out, ns, m * KP};
+  return s;
 }
 
 template <typename T>
 nmf_status mu_prod_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, const T* F, int k,
-                       int KP, T* Out, MuWork<T>& w) {
+                       int KP, T* Out, MuWork<T>& w, bool ft_ready = false,
+                       nmfk::Split<T>* parts = nullptr) {
   const bool tf = (m * (int64_t)sizeof(T)) % 16 == 0;
-  if (tf) HIP_TRY(nmfk::transpose_rows<T>(F, m, KP, w.Ft, ctx->stream));
-  return product_AtF<T>(ctx, pb, m, n, F, tf ? w.Ft : nullptr, k, KP, Out, w.part);
+  if (tf && !ft_ready) HIP_TRY(nmfk::transpose_rows<T>(F, m, KP, w.Ft, ctx->stream));
+  int ns = 1;
+  nmf_status s = product_AtF<T>(ctx, pb, m, n, F, tf ? w.Ft : nullptr, k, KP, Out, w.part,
+                                parts ? &ns : nullptr);
+  if (parts) *parts = nmfk::Split<T>{ns > 1 ? w.part : Out, ns, n * KP};
+  return s;
+}
+
+// Whether a row kernel can hand a rows x KP factor to the next product as the
+// transposed copy directly (the product reads one for these rows).
+template <typename T>
+bool rows_transposable(int64_t rows, int KP) {
+  return (rows * (int64_t)sizeof(T)) % 16 == 0 && KP <= 64;
 }
 
 // One MU iteration from (W, Ht) into (Wn, Htn) (which may alias W, Ht),
-// leaving P = A H^T, Q = H H^T, R = A^T Wn, S = Wn^T Wn in the given buffers.
+// leaving Q = H H^T and S = Wn^T Wn in the given buffers (and their
+// transposes in Qt and St where set), and P = A H^T and R = A^T Wn where P
+// and R are set (nullable). The products reach the updates as their split
+// slabs. *ft: on entry, whether w.Ft holds Ht's transposed copy; on return,
+// whether it holds Htn's (the update writes it for the next iteration's
+// product).
 template <typename T>
 nmf_status mu_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
                         T eps, const T* W, const T* Ht, T* Wn, T* Htn, T* P, T* Q, T* R, T* S,
-                        MuWork<T>& w) {
+                        MuWork<T>& w, bool* ft, T* Qt = nullptr, T* St = nullptr) {
   hipStream_t st = ctx->stream;
   nmf_status s;
-  if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part)) != NMF_OK) return s;
-  if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, P, w)) != NMF_OK) return s;
-  if (Wn != W) HIP_TRY(hipMemcpyAsync(Wn, W, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(nmfk::mu_rows<T>(Wn, P, Q, m, k, KP, eps, st));
-  if ((s = gram<T>(ctx, Wn, m, KP, S, w.part)) != NMF_OK) return s;
-  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, R, w)) != NMF_OK) return s;
-  if (Htn != Ht) HIP_TRY(hipMemcpyAsync(Htn, Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(nmfk::mu_rows<T>(Htn, R, S, n, k, KP, eps, st));
+  const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
+  nmfk::Split<T> sp;
+  T* Pd = P ? P : w.P;
+  T* Rd = R ? R : w.R;
+  if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part, Qt)) != NMF_OK) return s;
+  if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, Pd, w, *ft, &sp)) != NMF_OK) return s;
+  HIP_TRY(nmfk::mu_rows<T>(W, Wn, sp, Q, m, k, KP, eps, tW ? w.Ft : nullptr,
+                           sp.n > 1 ? P : nullptr, st));
+  if ((s = gram<T>(ctx, Wn, m, KP, S, w.part, St)) != NMF_OK) return s;
+  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, Rd, w, tW, &sp)) != NMF_OK) return s;
+  HIP_TRY(nmfk::mu_rows<T>(Ht, Htn, sp, S, n, k, KP, eps, tH ? w.Ft : nullptr,
+                           sp.n > 1 ? R : nullptr, st));
+  *ft = tH;
   return NMF_OK;
 }
 
@@ -1558,13 +1591,15 @@ nmf_status mu_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64
   Prob<T> pb;
   if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
   const int64_t slot = (m + n) * KP;
+  bool ft = false;
   for (int t = 0; t < iters; ++t) {
     if (ckpt && t % every == 0) {
       T* c = ckpt + (int64_t)(t / every) * slot;
       HIP_TRY(hipMemcpyAsync(c, w.W, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
       HIP_TRY(hipMemcpyAsync(c + m * KP, w.Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
     }
-    s = mu_iteration<T>(ctx, pb, m, n, k, KP, eps, w.W, w.Ht, w.W, w.Ht, w.P, w.Q, w.R, w.S, w);
+    s = mu_iteration<T>(ctx, pb, m, n, k, KP, eps, w.W, w.Ht, w.W, w.Ht, nullptr, w.Q, nullptr,
+                        w.S, w, &ft);
     if (s != NMF_OK) return s;
   }
   HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
@@ -1588,32 +1623,42 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
   const size_t oRs = cv.take<T>(seg * n * KP);         // A^T W_{t+1}
   const size_t oQs = cv.take<T>(seg * KP * KP);
   const size_t oSs = cv.take<T>(seg * KP * KP);
+  const size_t oQts = cv.take<T>(seg * KP * KP);       // their transposes
+  const size_t oSts = cv.take<T>(seg * KP * KP);
+  const size_t ogRs = cv.take<T>(seg * n * KP);        // dL/dR_t over one segment
+  const size_t ogPs = cv.take<T>(seg * m * KP);        // dL/dP_t over one segment
   const size_t ogW = cv.take<T>(m * KP);
   const size_t ogH = cv.take<T>(n * KP);
   const size_t ogW2 = cv.take<T>(m * KP);
   const size_t ogH2 = cv.take<T>(n * KP);
-  const size_t ogR = cv.take<T>(n * KP);
-  const size_t ogP = cv.take<T>(m * KP);
   const size_t ogD = cv.take<T>(mx * KP);
   const size_t otmp = cv.take<T>(mx * KP);
   const size_t ogG = cv.take<T>(KP * KP);
+  const size_t ogGt = cv.take<T>(KP * KP);
   const size_t ogGs = cv.take<T>(KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   MuWork<T> w = mu_bind<T>(ctx, off);
   T *Ws = at<T>(ctx, oWs), *Hs = at<T>(ctx, oHs), *Ps = at<T>(ctx, oPs), *Rs = at<T>(ctx, oRs);
-  T *Qs = at<T>(ctx, oQs), *Ss = at<T>(ctx, oSs);
+  T *Qs = at<T>(ctx, oQs), *Ss = at<T>(ctx, oSs), *gRs = at<T>(ctx, ogRs), *gPs = at<T>(ctx, ogPs);
   T *gW = at<T>(ctx, ogW), *gH = at<T>(ctx, ogH), *gW2 = at<T>(ctx, ogW2), *gH2 = at<T>(ctx, ogH2);
-  T *gR = at<T>(ctx, ogR), *gP = at<T>(ctx, ogP), *gD = at<T>(ctx, ogD), *tmp = at<T>(ctx, otmp);
-  T *gG = at<T>(ctx, ogG), *gGs = at<T>(ctx, ogGs);
+  T *gD = at<T>(ctx, ogD), *tmp = at<T>(ctx, otmp), *gG = at<T>(ctx, ogG), *gGs = at<T>(ctx, ogGs);
+  T *Qts = at<T>(ctx, oQts), *Sts = at<T>(ctx, oSts), *gGt = at<T>(ctx, ogGt);
   hipStream_t st = ctx->stream;
+  const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
   HIP_TRY(nmfk::pad_rows<T>(gWT, m, k, gW, KP, st));
   HIP_TRY(nmfk::transpose_in<T>(gHT, k, n, gH, KP, st));
-  if (gA) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
+  if (gA && iters == 0) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
   Prob<T> pb;
   if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
   const int64_t slot = (m + n) * KP;
   const int64_t nck = mu_ckpt_count(iters, every);
+  // After the first reverse step, the gradient reaching a factor has three
+  // parts: the direct term of the later half-step's adjoint (gW, gH), what
+  // that half-step's product passes back (tmp = A gR or A^T gP) and what its
+  // Gram passes back (X (gG + gG^T)); the adjoint kernel adds the last two.
+  bool pre = false;
+  nmfk::Split<T> yp{nullptr, 0, 0};
   for (int64_t j = nck - 1; j >= 0; --j) {
     const int t0 = (int)(j * every);
     const int L = std::min(iters, t0 + every) - t0;
@@ -1621,10 +1666,12 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
     HIP_TRY(hipMemcpyAsync(Ws, ckpt + j * slot, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(Hs, ckpt + j * slot + m * KP, sizeof(T) * n * KP,
                            hipMemcpyDeviceToDevice, st));
+    bool ft = false;
     for (int i = 0; i < L; ++i) {
       s = mu_iteration<T>(ctx, pb, m, n, k, KP, eps, Ws + i * m * KP, Hs + i * n * KP,
                           Ws + (i + 1) * m * KP, Hs + (i + 1) * n * KP, Ps + i * m * KP,
-                          Qs + i * KP * KP, Rs + i * n * KP, Ss + i * KP * KP, w);
+                          Qs + i * KP * KP, Rs + i * n * KP, Ss + i * KP * KP, w, &ft,
+                          Qts + i * KP * KP, Sts + i * KP * KP);
       if (s != NMF_OK) return s;
     }
     for (int i = L - 1; i >= 0; --i) {
@@ -1632,33 +1679,52 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
       const T* W1s = Ws + (i + 1) * m * KP;
       const T* H0s = Hs + i * n * KP;
       const T* H1s = Hs + (i + 1) * n * KP;
+      T* gR = gRs + i * n * KP;
+      T* gP = gPs + i * m * KP;
       // H step: Ht' = Ht * R / (Ht S + eps), R = A^T W1, S = W1^T W1
-      HIP_TRY(nmfk::mu_adjoint_rows<T>(H0s, H1s, Rs + i * n * KP, Ss + i * KP * KP, gH, n, k,
-                                       KP, eps, gR, gD, gH2, st));
+      HIP_TRY(nmfk::mu_adjoint_rows<T>(H0s, H1s, Rs + i * n * KP, Ss + i * KP * KP,
+                                       Sts + i * KP * KP, gH,
+                                       pre ? yp : nmfk::Split<T>{nullptr, 0, 0},
+                                       pre ? gG : nullptr, gGt, n, k, KP, eps, gR,
+                                       tH ? w.Ft : nullptr, gD, gH2, st));
       {
-        nmfk::GemmArgs<T> a{H0s, KP, gD, KP, gG, KP, KP, KP, n, false, 0};
+        nmfk::GemmArgs<T> a{H0s, KP, gD, KP, gG, KP, KP, KP, n, false, 0, gGt};
         HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(n), w.part, st));
       }
-      HIP_TRY(nmfk::symmetrize<T>(gG, KP, gGs, st));
-      if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w)) != NMF_OK) return s;
-      HIP_TRY(nmfk::add_to<T>(gW, tmp, m * KP, st));
-      HIP_TRY(nmfk::rowmm_add<T>(W1s, gGs, m, k, KP, gW, st));
-      // W step: W1 = W0 * P / (W0 Q + eps), P = A H0^T, Q = H0 H0^T
-      HIP_TRY(nmfk::mu_adjoint_rows<T>(W0s, W1s, Ps + i * m * KP, Qs + i * KP * KP, gW, m, k,
-                                       KP, eps, gP, gD, gW2, st));
+      if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w, tH, &yp)) != NMF_OK) return s;
+      // W step: W1 = W0 * P / (W0 Q + eps), P = A H0^T, Q = H0 H0^T; the
+      // gradient reaching W1 is gW + A gR + W1 (gG + gG^T)
+      HIP_TRY(nmfk::mu_adjoint_rows<T>(W0s, W1s, Ps + i * m * KP, Qs + i * KP * KP,
+                                       Qts + i * KP * KP, gW, yp, gG, gGt, m, k, KP, eps, gP,
+                                       tW ? w.Ft : nullptr, gD, gW2, st));
       {
-        nmfk::GemmArgs<T> a{W0s, KP, gD, KP, gG, KP, KP, KP, m, false, 0};
+        nmfk::GemmArgs<T> a{W0s, KP, gD, KP, gG, KP, KP, KP, m, false, 0, gGt};
         HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(m), w.part, st));
       }
-      HIP_TRY(nmfk::symmetrize<T>(gG, KP, gGs, st));
-      if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w)) != NMF_OK) return s;
-      HIP_TRY(nmfk::add_to<T>(gH2, tmp, n * KP, st));
-      HIP_TRY(nmfk::rowmm_add<T>(H0s, gGs, n, k, KP, gH2, st));
-      // dL/dA += W1 gR^T (from R = A^T W1) + gP H0 (from P = A H0^T)
-      if (gA) HIP_TRY(nmfk::rank_update<T>(gA, ldga, m, n, W1s, gR, gP, H0s, KP, st));
+      // A^T gP reaches the next H step as slabs, except across a segment
+      // boundary (the recomputation reuses w.part) and at the end
+      if (i > 0) {
+        if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w, tW, &yp)) != NMF_OK) return s;
+      } else {
+        if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w, tW)) != NMF_OK) return s;
+        yp = nmfk::Split<T>{tmp, 1, 0};
+      }
+      pre = true;
       std::swap(gW, gW2);
       std::swap(gH, gH2);
     }
+    // dL/dA (+)= sum over the segment of W_{t+1} gR_t^T (from R = A^T W1)
+    // + gP_t H_t (from P = A H0^T); the last segment (first in this loop)
+    // writes D, the others add to it
+    if (gA)
+      HIP_TRY(nmfk::rank_update<T>(gA, ldga, m, n, Ws + m * KP, gRs, gPs, Hs, KP, L,
+                                   j == nck - 1 ? 0 : 1, st));
+  }
+  if (pre) {
+    // H_0 also fed the first W step: dL/dH_0 += A^T gP_0 + H_0 (gG + gG^T)
+    HIP_TRY(nmfk::add_to<T>(gH, tmp, n * KP, st));
+    HIP_TRY(nmfk::symmetrize<T>(gG, KP, gGs, st));
+    HIP_TRY(nmfk::rowmm_add<T>(Hs, gGs, n, k, KP, gH, st));
   }
   HIP_TRY(nmfk::unpad_rows<T>(gW, m, k, KP, gW0, st));
   HIP_TRY(nmfk::transpose_out<T>(gH, k, n, KP, gH0, st));
@@ -1753,8 +1819,8 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   const size_t ogH = cv.take<T>(n * KP);
   const size_t ogW2 = cv.take<T>(m * KP);
   const size_t ogH2 = cv.take<T>(n * KP);
-  const size_t ogR = cv.take<T>(n * KP);
-  const size_t ogP = cv.take<T>(m * KP);
+  const size_t ogRs = cv.take<T>(seg * n * KP);       // dL/dR_t over one segment
+  const size_t ogPs = cv.take<T>(seg * m * KP);       // dL/dP_t over one segment
   const size_t ogHc = cv.take<T>(n * KP);
   const size_t ogWp = cv.take<T>(m * KP);
   const size_t otmp = cv.take<T>(mx * KP);
@@ -1769,13 +1835,14 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   T *Ws = at<T>(ctx, oWs), *Hs = at<T>(ctx, oHs), *Wps = at<T>(ctx, oWp), *Hcs = at<T>(ctx, oHc);
   T *Ns = at<T>(ctx, oNs), *Qs = at<T>(ctx, oQs), *Ss = at<T>(ctx, oSs);
   T *gW = at<T>(ctx, ogW), *gH = at<T>(ctx, ogH), *gW2 = at<T>(ctx, ogW2), *gH2 = at<T>(ctx, ogH2);
-  T *gR = at<T>(ctx, ogR), *gP = at<T>(ctx, ogP), *gHc = at<T>(ctx, ogHc), *gWp = at<T>(ctx, ogWp);
+  T *gRs = at<T>(ctx, ogRs), *gPs = at<T>(ctx, ogPs), *gHc = at<T>(ctx, ogHc);
+  T* gWp = at<T>(ctx, ogWp);
   T *tmp = at<T>(ctx, otmp), *T1 = at<T>(ctx, oT1), *T2 = at<T>(ctx, oT2), *M = at<T>(ctx, oM);
   double *dots = at<double>(ctx, odots), *dpart = at<double>(ctx, odpart);
   hipStream_t st = ctx->stream;
   HIP_TRY(nmfk::pad_rows<T>(gWT, m, k, gW, KP, st));
   HIP_TRY(nmfk::transpose_in<T>(gHT, k, n, gH, KP, st));
-  if (gA) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
+  if (gA && iters == 0) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
   Prob<T> pb;
   if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
   auto tn = [&](const T* X, const T* Y, int64_t rows, T* D) -> nmf_status {
@@ -1804,6 +1871,8 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
       const T* H1s = Hs + (i + 1) * n * KP;
       const T* Wp = Wps + i * m * KP;
       const T* Hc = Hcs + i * n * KP;
+      T* gR = gRs + i * n * KP;
+      T* gP = gPs + i * m * KP;
       // H sweep on the rows of Hc with R = A^T Wn and S = Wn^T Wn
       HIP_TRY(nmfk::hals_adjoint_rows<T>(H1s, Ss + i * KP * KP, gH, n, k, KP, gHc, gR, st));
       if ((s = tn(H1s, gR, n, T1)) != NMF_OK) return s;
@@ -1825,11 +1894,14 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
       if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w)) != NMF_OK) return s;
       HIP_TRY(nmfk::add_to<T>(gH2, tmp, n * KP, st));
       HIP_TRY(nmfk::rowmm_add<T>(H0s, M, n, k, KP, gH2, st));
-      // dL/dA += Wn gR^T (from R = A^T Wn) + gP H^T (from P = A H^T)
-      if (gA) HIP_TRY(nmfk::rank_update<T>(gA, ldga, m, n, W1s, gR, gP, H0s, KP, st));
       std::swap(gW, gW2);
       std::swap(gH, gH2);
     }
+    // dL/dA (+)= sum over the segment of Wn gR^T (from R = A^T Wn) + gP H^T
+    // (from P = A H^T); the last segment (first in this loop) writes D
+    if (gA)
+      HIP_TRY(nmfk::rank_update<T>(gA, ldga, m, n, Ws + m * KP, gRs, gPs, Hs, KP, L,
+                                   j == nck - 1 ? 0 : 1, st));
   }
   HIP_TRY(nmfk::unpad_rows<T>(gW, m, k, KP, gW0, st));
   HIP_TRY(nmfk::transpose_out<T>(gH, k, n, KP, gH0, st));

@@ -12,6 +12,7 @@
 // the HALS adjoint (reverse column sweep, Gram gradient, normalisation).
 #include "common.h"
 #include "grid.h"
+#include "rowtile.h"
 #include "kernels.h"
 
 namespace nmfk {
@@ -24,84 +25,175 @@ template <int KP> struct AdjSplit {
   static constexpr int ROWS = 256 / TPR;
 };
 
-// Local adjoint of Xn = X * N / (X G + eps) for the rows of one block: writes
-// gN, gD (= dL/dD) and gX; entries k..KP-1 are 0. G, the block's rows of X
-// and dL/dD (shared between a row's threads for the (dL/dD) G^T term) live in
-// LDS.
-template <typename T, int KP>
+// Local adjoint of Xn = X * N / (X G + eps) for the rows of one block. The
+// gradient reaching Xn is gXn, plus (PRE) Y + Xn (M + M^T): what the next
+// half-step's product (Y) and Gram (M) pass back to Xn, added here rather
+// than in kernels of their own. Writes gN (and, if gNt is set, its
+// transpose), gD (= dL/dD) and gX; entries k..KP-1 are 0. G, (PRE) M + M^T
+// (from M and its transpose Mtr), the block's rows of X and (PRE) of Xn live
+// in LDS; the Xn rows' buffer then holds dL/dD and the X rows' buffer gN for
+// the transposed store.
+// Both G-products run in the same form: one value of the row broadcast from
+// LDS times 16-byte runs of a matrix row, d_i = sum_j x_j G[j][i] from G
+// and (dL/dx)_i = sum_j dd_j G[i][j] from G^T (Gtr, the Gram's transposed
+// copy, staged as well where the LDS budget allows, GT; otherwise row i of G
+// against the row's dd).
+template <typename T, int KP, bool PRE>
 __global__ __launch_bounds__(256) void mu_adjoint_rows_kernel(
     const T* __restrict__ X, const T* __restrict__ Xn, const T* __restrict__ N,
-    const T* __restrict__ G, const T* __restrict__ gXn, int64_t rows, int k, T eps,
-    T* __restrict__ gN, T* __restrict__ gD, T* __restrict__ gX) {
+    const T* __restrict__ G, const T* __restrict__ Gtr, const T* __restrict__ gXn, Split<T> Y,
+    const T* __restrict__ M, const T* __restrict__ Mtr, int64_t rows, int k, T eps,
+    T* __restrict__ gN, T* __restrict__ gNt, T* __restrict__ gD, T* __restrict__ gX) {
   constexpr int TPR = AdjSplit<KP>::TPR, RPT = AdjSplit<KP>::RPT, ROWS = AdjSplit<KP>::ROWS;
   constexpr int VEC = Tr<T>::VEC;
   constexpr int DLD = KP + VEC;
+  constexpr bool GT = sizeof(T) == 4 || KP <= 32;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
+  __shared__ __attribute__((aligned(16))) T Gt[GT ? KP * KP : VEC];
+  __shared__ __attribute__((aligned(16))) T Ms[PRE ? KP * KP : VEC];
   __shared__ __attribute__((aligned(16))) T Xs[ROWS * DLD];
   __shared__ __attribute__((aligned(16))) T Ds[ROWS * DLD];
-  for (int e = threadIdx.x; e < KP * KP; e += 256) Gs[e] = G[e];
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
-  for (int e = threadIdx.x; e < ROWS * KP; e += 256) {
-    const int q = e / KP, j = e % KP;
-    Xs[q * DLD + j] = rb + q < rows ? X[(rb + q) * KP + j] : T(0);
-  }
-  __syncthreads();
   const int lr = threadIdx.x / TPR;
   const int64_t r = rb + lr;
   const bool live = r < rows;
   const int i0 = (threadIdx.x % TPR) * RPT;
-  const T* xs = &Xs[lr * DLD];
-  T d[RPT];
+  // The staging loads, then Y's slabs (independent of them, summed in slab
+  // order in double and rounded once), all in flight together; then the LDS
+  // writes.
+  SquareStage<T, KP, 256> gst, gtst, mst;
+  RowStage<T, KP, ROWS, DLD, 256> xst, xnst;
+  gst.load(G, nullptr);
+  if constexpr (GT) gtst.load(Gtr, nullptr);
+  if constexpr (PRE) {
+    if (M) mst.load(M, Mtr);
+    xnst.load(Xn, rb, rows);
+  }
+  xst.load(X, rb, rows);
+  // the row's entries of gXn, N and (not PRE) Xn: 16-byte runs, issued with
+  // the staging loads (rows past the end read the last row and store nothing)
+  constexpr int NV = RPT / VEC;
+  const int64_t rowc = live ? r : rows - 1;
+  V16<T> gxv[NV], nv[NV], xnv[NV];
 #pragma unroll
-  for (int ii = 0; ii < RPT; ++ii) d[ii] = T(0);
+  for (int h = 0; h < NV; ++h) {
+    gxv[h] = load16<T>(gXn + rowc * KP + i0 + h * VEC);
+    nv[h] = load16<T>(N + rowc * KP + i0 + h * VEC);
+    if constexpr (!PRE) xnv[h] = load16<T>(Xn + rowc * KP + i0 + h * VEC);
+  }
+  double ys[RPT];
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) ys[ii] = 0.0;
+  if (PRE && live && Y.p) slab_sum<T, RPT>(Y.p + r * KP + i0, Y.n, Y.stride, ys);
+  gst.store(Gs);
+  if constexpr (GT) gtst.store(Gt);
+  if constexpr (PRE) {
+    if (M) {
+      mst.store(Ms);
+    } else {
+      for (int e = threadIdx.x; e < KP * KP; e += 256) Ms[e] = T(0);
+    }
+    xnst.store(Ds, rb, rows);
+  }
+  xst.store(Xs, rb, rows);
+  __syncthreads();
+  const T* xs = &Xs[lr * DLD];
+  const T* xns = &Ds[lr * DLD];
+  // d = x G (the denominators) and, PRE, p = xn (M + M^T)
+  T d[RPT], p[RPT];
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) d[ii] = p[ii] = T(0);
 #pragma unroll 8
   for (int j = 0; j < KP; ++j) {
     const T xj = xs[j];
+    T xnj = T(0);
+    if constexpr (PRE) xnj = xns[j];
 #pragma unroll
     for (int q = 0; q < RPT / VEC; ++q) {
       const V16<T> v = load16<T>(&Gs[j * KP + i0 + q * VEC]);
 #pragma unroll
       for (int w = 0; w < VEC; ++w) d[q * VEC + w] = fma(xj, v.v[w], d[q * VEC + w]);
+      if constexpr (PRE) {
+        const V16<T> mv = load16<T>(&Ms[j * KP + i0 + q * VEC]);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) p[q * VEC + w] = fma(xnj, mv.v[w], p[q * VEC + w]);
+      }
     }
   }
+  if constexpr (PRE) {
+    if (Y.p) {
+#pragma unroll
+      for (int ii = 0; ii < RPT; ++ii) p[ii] += (T)ys[ii];
+    }
+  }
+  T gn[RPT], dd[RPT], gx[RPT];
 #pragma unroll
   for (int ii = 0; ii < RPT; ++ii) {
     const int i = i0 + ii;
-    T dd = T(0);
-    if (live) {
-      const int64_t e = r * KP + i;
-      if (i < k) {
-        const T den = d[ii] + eps;
-        const T g = gXn[e];
-        gN[e] = g * xs[i] / den;
-        dd = -g * Xn[e] / den;
-        gX[e] = g * N[e] / den;  // direct term; (dL/dD) G^T is added below
-      } else {
-        gN[e] = T(0);
-        gX[e] = T(0);
-      }
-      gD[e] = dd;
+    gn[ii] = dd[ii] = gx[ii] = T(0);
+    if (live && i < k) {
+      T g = gxv[ii / VEC].v[ii % VEC];
+      if constexpr (PRE) g += p[ii];
+      const T xn = PRE ? xns[i] : xnv[ii / VEC].v[ii % VEC];
+      const T den = d[ii] + eps;
+      gn[ii] = g * xs[i] / den;
+      dd[ii] = -g * xn / den;
+      gx[ii] = g * nv[ii / VEC].v[ii % VEC] / den;  // direct term; (dL/dD) G^T is added below
     }
-    Ds[lr * DLD + i] = dd;
+  }
+  if (live) {
+#pragma unroll
+    for (int ii = 0; ii < RPT; ++ii) {
+      gN[r * KP + i0 + ii] = gn[ii];
+      gD[r * KP + i0 + ii] = dd[ii];
+    }
+  }
+  __syncthreads();  // the staged rows of X and Xn are no longer read
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) {
+    Ds[lr * DLD + i0 + ii] = dd[ii];
+    Xs[lr * DLD + i0 + ii] = gn[ii];
   }
   __syncthreads();
-  if (!live) return;
-  // D_i = sum_j x_j G[j][i], so dL/dx_i picks up sum_j dd_j G[i][j]
+  if (live) {
+    // D_i = sum_j x_j G[j][i], so dL/dx_i picks up sum_j dd_j G[i][j]
+    if constexpr (GT) {
+      T acc[RPT];
 #pragma unroll
-  for (int ii = 0; ii < RPT; ++ii) {
-    const int i = i0 + ii;
-    if (i < k) {
-      T acc = T(0);
-#pragma unroll 4
-      for (int q = 0; q < KP / VEC; ++q) {
-        const V16<T> gv = load16<T>(&Gs[i * KP + q * VEC]);
-        const V16<T> dv = load16<T>(&Ds[lr * DLD + q * VEC]);
+      for (int ii = 0; ii < RPT; ++ii) acc[ii] = T(0);
+      const T* dds = &Ds[lr * DLD];
+#pragma unroll 8
+      for (int j = 0; j < KP; ++j) {
+        const T dj = dds[j];
 #pragma unroll
-        for (int w = 0; w < VEC; ++w) acc = fma(dv.v[w], gv.v[w], acc);
+        for (int q = 0; q < RPT / VEC; ++q) {
+          const V16<T> v = load16<T>(&Gt[j * KP + i0 + q * VEC]);
+#pragma unroll
+          for (int w = 0; w < VEC; ++w) acc[q * VEC + w] = fma(dj, v.v[w], acc[q * VEC + w]);
+        }
       }
-      gX[r * KP + i] += acc;
+#pragma unroll
+      for (int ii = 0; ii < RPT; ++ii)
+        gX[r * KP + i0 + ii] = i0 + ii < k ? gx[ii] + acc[ii] : T(0);
+    } else {
+#pragma unroll
+      for (int ii = 0; ii < RPT; ++ii) {
+        const int i = i0 + ii;
+        T acc = gx[ii];
+        if (i < k) {
+#pragma unroll 4
+          for (int q = 0; q < KP / VEC; ++q) {
+            const V16<T> gv = load16<T>(&Gs[i * KP + q * VEC]);
+            const V16<T> dv = load16<T>(&Ds[lr * DLD + q * VEC]);
+#pragma unroll
+            for (int w = 0; w < VEC; ++w) acc = fma(dv.v[w], gv.v[w], acc);
+          }
+        }
+        gX[r * KP + i] = acc;
+      }
     }
   }
+  if (gNt) store_rows_transposed<T, KP, ROWS, DLD>(Xs, rb, rows, gNt);
 }
 
 // Out[r] += X[r] M for rows x KP X and KP x KP M.
@@ -114,12 +206,9 @@ __global__ __launch_bounds__(256) void rowmm_add_kernel(const T* __restrict__ X,
   constexpr int XLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Ms[KP * KP];
   __shared__ __attribute__((aligned(16))) T Xs[ROWS * XLD];
-  for (int e = threadIdx.x; e < KP * KP; e += 256) Ms[e] = M[e];
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
-  for (int e = threadIdx.x; e < ROWS * KP; e += 256) {
-    const int q = e / KP, j = e % KP;
-    Xs[q * XLD + j] = rb + q < rows ? X[(rb + q) * KP + j] : T(0);
-  }
+  stage_square<T, KP, 256>(Ms, M, nullptr);
+  stage_rows<T, KP, ROWS, XLD, 256>(Xs, X, rb, rows);
   __syncthreads();
   const int lr = threadIdx.x / TPR;
   const int64_t r = rb + lr;
@@ -161,13 +250,16 @@ __global__ void add_kernel(T* __restrict__ Y, const T* __restrict__ X, int64_t n
     Y[e] += X[e];
 }
 
-// D (m x n, ld ldd) += X1 Y1^T + X2 Y2^T with X* m x KP and Y* n x KP (row
-// layout, KP contiguous). Each wave forms a 64 x 64 tile on the matrix cores
-// (16 x 16 x 4 tiles, the reduction index permuted so every operand load is
-// 16 bytes) and adds it to D; a workgroup is 64 rows x 256 columns. The tile
-// goes to D through LDS, 16 rows at a time, so that each row of D is read and
-// written as whole 16-byte runs across consecutive lanes (vec: n, ldd and D
-// allow it; otherwise element by element).
+// D (m x n, ld ldd) = beta D + sum_{t < L} (X1_t Y1_t^T + X2_t Y2_t^T) with
+// X*_t m x KP and Y*_t n x KP (row layout, KP contiguous, slab t at offset
+// t m KP or t n KP): the whole reduction of one checkpoint segment, 2 L KP
+// long, in one pass over D. Each wave forms a 64 x 64 tile on the matrix
+// cores (16 x 16 x 4 tiles, the reduction index permuted so every operand
+// load is 16 bytes; the loads of step s + 1 are in flight while step s
+// computes) and adds it to D; a workgroup is 64 rows x 256 columns. The
+// tile goes to D through LDS, 16 rows at a time, so that each row of D is
+// read and written as whole 16-byte runs across consecutive lanes (vec: n,
+// ldd and D allow it; otherwise element by element).
 constexpr int RU = 64;
 template <typename T>
 __global__ __launch_bounds__(256, 2) void rank_update_kernel(T* __restrict__ D, int64_t ldd,
@@ -176,8 +268,9 @@ __global__ __launch_bounds__(256, 2) void rank_update_kernel(T* __restrict__ D, 
                                                           const T* __restrict__ Y1,
                                                           const T* __restrict__ X2,
                                                           const T* __restrict__ Y2, int KP,
-                                                          int vec) {
+                                                          int L, int beta, int vec) {
   constexpr int VEC = Tr<T>::VEC;
+  constexpr int KSTEP = 4 * VEC;        // reduction entries per step
   constexpr int LD = RU + VEC;          // LDS row pitch of a staged slab
   constexpr int LPR = RU / VEC;         // lanes per row when draining (16 or 32)
   constexpr int RPP = 64 / LPR;         // rows per pass (4 or 2)
@@ -200,7 +293,7 @@ __global__ __launch_bounds__(256, 2) void rank_update_kernel(T* __restrict__ D, 
       for (int p = 0; p < NP; ++p) {
         const int64_t row = r0 + 16 * a + p * RPP + lane / LPR;
         const int64_t col = c0 + (lane % LPR) * VEC;
-        if (vec && row < m && col < n) {
+        if (beta && vec && row < m && col < n) {
           dpre[a][p] = load16<T>(D + row * ldd + col);
         } else {
 #pragma unroll
@@ -213,36 +306,47 @@ __global__ __launch_bounds__(256, 2) void rank_update_kernel(T* __restrict__ D, 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = zero4<T>();
+  // Offsets of the lane's rows of X and of Y within a slab (clamped at the
+  // ends; the extra products land outside D and are not stored).
+  int64_t xo[4], yo[4];
 #pragma unroll
-  for (int pr = 0; pr < 2; ++pr) {
-    const T* X = pr == 0 ? X1 : X2;
-    const T* Y = pr == 0 ? Y1 : Y2;
-    if (X == nullptr) continue;
-    const T* xr[4];
-    const T* yr[4];
+  for (int t = 0; t < 4; ++t) {
+    const int64_t row = r0 + 16 * t + c, col = c0 + 16 * t + c;
+    xo[t] = (row < m ? row : m - 1) * KP + VEC * g;
+    yo[t] = (col < n ? col : n - 1) * KP + VEC * g;
+  }
+  // Step s covers entries kk .. kk + KSTEP - 1 of pair p = s / SPP of the
+  // reduction: pair 2t is (X1_t, Y1_t), pair 2t + 1 is (X2_t, Y2_t).
+  const int SPP = KP / KSTEP;
+  const int npair = X2 ? 2 * L : L;
+  const int64_t nsteps = (int64_t)npair * SPP;
+  V16<T> xa[2][4], yb[2][4];
+  auto load = [&](V16<T>(&xv)[4], V16<T>(&yv)[4], int64_t s) {
+    const int p = (int)(s / SPP), kk = (int)(s % SPP) * KSTEP;
+    const int t = X2 ? p >> 1 : p;
+    const bool second = X2 && (p & 1);
+    const T* Xb = (second ? X2 : X1) + (int64_t)t * m * KP + kk;
+    const T* Yb = (second ? Y2 : Y1) + (int64_t)t * n * KP + kk;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      int64_t row = r0 + 16 * t + c;
-      row = row < m ? row : m - 1;
-      xr[t] = X + row * KP;
-      int64_t col = c0 + 16 * t + c;
-      col = col < n ? col : n - 1;
-      yr[t] = Y + col * KP;
+    for (int q = 0; q < 4; ++q) {
+      xv[q] = load16<T>(Xb + xo[q]);
+      yv[q] = load16<T>(Yb + yo[q]);
     }
-    for (int kk = 0; kk < KP; kk += 4 * VEC) {
-      V16<T> xa[4], yb[4];
+  };
+  auto compute = [&](const V16<T>(&xv)[4], const V16<T>(&yv)[4]) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        xa[t] = load16<T>(xr[t] + kk + VEC * g);
-        yb[t] = load16<T>(yr[t] + kk + VEC * g);
-      }
+    for (int v = 0; v < VEC; ++v)
 #pragma unroll
-      for (int v = 0; v < VEC; ++v)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(xa[a].v[v], yb[b].v[v], acc[a][b]);
-    }
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(xv[a].v[v], yv[b].v[v], acc[a][b]);
+  };
+  if (nsteps > 0) load(xa[0], yb[0], 0);
+  for (int64_t s = 0; s < nsteps; s += 2) {
+    if (s + 1 < nsteps) load(xa[1], yb[1], s + 1);
+    compute(xa[0], yb[0]);
+    if (s + 2 < nsteps) load(xa[0], yb[0], s + 2);
+    if (s + 1 < nsteps) compute(xa[1], yb[1]);
   }
   T* sw = slab[wave];
 #pragma unroll
@@ -264,8 +368,14 @@ __global__ __launch_bounds__(256, 2) void rank_update_kernel(T* __restrict__ D, 
         const T* sp = &sw[rl * LD + cl];
         if (vec) {
           V16<T> dv;
-          if constexpr (PREFETCH) dv = dpre[a][p];
-          else dv = load16<T>(dp);
+          if constexpr (PREFETCH) {
+            dv = dpre[a][p];
+          } else if (beta) {
+            dv = load16<T>(dp);
+          } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) dv.v[v] = T(0);
+          }
 #pragma unroll
           for (int v = 0; v < VEC; ++v) dv.v[v] += sp[v];
           if constexpr (sizeof(T) == 4) {
@@ -276,7 +386,7 @@ __global__ __launch_bounds__(256, 2) void rank_update_kernel(T* __restrict__ D, 
         } else {
 #pragma unroll
           for (int v = 0; v < VEC; ++v)
-            if (col + v < n) dp[v] += sp[v];
+            if (col + v < n) dp[v] = (beta ? dp[v] : T(0)) + sp[v];
         }
       }
     }
@@ -315,10 +425,7 @@ __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
   constexpr int TPR = HalsAdjGroup<KP>::TPR, R = HalsAdjGroup<KP>::R;
   constexpr int ROWS = HalsAdjGroup<KP>::ROWS;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
-  for (int e = threadIdx.x; e < KP * KP; e += 256) {
-    const int i = e / KP, j = e - i * KP;
-    Gs[e] = G[j * KP + i];
-  }
+  stage_square_t<T, KP, 256>(Gs, G);
   __syncthreads();
   const int sub = threadIdx.x % TPR;
   const int64_t r = (int64_t)blockIdx.x * ROWS + threadIdx.x / TPR;
@@ -448,15 +555,23 @@ __global__ void hals_norm_adjoint_kernel(const T* __restrict__ gWn, const T* __r
 }
 
 template <typename T>
-hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* gXn,
-                           int64_t rows, int k, int KP, T eps, T* gN, T* gD, T* gX,
-                           hipStream_t st) {
+hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* Gt,
+                           const T* gXn, Split<T> Y, const T* M, const T* Mt, int64_t rows, int k,
+                           int KP, T eps, T* gN, T* gNt, T* gD, T* gX, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
+  if ((Y.p && Y.n < 1) || !Gt || (M && !Mt)) return hipErrorInvalidValue;
+  const bool pre = Y.p != nullptr || M != nullptr;
   switch (KP) {
 #define CASE(K)                                                                               \
   case K:                                                                                     \
-    mu_adjoint_rows_kernel<T, K><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0, st>>>(   \
-        X, Xn, N, G, gXn, rows, k, eps, gN, gD, gX);                                          \
+    if (pre)                                                                                  \
+      mu_adjoint_rows_kernel<T, K, true><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0,    \
+                                           st>>>(X, Xn, N, G, Gt, gXn, Y, M, Mt, rows, k, eps, \
+                                                 gN, gNt, gD, gX);                             \
+    else                                                                                      \
+      mu_adjoint_rows_kernel<T, K, false><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0,   \
+                                            st>>>(X, Xn, N, G, Gt, gXn, Y, M, Mt, rows, k,     \
+                                                  eps, gN, gNt, gD, gX);                       \
     break;
     CASE(16) CASE(32) CASE(48) CASE(64)
 #undef CASE
@@ -498,13 +613,14 @@ hipError_t add_to(T* Y, const T* X, int64_t n, hipStream_t st) {
 
 template <typename T>
 hipError_t rank_update(T* D, int64_t ldd, int64_t m, int64_t n, const T* X1, const T* Y1,
-                       const T* X2, const T* Y2, int KP, hipStream_t st) {
+                       const T* X2, const T* Y2, int KP, int L, int beta, hipStream_t st) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (KP % (4 * Tr<T>::VEC) != 0) return hipErrorInvalidValue;
+  if (KP % (4 * Tr<T>::VEC) != 0 || L < 0 || (beta != 0 && beta != 1))
+    return hipErrorInvalidValue;
   constexpr int VEC = Tr<T>::VEC;
   const int vec = n % VEC == 0 && ldd % VEC == 0 && (uintptr_t)D % 16 == 0;
   dim3 grid((unsigned)cdiv(n, 4 * RU), (unsigned)cdiv(m, RU));
-  rank_update_kernel<T><<<grid, 256, 0, st>>>(D, ldd, m, n, X1, Y1, X2, Y2, KP, vec);
+  rank_update_kernel<T><<<grid, 256, 0, st>>>(D, ldd, m, n, X1, Y1, X2, Y2, KP, L, beta, vec);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -568,12 +684,13 @@ hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc,
                                            const T*, const double*, int, int, T*, T*,         \
                                            hipStream_t);                                      \
   template hipError_t mu_adjoint_rows<T>(const T*, const T*, const T*, const T*, const T*,    \
-                                         int64_t, int, int, T, T*, T*, T*, hipStream_t);      \
+                                         const T*, Split<T>, const T*, const T*, int64_t, int, \
+                                         int, T, T*, T*, T*, T*, hipStream_t);                 \
   template hipError_t rowmm_add<T>(const T*, const T*, int64_t, int, int, T*, hipStream_t);   \
   template hipError_t symmetrize<T>(const T*, int, T*, hipStream_t);                          \
   template hipError_t add_to<T>(T*, const T*, int64_t, hipStream_t);                          \
   template hipError_t rank_update<T>(T*, int64_t, int64_t, int64_t, const T*, const T*,       \
-                                     const T*, const T*, int, hipStream_t);
+                                     const T*, const T*, int, int, int, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

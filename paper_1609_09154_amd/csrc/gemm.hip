@@ -371,17 +371,19 @@ __global__ __launch_bounds__(256, WPE) void gemm_tn_kernel(
   }
 }
 
-// out[i] = sum_s part[s * stride + i] in order s = 0, 1, ... (double sums).
+// out[i] = sum_s part[s * stride + i] in order s = 0, 1, ... (double sums);
+// outt (nullable) receives the transpose, outt[c * rows + r].
 template <typename T>
 __global__ void reduce_splits_kernel(const T* __restrict__ part, int splits, int64_t stride,
                                      int64_t rows, int cols, int64_t ldo, T* __restrict__ out,
-                                     int64_t ldp) {
+                                     int64_t ldp, T* __restrict__ outt) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t r = idx / cols, cc = idx - r * cols;
   double s = 0.0;
   for (int p = 0; p < splits; ++p) s += (double)part[p * stride + r * ldp + cc];
   out[r * ldo + cc] = (T)s;
+  if (outt) outt[cc * rows + r] = (T)s;
 }
 
 // Same sums for few outputs and many splits (the k x k Grams): RS_SUB
@@ -392,7 +394,7 @@ constexpr int RS_OUT = 16, RS_SUB = 16;
 template <typename T>
 __global__ __launch_bounds__(RS_OUT * RS_SUB) void reduce_splits_wide_kernel(
     const T* __restrict__ part, int splits, int64_t stride, int64_t rows, int cols, int64_t ldo,
-    T* __restrict__ out, int64_t ldp) {
+    T* __restrict__ out, int64_t ldp, T* __restrict__ outt) {
   __shared__ double sh[RS_SUB][RS_OUT];
   const int o = threadIdx.x % RS_OUT, sub = threadIdx.x / RS_OUT;
   const int64_t idx = (int64_t)blockIdx.x * RS_OUT + o;
@@ -410,25 +412,26 @@ __global__ __launch_bounds__(RS_OUT * RS_SUB) void reduce_splits_wide_kernel(
 #pragma unroll
     for (int q = 0; q < RS_SUB; ++q) t += sh[q][o];
     out[r * ldo + cc] = (T)t;
+    if (outt) outt[cc * rows + r] = (T)t;
   }
 }
 
 template <typename T>
 hipError_t reduce_splits(const T* part, int splits, int64_t dsplit, int64_t M, int N,
-                         int64_t ldd, T* D, int64_t ldp, hipStream_t st) {
+                         int64_t ldd, T* D, int64_t ldp, hipStream_t st, T* Dt) {
   const int64_t total = M * N;
   if (total < 65536 && splits > 16)
     reduce_splits_wide_kernel<T><<<(unsigned)cdiv(total, RS_OUT), RS_OUT * RS_SUB, 0, st>>>(
-        part, splits, dsplit, M, N, ldd, D, ldp);
+        part, splits, dsplit, M, N, ldd, D, ldp, Dt);
   else
     reduce_splits_kernel<T><<<(unsigned)cdiv(total, 256), 256, 0, st>>>(part, splits, dsplit, M,
-                                                                         N, ldd, D, ldp);
+                                                                         N, ldd, D, ldp, Dt);
   return NMF_LAUNCH_CHECK();
 }
 template hipError_t reduce_splits<float>(const float*, int, int64_t, int64_t, int, int64_t, float*,
-                                         int64_t, hipStream_t);
+                                         int64_t, hipStream_t, float*);
 template hipError_t reduce_splits<double>(const double*, int, int64_t, int64_t, int, int64_t,
-                                          double*, int64_t, hipStream_t);
+                                          double*, int64_t, hipStream_t, double*);
 
 // ---------------------------------------------------------------------------
 // Host launchers
@@ -445,6 +448,15 @@ template <typename T> static constexpr Shape nn_shape(int NT) {
 template <typename T> static constexpr Shape tn_shape(int NT) {
   return sizeof(T) == 4 ? (NT <= 4 ? Shape{8, 4, 1} : Shape{4, 3, 1})
                         : Shape{NT <= 4 ? 4 : 2, 2, 2};
+}
+// A float TN product at ranks up to 64 whose streamed operand has under 2^28
+// elements (8192 x 4096 at k = 64 in the unrolled-gradient layers) has too
+// few 128-column waves to keep a pipeline per SIMD busy; there two waves per
+// SIMD of 64 columns each, with a shallower pipeline, took 5% less time per
+// product.
+constexpr Shape TN_SMALL = {4, 3, 2};
+template <typename T> static bool tn_small(int NT, int64_t M, int64_t K) {
+  return sizeof(T) == 4 && NT <= 4 && M * K < ((int64_t)1 << 28);
 }
 constexpr int WAVES = 4;  // waves per workgroup of the product kernels
 
@@ -521,6 +533,16 @@ static hipError_t tn_dispatch(const GemmArgs<T>& a, bool vx, bool small_m, int64
       return tn_launch<T, NT, 0, MWd, 2, 2, false>(a, vx, 1, splits, kchunk, D, ldd, dsplit, st);
     }
   }
+  if constexpr (sizeof(T) == 4 && NT + NR <= 4) {
+    if (tn_small<T>(NT + NR, a.M, a.K)) {
+      constexpr Shape sh = TN_SMALL;
+      if (a.yt)
+        return tn_launch<T, NT, NR, sh.mw, sh.stages, sh.wpe, true>(a, vx, WAVES, splits, kchunk,
+                                                                    D, ldd, dsplit, st);
+      return tn_launch<T, NT, NR, sh.mw, sh.stages, sh.wpe, false>(a, vx, WAVES, splits, kchunk,
+                                                                   D, ldd, dsplit, st);
+    }
+  }
   constexpr Shape sh = tn_shape<T>(NT + NR);
   if (a.yt)
     return tn_launch<T, NT, NR, sh.mw, sh.stages, sh.wpe, true>(a, vx, WAVES, splits, kchunk, D,
@@ -530,22 +552,24 @@ static hipError_t tn_dispatch(const GemmArgs<T>& a, bool vx, bool small_m, int64
 }
 
 template <typename T>
-static int64_t rows_per_wg(GemmKind kind, int NT) {
-  const Shape s = kind == GemmKind::NN ? nn_shape<T>(NT) : tn_shape<T>(NT);
+static int64_t rows_per_wg(GemmKind kind, int NT, int64_t M, int64_t K) {
+  const Shape s = kind == GemmKind::NN ? nn_shape<T>(NT)
+                  : tn_small<T>(NT, M, K) ? TN_SMALL
+                                          : tn_shape<T>(NT);
   return 16 * s.mw * WAVES;
 }
 
 template <typename T>
 int64_t gemm_auto_splits(GemmKind kind, int64_t M, int64_t N, int64_t K) {
   if (kind == GemmKind::TN_GRAM) return 0;
-  return auto_splits(cdiv(M, rows_per_wg<T>(kind, (int)(N / 16))), K, M * N * K, M * N);
+  return auto_splits(cdiv(M, rows_per_wg<T>(kind, (int)(N / 16), M, K)), K, M * N * K, M * N);
 }
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <typename T>
 hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a_in, int64_t splits, T* part,
-                    hipStream_t st) {
+                    hipStream_t st, int* nsplit) {
   constexpr int VEC = Tr<T>::VEC;
   GemmArgs<T> a = a_in;
   const int NT = (int)(a.N / 16);
@@ -560,8 +584,12 @@ hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a_in, int64_t splits, T* p
   if (a.yt && !(aligned16(a.Y) && a.ldy % VEC == 0)) return hipErrorInvalidValue;
   const bool small_m = kind == GemmKind::TN_GRAM;
   if (small_m) a.yt = false;
-  T* D = splits > 1 ? part : a.D;
-  const int64_t ldd = splits > 1 ? a.N : a.ldd;
+  // a transposed copy is written by the reduction, so a Gram that wants one
+  // goes through it even unsplit
+  if (a.Dt && !small_m) return hipErrorInvalidValue;
+  const bool reduce = splits > 1 || a.Dt;
+  T* D = reduce ? part : a.D;
+  const int64_t ldd = reduce ? a.N : a.ldd;
   const int64_t dsplit = a.M * a.N;
   // Rank remainder: float, not a Gram, and the valid columns end 1..4 past a
   // multiple of 16 (the rest of the padded tile is zero).
@@ -588,13 +616,16 @@ hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a_in, int64_t splits, T* p
     default: return hipErrorInvalidValue;
   }
 #undef NT_CASE
-  if (e != hipSuccess || splits == 1) return e;
-  return reduce_splits<T>(part, (int)splits, dsplit, a.M, (int)a.N, a.ldd, a.D, a.N, st);
+  if (nsplit) *nsplit = (int)splits;
+  if (e != hipSuccess || !reduce || nsplit) return e;
+  return reduce_splits<T>(part, (int)splits, dsplit, a.M, (int)a.N, a.ldd, a.D, a.N, st, a.Dt);
 }
 
 template int64_t gemm_auto_splits<float>(GemmKind, int64_t, int64_t, int64_t);
 template int64_t gemm_auto_splits<double>(GemmKind, int64_t, int64_t, int64_t);
-template hipError_t gemm_run<float>(GemmKind, const GemmArgs<float>&, int64_t, float*, hipStream_t);
-template hipError_t gemm_run<double>(GemmKind, const GemmArgs<double>&, int64_t, double*, hipStream_t);
+template hipError_t gemm_run<float>(GemmKind, const GemmArgs<float>&, int64_t, float*, hipStream_t,
+                                    int*);
+template hipError_t gemm_run<double>(GemmKind, const GemmArgs<double>&, int64_t, double*,
+                                     hipStream_t, int*);
 
 }  // namespace nmfk

@@ -21,6 +21,7 @@ template <typename T> struct GemmArgs {
   int64_t M, N, K;
   bool yt;
   int nvalid;  // output columns that matter (0: all N); columns >= nvalid may be 0
+  T* Dt;       // nullable: also receives D transposed (Dt[j * M + i]; Grams only)
 };
 
 // `part` must hold splits * M * N elements when splits > 1. splits <= 0 picks
@@ -28,16 +29,30 @@ template <typename T> struct GemmArgs {
 // MAX_PRODUCT_SPLITS for the products: 32, so that products with few output
 // rows still fill the chip).
 constexpr int64_t MAX_PRODUCT_SPLITS = 32;
+// With nsplit set, a split product is not summed: the slabs stay in part
+// (slab s at part + s M N, ld N) and *nsplit receives their count, for a
+// consumer that adds them itself (Split below); *nsplit = 1 means D holds
+// the product.
 template <typename T>
 hipError_t gemm_run(GemmKind kind, const GemmArgs<T>& a, int64_t splits, T* part,
-                    hipStream_t st);
+                    hipStream_t st, int* nsplit = nullptr);
+
+// A product handed over as n slabs of rows x KP (slab q at p + q stride),
+// whose entries the consumer sums in slab order in double and rounds once,
+// as reduce_splits does (n = 1: p is the product itself). p == nullptr: no
+// product.
+template <typename T> struct Split {
+  const T* p;
+  int n;
+  int64_t stride;
+};
 template <typename T>
 int64_t gemm_auto_splits(GemmKind kind, int64_t M, int64_t N, int64_t K);
 // D[i][j] (ld ldd) = sum over s of part[s * dsplit + i * ldp + j], in the
 // order s = 0, 1, ... with double sums, for i < M, j < N.
 template <typename T>
 hipError_t reduce_splits(const T* part, int splits, int64_t dsplit, int64_t M, int N,
-                         int64_t ldd, T* D, int64_t ldp, hipStream_t st);
+                         int64_t ldd, T* D, int64_t ldp, hipStream_t st, T* Dt = nullptr);
 
 // Reduced-precision products: D (M x N float, ld ldd) = X Y^T for X (M x K)
 // and Y (N x K) stored as bfloat16 bits (uint16_t) or FP8 E4M3 bits
@@ -63,9 +78,12 @@ hipError_t pack_fp8_t(const float* F, int64_t rows, int KP, uint8_t* Ft, int64_t
 
 // Local updates on rows x KP row-major factors (leading dimension KP); k is
 // the true rank, entries k..KP-1 are zero padding and stay zero.
+// mu_rows writes the updated rows of X to Xn (Xn == X: in place) and, when
+// Xt is set (KP <= 64), their transpose Xt[i * rows + r] as well; P is summed
+// from its slabs, and Pout (nullable) receives the sum.
 template <typename T>
-hipError_t mu_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, T eps,
-                   hipStream_t st);
+hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
+                   T* Xt, T* Pout, hipStream_t st);
 template <typename T>
 hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
                      hipStream_t st);
@@ -154,12 +172,16 @@ hipError_t csr_residual_sq(const int64_t* rowptr, const int32_t* colidx, const f
 hipError_t csr_sumsq(const float* vals, int64_t nnz, double* partial, int64_t np,
                      hipStream_t st);
 // Reverse mode through unrolled multiplicative updates (row layout, KP in
-// {16, 32, 48, 64}). For Xn = X * N / (X G + eps): gN = gXn * X / D,
-// gD = -gXn * Xn / D, gX = gXn * N / D + gD G^T (D = X G + eps).
+// {16, 32, 48, 64}). For Xn = X * N / (X G + eps), with the gradient reaching
+// Xn taken as g = gXn + Y + Xn (M + M^T) (Y and M nullable: the terms that
+// the next half-step's product and Gram pass back): gN = g * X / D,
+// gD = -g * Xn / D, gX = g * N / D + gD G^T (D = X G + eps). Gt and Mt are
+// the transposes of G and M (as the Gram's reduction writes them). gNt
+// (nullable) receives gN transposed, gNt[i * rows + r].
 template <typename T>
-hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* gXn,
-                           int64_t rows, int k, int KP, T eps, T* gN, T* gD, T* gX,
-                           hipStream_t st);
+hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* Gt,
+                           const T* gXn, Split<T> Y, const T* M, const T* Mt, int64_t rows, int k,
+                           int KP, T eps, T* gN, T* gNt, T* gD, T* gX, hipStream_t st);
 // Reverse of the HALS sweep on rows x KP rows (KP in {16, 32, 48, 64}): from
 // the sweep's output Xnew, the Gram G and gXnew = dL/dXnew, writes
 // gXold = dL/dX (input) and Delta = dL/dP (one delta per row and column).
@@ -193,10 +215,13 @@ hipError_t symmetrize(const T* G, int KP, T* M, hipStream_t st);
 // Y += X (n elements).
 template <typename T>
 hipError_t add_to(T* Y, const T* X, int64_t n, hipStream_t st);
-// D (m x n, ldd) += X1 Y1^T + X2 Y2^T, X* m x KP, Y* n x KP (X2 may be null).
+// D (m x n, ldd) = beta D + sum_{t < L} (X1_t Y1_t^T + X2_t Y2_t^T), beta 0 or
+// 1, with X*_t = X* + t m KP (m x KP) and Y*_t = Y* + t n KP (n x KP): the L
+// rank-2KP terms of one checkpoint segment in one pass over D (X2 may be
+// null).
 template <typename T>
 hipError_t rank_update(T* D, int64_t ldd, int64_t m, int64_t n, const T* X1, const T* Y1,
-                       const T* X2, const T* Y2, int KP, hipStream_t st);
+                       const T* X2, const T* Y2, int KP, int L, int beta, hipStream_t st);
 
 // Input checks: sets *flag (device int) nonzero on a bad entry.
 template <typename T>

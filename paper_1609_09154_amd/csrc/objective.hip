@@ -4,6 +4,7 @@
 // double. Each workgroup writes one double; finish_relerr sums them in a
 // fixed order, so the value is reproducible run to run.
 #include "common.h"
+#include "rowtile.h"
 #include "kernels.h"
 
 namespace nmfk {
@@ -146,12 +147,9 @@ __global__ __launch_bounds__(256) void pgrad_sq_kernel(const T* __restrict__ X,
   constexpr int XLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
   __shared__ __attribute__((aligned(16))) T Xs[PG_ROWS * XLD];
-  for (int e = threadIdx.x; e < KP * KP; e += 256) Gs[e] = G[e];
   const int64_t rb = (int64_t)blockIdx.x * PG_ROWS;
-  for (int e = threadIdx.x; e < PG_ROWS * KP; e += 256) {
-    const int q = e / KP, j = e % KP;
-    Xs[q * XLD + j] = rb + q < rows ? X[(rb + q) * KP + j] : T(0);
-  }
+  stage_square<T, KP, 256>(Gs, G, nullptr);
+  stage_rows<T, KP, PG_ROWS, XLD, 256>(Xs, X, rb, rows);
   __syncthreads();
   const int lr = threadIdx.x / PG_TPR;
   const int64_t r = rb + lr;

@@ -13,6 +13,7 @@
 // Padding entries k..KP-1 of x are zero on entry and stay zero.
 #include "common.h"
 #include "grid.h"
+#include "rowtile.h"
 #include "kernels.h"
 
 namespace nmfk {
@@ -34,10 +35,7 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(T* __restrict__ X,
                                                             int64_t rows, int k) {
   constexpr int R = KP / TPR, ROWS = 256 / TPR;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
-  for (int e = threadIdx.x; e < KP * KP; e += 256) {
-    const int i = e / KP, j = e - i * KP;
-    Gs[e] = G[j * KP + i];
-  }
+  stage_square_t<T, KP, 256>(Gs, G);
   __syncthreads();
   const int sub = threadIdx.x % TPR;
   const int64_t r = (int64_t)blockIdx.x * ROWS + threadIdx.x / TPR;
@@ -73,9 +71,13 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(T* __restrict__ X,
 
 // MU with several threads per row: the KP outputs of a row are split over
 // TPR threads of RPT outputs each, and a block of 256 threads covers 256 / TPR
-// rows. G and the block's rows of x are staged in LDS first (so the in-place
-// update of X reads nothing a lane has already written) and read with
-// 16-byte loads.
+// rows. G and the block's rows of x are staged in LDS first (so an in-place
+// update, Xn = X, reads nothing a lane has already written) and read with
+// 16-byte loads. Xn receives every entry of the new rows (entries k..KP-1
+// copied from X); Xt (nullable) receives their transpose, Xt[i * rows + r],
+// the layout the next product reads the factor in. P arrives as the product's
+// slabs, summed here in slab order in double (Pout, nullable, receives the
+// sum), so that a split product needs no pass of its own to add them.
 template <int KP> struct RowSplit {
   static constexpr int TPR = KP == 48 ? 4 : KP / 8;
   static constexpr int RPT = KP / TPR;
@@ -83,27 +85,34 @@ template <int KP> struct RowSplit {
 };
 
 template <typename T, int KP>
-__global__ __launch_bounds__(256) void mu_rows_tpr_kernel(T* __restrict__ X,
-                                                          const T* __restrict__ P,
+__global__ __launch_bounds__(256) void mu_rows_tpr_kernel(const T* X, T* Xn, Split<T> P,
                                                           const T* __restrict__ G, int64_t rows,
-                                                          int k, T eps) {
+                                                          int k, T eps, T* __restrict__ Xt,
+                                                          T* __restrict__ Pout) {
   constexpr int TPR = RowSplit<KP>::TPR, RPT = RowSplit<KP>::RPT, ROWS = RowSplit<KP>::ROWS;
   constexpr int VEC = Tr<T>::VEC;
   static_assert(RPT % VEC == 0, "16-byte reads of G");
   constexpr int XLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
   __shared__ __attribute__((aligned(16))) T Xs[ROWS * XLD];
-  for (int e = threadIdx.x; e < KP * KP; e += 256) Gs[e] = G[e];
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
-  for (int e = threadIdx.x; e < ROWS * KP; e += 256) {
-    const int lr = e / KP, j = e % KP;
-    Xs[lr * XLD + j] = rb + lr < rows ? X[(rb + lr) * KP + j] : T(0);
-  }
-  __syncthreads();
   const int lr = threadIdx.x / TPR;
   const int64_t r = rb + lr;
-  if (r >= rows) return;  // no barrier below
+  const bool live = r < rows;
   const int i0 = (threadIdx.x % TPR) * RPT;
+  // the staging loads, then the row's entries of P (independent of them),
+  // all in flight together
+  SquareStage<T, KP, 256> gst;
+  RowStage<T, KP, ROWS, XLD, 256> xst;
+  gst.load(G, nullptr);
+  xst.load(X, rb, rows);
+  double ps[RPT];
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) ps[ii] = 0.0;
+  if (live) slab_sum<T, RPT>(P.p + r * KP + i0, P.n, P.stride, ps);
+  gst.store(Gs);
+  xst.store(Xs, rb, rows);
+  __syncthreads();
   const T* xs = &Xs[lr * XLD];
   T d[RPT];
 #pragma unroll
@@ -118,13 +127,25 @@ __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(T* __restrict__ X,
       for (int w = 0; w < VEC; ++w) d[q * VEC + w] = fma(xj, v.v[w], d[q * VEC + w]);
     }
   }
-  const T* pr = P + r * KP;
-  T* xr = X + r * KP;
+  T out[RPT];
 #pragma unroll
-  for (int ii = 0; ii < RPT; ++ii) {
-    const int i = i0 + ii;
-    if (i < k) xr[i] = xs[i] * pr[i] / (d[ii] + eps);
+  for (int ii = 0; ii < RPT; ++ii) out[ii] = xs[i0 + ii];
+  if (live) {
+#pragma unroll
+    for (int ii = 0; ii < RPT; ++ii) {
+      const int i = i0 + ii;
+      const T pv = (T)ps[ii];
+      if (Pout) Pout[r * KP + i] = pv;
+      if (i < k) out[ii] = xs[i] * pv / (d[ii] + eps);
+      Xn[r * KP + i] = out[ii];
+    }
   }
+  if (Xt == nullptr) return;  // uniform over the block
+  __syncthreads();            // every read of the staged rows is done
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) Xs[lr * XLD + i0 + ii] = out[ii];
+  __syncthreads();
+  store_rows_transposed<T, KP, ROWS, XLD>(Xs, rb, rows, Xt);
 }
 
 // MU at ranks above 64: each thread's row kept in LDS (column tid of a
@@ -133,11 +154,10 @@ __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(T* __restrict__ X,
 // read along j with uniform loads.
 constexpr int LDS_ROWS = 64;
 template <typename T>
-__global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(T* __restrict__ X,
-                                                               const T* __restrict__ P,
+__global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(const T* X, T* Xn, Split<T> P,
                                                                const T* __restrict__ G,
                                                                int64_t rows, int k, int KP,
-                                                               T eps) {
+                                                               T eps, T* __restrict__ Pout) {
   __shared__ T xs[NMF_MAX_K * LDS_ROWS];
   const int t = threadIdx.x;
   const int64_t r = (int64_t)blockIdx.x * LDS_ROWS + t;
@@ -146,7 +166,15 @@ __global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(T* __restrict__ X
   for (int i = 0; i < k; ++i) {
     T d = T(0);
     for (int j = 0; j < k; ++j) d = fma(xs[j * LDS_ROWS + t], G[i * KP + j], d);
-    X[r * KP + i] = xs[i * LDS_ROWS + t] * P[r * KP + i] / (d + eps);
+    double ps = 0.0;
+    for (int q = 0; q < P.n; ++q) ps += (double)P.p[q * P.stride + r * KP + i];
+    const T pv = (T)ps;
+    if (Pout) Pout[r * KP + i] = pv;
+    Xn[r * KP + i] = xs[i * LDS_ROWS + t] * pv / (d + eps);
+  }
+  for (int i = k; i < KP; ++i) {
+    if (Pout) Pout[r * KP + i] = T(0);
+    Xn[r * KP + i] = xs[i * LDS_ROWS + t];
   }
 }
 
@@ -162,13 +190,14 @@ __global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(T* __restrict__ X
   }
 
 template <typename T>
-hipError_t mu_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP, T eps,
-                   hipStream_t st) {
+hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
+                   T* Xt, T* Pout, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
+  if ((Xt && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
   KP_SWITCH(KP, (mu_rows_tpr_kernel<T, KPc><<<(unsigned)cdiv(rows, RowSplit<KPc>::ROWS), 256,
-                                               0, st>>>(X, P, G, rows, k, eps)),
+                                               0, st>>>(X, Xn, P, G, rows, k, eps, Xt, Pout)),
             (mu_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
-                X, P, G, rows, k, KP, eps)));
+                X, Xn, P, G, rows, k, KP, eps, Pout)));
   return NMF_LAUNCH_CHECK();
 }
 
@@ -475,7 +504,8 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
 }
 
 #define INST(T)                                                                             \
-  template hipError_t mu_rows<T>(T*, const T*, const T*, int64_t, int, int, T, hipStream_t); \
+  template hipError_t mu_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T, T*, \
+                                 T*, hipStream_t); \
   template hipError_t hals_rows<T>(T*, const T*, const T*, int64_t, int, int, hipStream_t);  \
   template hipError_t hals_normalize<T>(T*, int64_t, T*, int64_t, T*, T*, int, int,         \
                                         hipStream_t);                                       \
