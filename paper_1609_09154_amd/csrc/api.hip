@@ -264,7 +264,8 @@ nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, i
   if (algo == NMF_MU)
     HIP_TRY(nmfk::mu_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, (T)o->eps_mu,
                              nullptr, nullptr, st));
-  else if (algo == NMF_HALS) HIP_TRY(nmfk::hals_rows<T>(X, Pm, G, rows, k, KP, st));
+  else if (algo == NMF_HALS)
+    HIP_TRY(nmfk::hals_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, nullptr, st));
   else {
     const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
     // the incoming X (the current iterate) starts each right-hand side's pivoting
@@ -598,7 +599,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
     if (o->algo == NMF_HALS) {
       tm.mark(PH_LUC);
-      HIP_TRY(nmfk::hals_normalize<T>(w.W, m, w.Ht, n, w.S, w.norms, k, KP, st));
+      HIP_TRY(nmfk::hals_normalize<T>(w.W, w.W, m, w.Ht, w.Ht, n, w.S, w.norms, k, KP, st));
     }
     if (tW) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
     tm.mark(PH_MM_T);
@@ -1218,7 +1219,7 @@ nmf_status normalize_impl(nmf_ctx* ctx, int64_t m, int64_t n, int k, T* W, T* Ht
   HIP_TRY(nmfk::pad_rows<T>(W, m, k, Wp, KP, st));
   HIP_TRY(nmfk::pad_rows<T>(Ht, n, k, Hp, KP, st));
   if ((s = gram<T>(ctx, Wp, m, KP, Sp, at<T>(ctx, oP))) != NMF_OK) return s;
-  HIP_TRY(nmfk::hals_normalize<T>(Wp, m, Hp, n, Sp, Np, k, KP, st));
+  HIP_TRY(nmfk::hals_normalize<T>(Wp, Wp, m, Hp, Hp, n, Sp, Np, k, KP, st));
   HIP_TRY(nmfk::unpad_rows<T>(Wp, m, k, KP, W, st));
   HIP_TRY(nmfk::unpad_rows<T>(Hp, n, k, KP, Ht, st));
   if (S) HIP_TRY(nmfk::unpad_rows<T>(Sp, k, k, KP, S, st));
@@ -1739,24 +1740,27 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
 // the order nmf_dense runs it: Q = H H^T, P = A H^T, the W sweep, S = W^T W,
 // the normalisation (W, H and S rescaled; norms into nrm), R = A^T W, the H
 // sweep. Wp and Hc (nullable) receive W after the sweep and H^T after the
-// rescaling, which the backward pass needs.
+// rescaling, which the backward pass needs; every step writes its output
+// where the next one reads it, so nothing is copied. *ft: on entry, whether
+// w.Ft holds Ht's transposed copy; on return, whether it holds Htn's.
 template <typename T>
 nmf_status hals_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
                           const T* W, const T* Ht, T* Wn, T* Htn, T* Wp, T* Hc, T* nrm, T* Q,
-                          T* S, MuWork<T>& w) {
+                          T* S, MuWork<T>& w, bool* ft) {
   hipStream_t st = ctx->stream;
   nmf_status s;
+  const bool tH = rows_transposable<T>(n, KP);
+  nmfk::Split<T> sp;
+  T* Wsw = Wp ? Wp : Wn;    // the W sweep's output
+  T* Hsc = Hc ? Hc : Htn;   // H^T after the rescaling
   if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part)) != NMF_OK) return s;
-  if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, w.P, w)) != NMF_OK) return s;
-  if (Wn != W) HIP_TRY(hipMemcpyAsync(Wn, W, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(nmfk::hals_rows<T>(Wn, w.P, Q, m, k, KP, st));
-  if (Wp) HIP_TRY(hipMemcpyAsync(Wp, Wn, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
-  if ((s = gram<T>(ctx, Wn, m, KP, S, w.part)) != NMF_OK) return s;
-  if (Htn != Ht) HIP_TRY(hipMemcpyAsync(Htn, Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(nmfk::hals_normalize<T>(Wn, m, Htn, n, S, nrm, k, KP, st));
-  if (Hc) HIP_TRY(hipMemcpyAsync(Hc, Htn, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
-  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, w.R, w)) != NMF_OK) return s;
-  HIP_TRY(nmfk::hals_rows<T>(Htn, w.R, S, n, k, KP, st));
+  if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, w.P, w, *ft, &sp)) != NMF_OK) return s;
+  HIP_TRY(nmfk::hals_rows<T>(W, Wsw, sp, Q, m, k, KP, nullptr, st));
+  if ((s = gram<T>(ctx, Wsw, m, KP, S, w.part)) != NMF_OK) return s;
+  HIP_TRY(nmfk::hals_normalize<T>(Wsw, Wn, m, Ht, Hsc, n, S, nrm, k, KP, st));
+  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, w.R, w, false, &sp)) != NMF_OK) return s;
+  HIP_TRY(nmfk::hals_rows<T>(Hsc, Htn, sp, S, n, k, KP, tH ? w.Ft : nullptr, st));
+  *ft = tH;
   return NMF_OK;
 }
 
@@ -1778,6 +1782,7 @@ nmf_status hals_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int
   Prob<T> pb;
   if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
   const int64_t slot = (m + n) * KP;
+  bool ft = false;
   for (int t = 0; t < iters; ++t) {
     if (ckpt && t % every == 0) {
       T* c = ckpt + (int64_t)(t / every) * slot;
@@ -1785,7 +1790,7 @@ nmf_status hals_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int
       HIP_TRY(hipMemcpyAsync(c + m * KP, w.Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
     }
     s = hals_iteration<T>(ctx, pb, m, n, k, KP, w.W, w.Ht, w.W, w.Ht, nullptr, nullptr, nrm,
-                          w.Q, w.S, w);
+                          w.Q, w.S, w, &ft);
     if (s != NMF_OK) return s;
   }
   HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
@@ -1840,6 +1845,8 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   T *tmp = at<T>(ctx, otmp), *T1 = at<T>(ctx, oT1), *T2 = at<T>(ctx, oT2), *M = at<T>(ctx, oM);
   double *dots = at<double>(ctx, odots), *dpart = at<double>(ctx, odpart);
   hipStream_t st = ctx->stream;
+  const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
+  nmfk::Split<T> yp{nullptr, 0, 0};
   HIP_TRY(nmfk::pad_rows<T>(gWT, m, k, gW, KP, st));
   HIP_TRY(nmfk::transpose_in<T>(gHT, k, n, gH, KP, st));
   if (gA && iters == 0) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
@@ -1858,10 +1865,12 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
     HIP_TRY(hipMemcpyAsync(Ws, ckpt + j * slot, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(Hs, ckpt + j * slot + m * KP, sizeof(T) * n * KP,
                            hipMemcpyDeviceToDevice, st));
+    bool ft = false;
     for (int i = 0; i < L; ++i) {
       s = hals_iteration<T>(ctx, pb, m, n, k, KP, Ws + i * m * KP, Hs + i * n * KP,
                             Ws + (i + 1) * m * KP, Hs + (i + 1) * n * KP, Wps + i * m * KP,
-                            Hcs + i * n * KP, Ns + i * KP, Qs + i * KP * KP, Ss + i * KP * KP, w);
+                            Hcs + i * n * KP, Ns + i * KP, Qs + i * KP * KP, Ss + i * KP * KP, w,
+                            &ft);
       if (s != NMF_OK) return s;
     }
     for (int i = L - 1; i >= 0; --i) {
@@ -1874,26 +1883,28 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
       T* gR = gRs + i * n * KP;
       T* gP = gPs + i * m * KP;
       // H sweep on the rows of Hc with R = A^T Wn and S = Wn^T Wn
-      HIP_TRY(nmfk::hals_adjoint_rows<T>(H1s, Ss + i * KP * KP, gH, n, k, KP, gHc, gR, st));
+      HIP_TRY(nmfk::hals_adjoint_rows<T>(H1s, Ss + i * KP * KP, gH, n, k, KP, gHc, gR,
+                                         tH ? w.Ft : nullptr, st));
       if ((s = tn(H1s, gR, n, T1)) != NMF_OK) return s;
       if ((s = tn(Hc, gR, n, T2)) != NMF_OK) return s;
       HIP_TRY(nmfk::hals_gram_grad<T>(T1, T2, KP, M, st));
-      if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w)) != NMF_OK) return s;
-      HIP_TRY(nmfk::add_to<T>(gW, tmp, m * KP, st));
-      HIP_TRY(nmfk::rowmm_add<T>(W1s, M, m, k, KP, gW, st));
+      // gW += A gR (the product's slabs) + Wn M
+      if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w, tH, &yp)) != NMF_OK) return s;
+      HIP_TRY(nmfk::rowmm_add<T>(W1s, M, m, k, KP, gW, st, yp));
       // normalisation: Wn = W' / s, Hc = s H
       HIP_TRY(nmfk::coldot<T>(gW, W1s, m, KP, dpart, dots, st));
       HIP_TRY(nmfk::coldot<T>(gHc, H0s, n, KP, dpart, dots + KP, st));
       HIP_TRY(nmfk::hals_norm_adjoint<T>(gW, W1s, m, gHc, n, Ns + i * KP, dots, k, KP, gWp, gH2,
                                          st));
       // W sweep with P = A H^T and Q = H H^T
-      HIP_TRY(nmfk::hals_adjoint_rows<T>(Wp, Qs + i * KP * KP, gWp, m, k, KP, gW2, gP, st));
+      HIP_TRY(nmfk::hals_adjoint_rows<T>(Wp, Qs + i * KP * KP, gWp, m, k, KP, gW2, gP,
+                                         tW ? w.Ft : nullptr, st));
       if ((s = tn(Wp, gP, m, T1)) != NMF_OK) return s;
       if ((s = tn(W0s, gP, m, T2)) != NMF_OK) return s;
       HIP_TRY(nmfk::hals_gram_grad<T>(T1, T2, KP, M, st));
-      if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w)) != NMF_OK) return s;
-      HIP_TRY(nmfk::add_to<T>(gH2, tmp, n * KP, st));
-      HIP_TRY(nmfk::rowmm_add<T>(H0s, M, n, k, KP, gH2, st));
+      // gH += A^T gP (the product's slabs) + H M
+      if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w, tW, &yp)) != NMF_OK) return s;
+      HIP_TRY(nmfk::rowmm_add<T>(H0s, M, n, k, KP, gH2, st, yp));
       std::swap(gW, gW2);
       std::swap(gH, gH2);
     }

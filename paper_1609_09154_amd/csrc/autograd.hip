@@ -196,24 +196,35 @@ __global__ __launch_bounds__(256) void mu_adjoint_rows_kernel(
   if (gNt) store_rows_transposed<T, KP, ROWS, DLD>(Xs, rb, rows, gNt);
 }
 
-// Out[r] += X[r] M for rows x KP X and KP x KP M.
+// Out[r] = (Out[r] + Y[r]) + X[r] M for rows x KP X and KP x KP M, columns
+// < k; Y (nullable) arrives as a product's slabs, summed in slab order in
+// double.
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void rowmm_add_kernel(const T* __restrict__ X,
-                                                        const T* __restrict__ M, int64_t rows,
-                                                        int k, T* __restrict__ Out) {
+                                                        const T* __restrict__ M, Split<T> Y,
+                                                        int64_t rows, int k, T* __restrict__ Out) {
   constexpr int TPR = AdjSplit<KP>::TPR, RPT = AdjSplit<KP>::RPT, ROWS = AdjSplit<KP>::ROWS;
   constexpr int VEC = Tr<T>::VEC;
   constexpr int XLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Ms[KP * KP];
   __shared__ __attribute__((aligned(16))) T Xs[ROWS * XLD];
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
-  stage_square<T, KP, 256>(Ms, M, nullptr);
-  stage_rows<T, KP, ROWS, XLD, 256>(Xs, X, rb, rows);
-  __syncthreads();
   const int lr = threadIdx.x / TPR;
   const int64_t r = rb + lr;
-  if (r >= rows) return;
+  const bool live = r < rows;
   const int i0 = (threadIdx.x % TPR) * RPT;
+  SquareStage<T, KP, 256> mst;
+  RowStage<T, KP, ROWS, XLD, 256> xst;
+  mst.load(M, nullptr);
+  xst.load(X, rb, rows);
+  double ys[RPT];
+#pragma unroll
+  for (int ii = 0; ii < RPT; ++ii) ys[ii] = 0.0;
+  if (live && Y.p) slab_sum<T, RPT>(Y.p + r * KP + i0, Y.n, Y.stride, ys);
+  mst.store(Ms);
+  xst.store(Xs, rb, rows);
+  __syncthreads();
+  if (!live) return;
   const T* xs = &Xs[lr * XLD];
   T s[RPT];
 #pragma unroll
@@ -230,7 +241,11 @@ __global__ __launch_bounds__(256) void rowmm_add_kernel(const T* __restrict__ X,
   }
 #pragma unroll
   for (int ii = 0; ii < RPT; ++ii)
-    if (i0 + ii < k) Out[r * KP + i0 + ii] += s[ii];
+    if (i0 + ii < k) {
+      T o = Out[r * KP + i0 + ii];
+      if (Y.p) o += (T)ys[ii];
+      Out[r * KP + i0 + ii] = o + s[ii];
+    }
 }
 
 // M = G + G^T (KP x KP).
@@ -421,15 +436,20 @@ template <int KP> struct HalsAdjGroup {
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
     const T* __restrict__ Xnew, const T* __restrict__ G, const T* __restrict__ gXnew,
-    int64_t rows, int k, T* __restrict__ gXold, T* __restrict__ Delta) {
+    int64_t rows, int k, T* __restrict__ gXold, T* __restrict__ Delta, T* __restrict__ Dt) {
   constexpr int TPR = HalsAdjGroup<KP>::TPR, R = HalsAdjGroup<KP>::R;
   constexpr int ROWS = HalsAdjGroup<KP>::ROWS;
+  constexpr int VEC = Tr<T>::VEC;
+  constexpr int DLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
-  stage_square_t<T, KP, 256>(Gs, G);
-  __syncthreads();
+  __shared__ __attribute__((aligned(16))) T Ds[ROWS * DLD];
   const int sub = threadIdx.x % TPR;
-  const int64_t r = (int64_t)blockIdx.x * ROWS + threadIdx.x / TPR;
+  const int64_t rb = (int64_t)blockIdx.x * ROWS;
+  const int64_t r = rb + threadIdx.x / TPR;
   const int64_t rr = r < rows ? r : rows - 1;
+  // G's loads and the row's values, in flight together
+  SquareStage<T, KP, 256> gst;
+  gst.load(G, nullptr);
   T g[R], d[R];
   unsigned mask = 0;
 #pragma unroll
@@ -438,6 +458,8 @@ __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
     mask |= (Xnew[rr * KP + sub * R + q] > T(0) ? 1u : 0u) << q;
     d[q] = T(0);
   }
+  gst.store_t(Gs);
+  __syncthreads();
 #pragma unroll
   for (int i = KP - 1; i >= 0; --i) {
     if (i < k) {
@@ -463,6 +485,12 @@ __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
       Delta[r * KP + sub * R + q] = d[q];
     }
   }
+  if (Dt == nullptr) return;  // uniform over the block
+  // Delta transposed (Dt[i * rows + r]), the layout the next product reads
+#pragma unroll
+  for (int q = 0; q < R; ++q) Ds[(threadIdx.x / TPR) * DLD + sub * R + q] = d[q];
+  __syncthreads();
+  store_rows_transposed<T, KP, ROWS, DLD>(Ds, rb, rows, Dt);
 }
 
 // M = S + S^T with S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (KP x KP): the
@@ -582,12 +610,13 @@ hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, cons
 
 template <typename T>
 hipError_t rowmm_add(const T* X, const T* M, int64_t rows, int k, int KP, T* Out,
-                     hipStream_t st) {
+                     hipStream_t st, Split<T> Y) {
   if (rows <= 0) return hipSuccess;
+  if (Y.p && Y.n < 1) return hipErrorInvalidValue;
   switch (KP) {
 #define CASE(K)                                                                              \
   case K:                                                                                    \
-    rowmm_add_kernel<T, K><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0, st>>>(X, M,     \
+    rowmm_add_kernel<T, K><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0, st>>>(X, M, Y,  \
                                                                                   rows, k,   \
                                                                                   Out);      \
     break;
@@ -626,13 +655,13 @@ hipError_t rank_update(T* D, int64_t ldd, int64_t m, int64_t n, const T* X1, con
 
 template <typename T>
 hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t rows, int k,
-                             int KP, T* gXold, T* Delta, hipStream_t st) {
+                             int KP, T* gXold, T* Delta, T* Dt, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   switch (KP) {
 #define CASE(K)                                                                               \
   case K:                                                                                     \
     hals_adjoint_rows_kernel<T, K><<<(unsigned)cdiv(rows, HalsAdjGroup<K>::ROWS), 256, 0,      \
-                                     st>>>(Xnew, G, gXnew, rows, k, gXold, Delta);            \
+                                     st>>>(Xnew, G, gXnew, rows, k, gXold, Delta, Dt);        \
     break;
     CASE(16) CASE(32) CASE(48) CASE(64)
 #undef CASE
@@ -676,7 +705,7 @@ hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc,
 
 #define INST(T)                                                                               \
   template hipError_t hals_adjoint_rows<T>(const T*, const T*, const T*, int64_t, int, int,   \
-                                           T*, T*, hipStream_t);                              \
+                                           T*, T*, T*, hipStream_t);                          \
   template hipError_t hals_gram_grad<T>(const T*, const T*, int, T*, hipStream_t);            \
   template hipError_t coldot<T>(const T*, const T*, int64_t, int, double*, double*,           \
                                 hipStream_t);                                                 \
@@ -686,7 +715,8 @@ hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc,
   template hipError_t mu_adjoint_rows<T>(const T*, const T*, const T*, const T*, const T*,    \
                                          const T*, Split<T>, const T*, const T*, int64_t, int, \
                                          int, T, T*, T*, T*, T*, hipStream_t);                 \
-  template hipError_t rowmm_add<T>(const T*, const T*, int64_t, int, int, T*, hipStream_t);   \
+  template hipError_t rowmm_add<T>(const T*, const T*, int64_t, int, int, T*, hipStream_t,    \
+                                   Split<T>);                                                \
   template hipError_t symmetrize<T>(const T*, int, T*, hipStream_t);                          \
   template hipError_t add_to<T>(T*, const T*, int64_t, hipStream_t);                          \
   template hipError_t rank_update<T>(T*, int64_t, int64_t, int64_t, const T*, const T*,       \

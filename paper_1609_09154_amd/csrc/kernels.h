@@ -85,14 +85,14 @@ template <typename T>
 hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
                    T* Xt, T* Pout, hipStream_t st);
 template <typename T>
-hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
-                     hipStream_t st);
+hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP,
+                     T* Xt, hipStream_t st);
 
 // HALS normalisation: s_i = sqrt(S[i][i]); W[:, i] /= s_i, Ht[:, i] *= s_i and
 // S[i][j] /= s_i s_j for s_i > 0. norms (nullable) receives s.
 template <typename T>
-hipError_t hals_normalize(T* W, int64_t m, T* Ht, int64_t n, T* S, T* norms, int k, int KP,
-                          hipStream_t st);
+hipError_t hals_normalize(const T* W, T* Wn, int64_t m, const T* Ht, T* Htn, int64_t n, T* S,
+                          T* norms, int k, int KP, hipStream_t st);
 
 // Copies between the caller's layouts (ld = k) and the padded row layout.
 template <typename T>
@@ -184,10 +184,11 @@ hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, cons
                            int KP, T eps, T* gN, T* gNt, T* gD, T* gX, hipStream_t st);
 // Reverse of the HALS sweep on rows x KP rows (KP in {16, 32, 48, 64}): from
 // the sweep's output Xnew, the Gram G and gXnew = dL/dXnew, writes
-// gXold = dL/dX (input) and Delta = dL/dP (one delta per row and column).
+// gXold = dL/dX (input) and Delta = dL/dP (one delta per row and column);
+// Dt (nullable) receives Delta transposed, Dt[i * rows + r].
 template <typename T>
 hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t rows, int k,
-                             int KP, T* gXold, T* Delta, hipStream_t st);
+                             int KP, T* gXold, T* Delta, T* Dt, hipStream_t st);
 // M = S + S^T, S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (the sweep's Gram
 // gradient from T1 = Xnew^T Delta and T2 = Xold^T Delta).
 template <typename T>
@@ -205,10 +206,11 @@ template <typename T>
 hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc, int64_t n,
                              const T* norms, const double* dots, int k, int KP, T* gWp, T* gHt,
                              hipStream_t st);
-// Out[r] += X[r] M (M KP x KP), columns < k.
+// Out[r] = (Out[r] + Y[r]) + X[r] M (M KP x KP), columns < k; Y (a product's
+// slabs) may be empty.
 template <typename T>
 hipError_t rowmm_add(const T* X, const T* M, int64_t rows, int k, int KP, T* Out,
-                     hipStream_t st);
+                     hipStream_t st, Split<T> Y = Split<T>{nullptr, 0, 0});
 // M = G + G^T.
 template <typename T>
 hipError_t symmetrize(const T* G, int KP, T* M, hipStream_t st);

@@ -105,35 +105,54 @@ __device__ __forceinline__ void stage_rows(T* dst, const T* __restrict__ X, int6
   st.store(dst, rb, rows);
 }
 
-// acc[e] += the RPT entries at p[e] (RPT / VEC 16-byte runs, p 16-byte
-// aligned) of each slab q < n at p + q stride, added in slab order in double.
-// The slabs are fetched eight at a time so that their loads are in flight
-// together rather than one memory latency per slab.
+// acc[e] += the RPT entries at p[e] of each slab q < n at p + q stride,
+// added in slab order in double (16-byte runs when RPT is a multiple of VEC
+// and p is 16-byte aligned, else element by element). The slabs are fetched
+// eight at a time so that their loads are in flight together rather than one
+// memory latency per slab.
 template <typename T, int RPT>
 __device__ __forceinline__ void slab_sum(const T* p, int n, int64_t stride, double (&acc)[RPT]) {
-  constexpr int VEC = Tr<T>::VEC, NV = RPT / VEC, G = 8;
-  static_assert(RPT % VEC == 0, "whole 16-byte runs");
-  int q = 0;
-  for (; q + G <= n; q += G) {
-    V16<T> v[G][NV];
+  constexpr int VEC = Tr<T>::VEC, G = 8;
+  if constexpr (RPT % VEC == 0) {
+    constexpr int NV = RPT / VEC;
+    int q = 0;
+    for (; q + G <= n; q += G) {
+      V16<T> v[G][NV];
 #pragma unroll
-    for (int u = 0; u < G; ++u)
+      for (int u = 0; u < G; ++u)
 #pragma unroll
-      for (int h = 0; h < NV; ++h) v[u][h] = load16<T>(p + (q + u) * stride + h * VEC);
+        for (int h = 0; h < NV; ++h) v[u][h] = load16<T>(p + (q + u) * stride + h * VEC);
 #pragma unroll
-    for (int u = 0; u < G; ++u)
+      for (int u = 0; u < G; ++u)
 #pragma unroll
-      for (int h = 0; h < NV; ++h)
+        for (int h = 0; h < NV; ++h)
 #pragma unroll
-        for (int w = 0; w < VEC; ++w) acc[h * VEC + w] += (double)v[u][h].v[w];
-  }
-  for (; q < n; ++q) {
-#pragma unroll
-    for (int h = 0; h < NV; ++h) {
-      const V16<T> v = load16<T>(p + q * stride + h * VEC);
-#pragma unroll
-      for (int w = 0; w < VEC; ++w) acc[h * VEC + w] += (double)v.v[w];
+          for (int w = 0; w < VEC; ++w) acc[h * VEC + w] += (double)v[u][h].v[w];
     }
+    for (; q < n; ++q) {
+#pragma unroll
+      for (int h = 0; h < NV; ++h) {
+        const V16<T> v = load16<T>(p + q * stride + h * VEC);
+#pragma unroll
+        for (int w = 0; w < VEC; ++w) acc[h * VEC + w] += (double)v.v[w];
+      }
+    }
+  } else {
+    int q = 0;
+    for (; q + G <= n; q += G) {
+      T v[G][RPT];
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) v[u][e] = p[(q + u) * stride + e];
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) acc[e] += (double)v[u][e];
+    }
+    for (; q < n; ++q)
+#pragma unroll
+      for (int e = 0; e < RPT; ++e) acc[e] += (double)p[q * stride + e];
   }
 }
 

@@ -29,23 +29,34 @@ namespace nmfk {
 // number of rows: many rows fill the chip with small groups, which take fewer
 // permutation steps per column; few rows need larger groups to fill it.
 template <typename T, int KP, int TPR>
-__global__ __launch_bounds__(256) void hals_rows_grp_kernel(T* __restrict__ X,
-                                                            const T* __restrict__ P,
+__global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, Split<T> P,
                                                             const T* __restrict__ G,
-                                                            int64_t rows, int k) {
+                                                            int64_t rows, int k,
+                                                            T* __restrict__ Xt) {
   constexpr int R = KP / TPR, ROWS = 256 / TPR;
+  constexpr int VEC = Tr<T>::VEC;
+  constexpr int XLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
-  stage_square_t<T, KP, 256>(Gs, G);
-  __syncthreads();
+  __shared__ __attribute__((aligned(16))) T Xs[KP <= 64 ? ROWS * XLD : VEC];
   const int sub = threadIdx.x % TPR;
-  const int64_t r = (int64_t)blockIdx.x * ROWS + threadIdx.x / TPR;
+  const int64_t rb = (int64_t)blockIdx.x * ROWS;
+  const int64_t r = rb + threadIdx.x / TPR;
   const int64_t rr = r < rows ? r : rows - 1;
+  // G's loads, the row's x and its entries of P (summed from the slabs in
+  // slab order in double), all in flight together
+  SquareStage<T, KP, 256> gst;
+  gst.load(G, nullptr);
   T x[R], p[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    x[q] = X[rr * KP + sub * R + q];
-    p[q] = P[rr * KP + sub * R + q];
-  }
+  for (int q = 0; q < R; ++q) x[q] = X[rr * KP + sub * R + q];
+  double ps[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) ps[q] = 0.0;
+  slab_sum<T, R>(P.p + rr * KP + sub * R, P.n, P.stride, ps);
+#pragma unroll
+  for (int q = 0; q < R; ++q) p[q] = (T)ps[q];
+  gst.store_t(Gs);
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
     if (i < k) {
@@ -65,7 +76,14 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(T* __restrict__ X,
   }
   if (r < rows) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) X[r * KP + sub * R + q] = x[q];
+    for (int q = 0; q < R; ++q) Xn[r * KP + sub * R + q] = x[q];
+  }
+  if constexpr (KP <= 64) {
+    if (Xt == nullptr) return;  // uniform over the block
+#pragma unroll
+    for (int q = 0; q < R; ++q) Xs[(threadIdx.x / TPR) * XLD + sub * R + q] = x[q];
+    __syncthreads();
+    store_rows_transposed<T, KP, ROWS, XLD>(Xs, rb, rows, Xt);
   }
 }
 
@@ -202,32 +220,36 @@ hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int 
 }
 
 template <typename T, int KP>
-void launch_hals_grp(T* X, const T* P, const T* G, int64_t rows, int k, int tpr,
-                     hipStream_t st) {
+void launch_hals_grp(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int tpr,
+                     T* Xt, hipStream_t st) {
   if (tpr == 4)
-    hals_rows_grp_kernel<T, KP, 4><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(X, P, G, rows, k);
+    hals_rows_grp_kernel<T, KP, 4><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(X, Xn, P, G, rows,
+                                                                             k, Xt);
   else if (tpr == 8)
-    hals_rows_grp_kernel<T, KP, 8><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(X, P, G, rows, k);
+    hals_rows_grp_kernel<T, KP, 8><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(X, Xn, P, G, rows,
+                                                                             k, Xt);
   else
-    hals_rows_grp_kernel<T, KP, 16><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(X, P, G, rows, k);
+    hals_rows_grp_kernel<T, KP, 16><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(X, Xn, P, G, rows,
+                                                                              k, Xt);
 }
 
 template <typename T>
-hipError_t hals_rows(T* X, const T* P, const T* G, int64_t rows, int k, int KP,
-                     hipStream_t st) {
+hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP,
+                     T* Xt, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
+  if ((Xt && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
   const int tpr = rows >= 65536 ? 4 : (rows >= 16384 ? 8 : 16);
   // every padded rank up to NMF_MAX_K takes the grouped sweep; G (KP x KP)
   // is staged in LDS, at most 64 KB (float) or 128 KB (double) at KP = 128
   switch (KP) {
-    case 16: launch_hals_grp<T, 16>(X, P, G, rows, k, tpr, st); break;
-    case 32: launch_hals_grp<T, 32>(X, P, G, rows, k, tpr, st); break;
-    case 48: launch_hals_grp<T, 48>(X, P, G, rows, k, tpr, st); break;
-    case 64: launch_hals_grp<T, 64>(X, P, G, rows, k, tpr, st); break;
-    case 80: launch_hals_grp<T, 80>(X, P, G, rows, k, tpr, st); break;
-    case 96: launch_hals_grp<T, 96>(X, P, G, rows, k, tpr, st); break;
-    case 112: launch_hals_grp<T, 112>(X, P, G, rows, k, tpr, st); break;
-    case 128: launch_hals_grp<T, 128>(X, P, G, rows, k, tpr, st); break;
+    case 16: launch_hals_grp<T, 16>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 32: launch_hals_grp<T, 32>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 48: launch_hals_grp<T, 48>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 64: launch_hals_grp<T, 64>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 80: launch_hals_grp<T, 80>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 96: launch_hals_grp<T, 96>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 112: launch_hals_grp<T, 112>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 128: launch_hals_grp<T, 128>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
     default: return hipErrorInvalidValue;
   }
   return NMF_LAUNCH_CHECK();
@@ -253,31 +275,38 @@ __global__ void hals_norms_kernel(T* __restrict__ S, T* __restrict__ norms, int 
   }
 }
 
-// W[:, i] /= s_i (rows 0..m-1), Ht[:, i] *= s_i (rows m..m+n-1 of the grid).
+// Wn[:, i] = W[:, i] / s_i (rows 0..m-1), Htn[:, i] = Ht[:, i] * s_i (rows
+// m..m+n-1 of the grid); columns with s_i = 0 (and the padding) are copied.
+// Wn and Htn may be W and Ht.
 template <typename T>
-__global__ void hals_scale_kernel(T* __restrict__ W, int64_t m, T* __restrict__ Ht, int64_t n,
+__global__ void hals_scale_kernel(const T* W, T* Wn, int64_t m, const T* Ht, T* Htn, int64_t n,
                                   const T* __restrict__ norms, int k, int KP) {
   const int64_t total = (m + n) * KP, stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int64_t r = e / KP;
     const int i = (int)(e - r * KP);
-    if (i >= k) continue;
-    const T s = norms[i];
-    if (!(s > T(0))) continue;
-    if (r < m) W[r * KP + i] = W[r * KP + i] / s;
-    else Ht[(r - m) * KP + i] = Ht[(r - m) * KP + i] * s;
+    const T s = i < k ? norms[i] : T(0);
+    const bool sc = s > T(0);
+    if (r < m) {
+      const T v = W[r * KP + i];
+      Wn[r * KP + i] = sc ? v / s : v;
+    } else {
+      const T v = Ht[(r - m) * KP + i];
+      Htn[(r - m) * KP + i] = sc ? v * s : v;
+    }
   }
 }
 
 template <typename T>
-hipError_t hals_normalize(T* W, int64_t m, T* Ht, int64_t n, T* S, T* norms, int k, int KP,
-                          hipStream_t st) {
+hipError_t hals_normalize(const T* W, T* Wn, int64_t m, const T* Ht, T* Htn, int64_t n, T* S,
+                          T* norms, int k, int KP, hipStream_t st) {
   hals_norms_kernel<T><<<1, 256, 0, st>>>(S, norms, k, KP);
   hipError_t e = NMF_LAUNCH_CHECK();
   if (e != hipSuccess) return e;
   const int64_t total = (m + n) * KP;
   if (total == 0) return hipSuccess;
-  hals_scale_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(W, m, Ht, n, norms, k, KP);
+  hals_scale_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(W, Wn, m, Ht, Htn, n, norms,
+                                                                      k, KP);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -506,9 +535,10 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
 #define INST(T)                                                                             \
   template hipError_t mu_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T, T*, \
                                  T*, hipStream_t); \
-  template hipError_t hals_rows<T>(T*, const T*, const T*, int64_t, int, int, hipStream_t);  \
-  template hipError_t hals_normalize<T>(T*, int64_t, T*, int64_t, T*, T*, int, int,         \
-                                        hipStream_t);                                       \
+  template hipError_t hals_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T*, \
+                                   hipStream_t);                                            \
+  template hipError_t hals_normalize<T>(const T*, T*, int64_t, const T*, T*, int64_t, T*, T*, \
+                                        int, int, hipStream_t);                             \
   template hipError_t pad_rows<T>(const T*, int64_t, int, T*, int, hipStream_t);            \
   template hipError_t unpad_rows<T>(const T*, int64_t, int, int, T*, hipStream_t);          \
   template hipError_t transpose_in<T>(const T*, int, int64_t, T*, int, hipStream_t);        \
