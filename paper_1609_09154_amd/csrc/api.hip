@@ -1637,6 +1637,9 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
   const size_t ogG = cv.take<T>(KP * KP);
   const size_t ogGt = cv.take<T>(KP * KP);
   const size_t ogGs = cv.take<T>(KP * KP);
+  // the adjoints' per-block shares of the Gram gradients
+  const int64_t nbm = nmfk::mu_adjoint_blocks<T>(m, KP), nbn = nmfk::mu_adjoint_blocks<T>(n, KP);
+  const size_t ogsl = cv.take<T>(std::max(nbm, nbn) * KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   MuWork<T> w = mu_bind<T>(ctx, off);
@@ -1645,6 +1648,7 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
   T *gW = at<T>(ctx, ogW), *gH = at<T>(ctx, ogH), *gW2 = at<T>(ctx, ogW2), *gH2 = at<T>(ctx, ogH2);
   T *gD = at<T>(ctx, ogD), *tmp = at<T>(ctx, otmp), *gG = at<T>(ctx, ogG), *gGs = at<T>(ctx, ogGs);
   T *Qts = at<T>(ctx, oQts), *Sts = at<T>(ctx, oSts), *gGt = at<T>(ctx, ogGt);
+  T* gsl = at<T>(ctx, ogsl);
   hipStream_t st = ctx->stream;
   const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
   HIP_TRY(nmfk::pad_rows<T>(gWT, m, k, gW, KP, st));
@@ -1687,21 +1691,16 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
                                        Sts + i * KP * KP, gH,
                                        pre ? yp : nmfk::Split<T>{nullptr, 0, 0},
                                        pre ? gG : nullptr, gGt, n, k, KP, eps, gR,
-                                       tH ? w.Ft : nullptr, gD, gH2, st));
-      {
-        nmfk::GemmArgs<T> a{H0s, KP, gD, KP, gG, KP, KP, KP, n, false, 0, gGt};
-        HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(n), w.part, st));
-      }
+                                       tH ? w.Ft : nullptr, gD, gH2, gsl, st));
+      // dL/dS = H0^T gD: the adjoint's per-block shares, summed in order
+      HIP_TRY(nmfk::reduce_splits<T>(gsl, (int)nbn, KP * KP, KP, KP, KP, gG, KP, st, gGt));
       if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w, tH, &yp)) != NMF_OK) return s;
       // W step: W1 = W0 * P / (W0 Q + eps), P = A H0^T, Q = H0 H0^T; the
       // gradient reaching W1 is gW + A gR + W1 (gG + gG^T)
       HIP_TRY(nmfk::mu_adjoint_rows<T>(W0s, W1s, Ps + i * m * KP, Qs + i * KP * KP,
                                        Qts + i * KP * KP, gW, yp, gG, gGt, m, k, KP, eps, gP,
-                                       tW ? w.Ft : nullptr, gD, gW2, st));
-      {
-        nmfk::GemmArgs<T> a{W0s, KP, gD, KP, gG, KP, KP, KP, m, false, 0, gGt};
-        HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(m), w.part, st));
-      }
+                                       tW ? w.Ft : nullptr, gD, gW2, gsl, st));
+      HIP_TRY(nmfk::reduce_splits<T>(gsl, (int)nbm, KP * KP, KP, KP, KP, gG, KP, st, gGt));
       // A^T gP reaches the next H step as slabs, except across a segment
       // boundary (the recomputation reuses w.part) and at the end
       if (i > 0) {

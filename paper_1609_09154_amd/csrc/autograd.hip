@@ -25,6 +25,31 @@ template <int KP> struct AdjSplit {
   static constexpr int ROWS = 256 / TPR;
 };
 
+// slab[a][b] = sum_q Xs[q][a] Ds[q][b] over a block's ROWS staged rows (LDS,
+// pitch LD): the block's share of the Gram product X^T D, on the matrix
+// cores. The block's waves take the 16 x 16 output tiles in turn; each tile
+// runs down the rows four at a time (lane l: row k0 + l / 16, column l % 16
+// of both operands). Rows past the end are zero in both.
+template <typename T, int KP, int ROWS, int LD>
+__device__ __forceinline__ void block_gram_partial(const T* Xs, const T* Ds, T* __restrict__ slab) {
+  constexpr int NTL = KP / 16, TILES = NTL * NTL;
+  typedef typename Tr<T>::acc4 acc4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  for (int t = wave; t < TILES; t += nwaves) {
+    const int a0 = (t / NTL) * 16, b0 = (t % NTL) * 16;
+    acc4 acc = zero4<T>();
+#pragma unroll 8
+    for (int k0 = 0; k0 < ROWS; k0 += 4) {
+      const int q = k0 + (lane >> 4);
+      acc = mfma16(Xs[q * LD + a0 + (lane & 15)], Ds[q * LD + b0 + (lane & 15)], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      slab[(a0 + acc_row<T>(lane, r)) * KP + b0 + (lane & 15)] = acc[r];
+  }
+}
+
 // Local adjoint of Xn = X * N / (X G + eps) for the rows of one block. The
 // gradient reaching Xn is gXn, plus (PRE) Y + Xn (M + M^T): what the next
 // half-step's product (Y) and Gram (M) pass back to Xn, added here rather
@@ -32,7 +57,9 @@ template <int KP> struct AdjSplit {
 // transpose), gD (= dL/dD) and gX; entries k..KP-1 are 0. G, (PRE) M + M^T
 // (from M and its transpose Mtr), the block's rows of X and (PRE) of Xn live
 // in LDS; the Xn rows' buffer then holds dL/dD and the X rows' buffer gN for
-// the transposed store.
+// the transposed store. With Gslab set, the block also writes its share of
+// dL/dG = X^T (dL/dD) to slab blockIdx.x (KP x KP) of Gslab, for an ordered
+// sum over the blocks.
 // Both G-products run in the same form: one value of the row broadcast from
 // LDS times 16-byte runs of a matrix row, d_i = sum_j x_j G[j][i] from G
 // and (dL/dx)_i = sum_j dd_j G[i][j] from G^T (Gtr, the Gram's transposed
@@ -43,7 +70,8 @@ __global__ __launch_bounds__(256) void mu_adjoint_rows_kernel(
     const T* __restrict__ X, const T* __restrict__ Xn, const T* __restrict__ N,
     const T* __restrict__ G, const T* __restrict__ Gtr, const T* __restrict__ gXn, Split<T> Y,
     const T* __restrict__ M, const T* __restrict__ Mtr, int64_t rows, int k, T eps,
-    T* __restrict__ gN, T* __restrict__ gNt, T* __restrict__ gD, T* __restrict__ gX) {
+    T* __restrict__ gN, T* __restrict__ gNt, T* __restrict__ gD, T* __restrict__ gX,
+    T* __restrict__ Gslab) {
   constexpr int TPR = AdjSplit<KP>::TPR, RPT = AdjSplit<KP>::RPT, ROWS = AdjSplit<KP>::ROWS;
   constexpr int VEC = Tr<T>::VEC;
   constexpr int DLD = KP + VEC;
@@ -53,6 +81,7 @@ __global__ __launch_bounds__(256) void mu_adjoint_rows_kernel(
   __shared__ __attribute__((aligned(16))) T Ms[PRE ? KP * KP : VEC];
   __shared__ __attribute__((aligned(16))) T Xs[ROWS * DLD];
   __shared__ __attribute__((aligned(16))) T Ds[ROWS * DLD];
+  __shared__ __attribute__((aligned(16))) T GNs[ROWS * DLD];
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
   const int lr = threadIdx.x / TPR;
   const int64_t r = rb + lr;
@@ -148,13 +177,14 @@ __global__ __launch_bounds__(256) void mu_adjoint_rows_kernel(
       gD[r * KP + i0 + ii] = dd[ii];
     }
   }
-  __syncthreads();  // the staged rows of X and Xn are no longer read
+  __syncthreads();  // the staged rows of Xn are no longer read
 #pragma unroll
   for (int ii = 0; ii < RPT; ++ii) {
     Ds[lr * DLD + i0 + ii] = dd[ii];
-    Xs[lr * DLD + i0 + ii] = gn[ii];
+    GNs[lr * DLD + i0 + ii] = gn[ii];
   }
   __syncthreads();
+  if (Gslab) block_gram_partial<T, KP, ROWS, DLD>(Xs, Ds, Gslab + (int64_t)blockIdx.x * KP * KP);
   if (live) {
     // D_i = sum_j x_j G[j][i], so dL/dx_i picks up sum_j dd_j G[i][j]
     if constexpr (GT) {
@@ -193,7 +223,7 @@ __global__ __launch_bounds__(256) void mu_adjoint_rows_kernel(
       }
     }
   }
-  if (gNt) store_rows_transposed<T, KP, ROWS, DLD>(Xs, rb, rows, gNt);
+  if (gNt) store_rows_transposed<T, KP, ROWS, DLD>(GNs, rb, rows, gNt);
 }
 
 // Out[r] = (Out[r] + Y[r]) + X[r] M for rows x KP X and KP x KP M, columns
@@ -583,9 +613,21 @@ __global__ void hals_norm_adjoint_kernel(const T* __restrict__ gWn, const T* __r
 }
 
 template <typename T>
+int64_t mu_adjoint_blocks(int64_t rows, int KP) {
+  switch (KP) {
+    case 16: return cdiv(rows, AdjSplit<16>::ROWS);
+    case 32: return cdiv(rows, AdjSplit<32>::ROWS);
+    case 48: return cdiv(rows, AdjSplit<48>::ROWS);
+    case 64: return cdiv(rows, AdjSplit<64>::ROWS);
+    default: return 0;
+  }
+}
+
+template <typename T>
 hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* Gt,
                            const T* gXn, Split<T> Y, const T* M, const T* Mt, int64_t rows, int k,
-                           int KP, T eps, T* gN, T* gNt, T* gD, T* gX, hipStream_t st) {
+                           int KP, T eps, T* gN, T* gNt, T* gD, T* gX, T* Gslab,
+                           hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   if ((Y.p && Y.n < 1) || !Gt || (M && !Mt)) return hipErrorInvalidValue;
   const bool pre = Y.p != nullptr || M != nullptr;
@@ -595,11 +637,11 @@ hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, cons
     if (pre)                                                                                  \
       mu_adjoint_rows_kernel<T, K, true><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0,    \
                                            st>>>(X, Xn, N, G, Gt, gXn, Y, M, Mt, rows, k, eps, \
-                                                 gN, gNt, gD, gX);                             \
+                                                 gN, gNt, gD, gX, Gslab);                      \
     else                                                                                      \
       mu_adjoint_rows_kernel<T, K, false><<<(unsigned)cdiv(rows, AdjSplit<K>::ROWS), 256, 0,   \
                                             st>>>(X, Xn, N, G, Gt, gXn, Y, M, Mt, rows, k,     \
-                                                  eps, gN, gNt, gD, gX);                       \
+                                                  eps, gN, gNt, gD, gX, Gslab);                \
     break;
     CASE(16) CASE(32) CASE(48) CASE(64)
 #undef CASE
@@ -714,7 +756,8 @@ hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc,
                                            hipStream_t);                                      \
   template hipError_t mu_adjoint_rows<T>(const T*, const T*, const T*, const T*, const T*,    \
                                          const T*, Split<T>, const T*, const T*, int64_t, int, \
-                                         int, T, T*, T*, T*, T*, hipStream_t);                 \
+                                         int, T, T*, T*, T*, T*, T*, hipStream_t);             \
+  template int64_t mu_adjoint_blocks<T>(int64_t, int);                                        \
   template hipError_t rowmm_add<T>(const T*, const T*, int64_t, int, int, T*, hipStream_t,    \
                                    Split<T>);                                                \
   template hipError_t symmetrize<T>(const T*, int, T*, hipStream_t);                          \

@@ -178,10 +178,14 @@ hipError_t csr_sumsq(const float* vals, int64_t nnz, double* partial, int64_t np
 // gD = -g * Xn / D, gX = g * N / D + gD G^T (D = X G + eps). Gt and Mt are
 // the transposes of G and M (as the Gram's reduction writes them). gNt
 // (nullable) receives gN transposed, gNt[i * rows + r].
+// Gslab (nullable) receives the Gram gradient dL/dG = X^T gD as one KP x KP
+// slab per row block (mu_adjoint_blocks of them), to be summed in order.
 template <typename T>
 hipError_t mu_adjoint_rows(const T* X, const T* Xn, const T* N, const T* G, const T* Gt,
                            const T* gXn, Split<T> Y, const T* M, const T* Mt, int64_t rows, int k,
-                           int KP, T eps, T* gN, T* gNt, T* gD, T* gX, hipStream_t st);
+                           int KP, T eps, T* gN, T* gNt, T* gD, T* gX, T* Gslab, hipStream_t st);
+template <typename T>
+int64_t mu_adjoint_blocks(int64_t rows, int KP);
 // Reverse of the HALS sweep on rows x KP rows (KP in {16, 32, 48, 64}): from
 // the sweep's output Xnew, the Gram G and gXnew = dL/dXnew, writes
 // gXold = dL/dX (input) and Delta = dL/dP (one delta per row and column);
