@@ -1828,9 +1828,10 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   const size_t ogHc = cv.take<T>(n * KP);
   const size_t ogWp = cv.take<T>(m * KP);
   const size_t otmp = cv.take<T>(mx * KP);
-  const size_t oT1 = cv.take<T>(KP * KP);
-  const size_t oT2 = cv.take<T>(KP * KP);
   const size_t oM = cv.take<T>(KP * KP);
+  // the reverse sweeps' per-block shares of their two Gram products
+  const int64_t hbm = nmfk::hals_adjoint_blocks<T>(m, KP), hbn = nmfk::hals_adjoint_blocks<T>(n, KP);
+  const size_t otsl = cv.take<T>(2 * std::max(hbm, hbn) * KP * KP);
   const size_t odots = cv.take<double>(2 * KP);
   const size_t odpart = cv.take<double>(nmfk::coldot_partials(KP));
   nmf_status s = ensure_ws(ctx, cv.off);
@@ -1841,8 +1842,9 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   T *gW = at<T>(ctx, ogW), *gH = at<T>(ctx, ogH), *gW2 = at<T>(ctx, ogW2), *gH2 = at<T>(ctx, ogH2);
   T *gRs = at<T>(ctx, ogRs), *gPs = at<T>(ctx, ogPs), *gHc = at<T>(ctx, ogHc);
   T* gWp = at<T>(ctx, ogWp);
-  T *tmp = at<T>(ctx, otmp), *T1 = at<T>(ctx, oT1), *T2 = at<T>(ctx, oT2), *M = at<T>(ctx, oM);
+  T *tmp = at<T>(ctx, otmp), *M = at<T>(ctx, oM);
   double *dots = at<double>(ctx, odots), *dpart = at<double>(ctx, odpart);
+  T* tsl = at<T>(ctx, otsl);
   hipStream_t st = ctx->stream;
   const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
   nmfk::Split<T> yp{nullptr, 0, 0};
@@ -1851,11 +1853,6 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   if (gA && iters == 0) HIP_TRY(hipMemset2DAsync(gA, ldga * sizeof(T), 0, n * sizeof(T), m, st));
   Prob<T> pb;
   if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
-  auto tn = [&](const T* X, const T* Y, int64_t rows, T* D) -> nmf_status {
-    nmfk::GemmArgs<T> a{X, KP, Y, KP, D, KP, KP, KP, rows, false, 0};
-    HIP_TRY(nmfk::gemm_run<T>(nmfk::GemmKind::TN_GRAM, a, gram_splits(rows), w.part, st));
-    return NMF_OK;
-  };
   const int64_t slot = (m + n) * KP;
   const int64_t nck = mu_ckpt_count(iters, every);
   for (int64_t j = nck - 1; j >= 0; --j) {
@@ -1883,10 +1880,9 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
       T* gP = gPs + i * m * KP;
       // H sweep on the rows of Hc with R = A^T Wn and S = Wn^T Wn
       HIP_TRY(nmfk::hals_adjoint_rows<T>(H1s, Ss + i * KP * KP, gH, n, k, KP, gHc, gR,
-                                         tH ? w.Ft : nullptr, st));
-      if ((s = tn(H1s, gR, n, T1)) != NMF_OK) return s;
-      if ((s = tn(Hc, gR, n, T2)) != NMF_OK) return s;
-      HIP_TRY(nmfk::hals_gram_grad<T>(T1, T2, KP, M, st));
+                                         tH ? w.Ft : nullptr, Hc, tsl, st));
+      // M from T1 = H1^T gR and T2 = Hc^T gR, summed from the blocks' shares
+      HIP_TRY(nmfk::hals_gram_grad<T>(tsl, (int)hbn, KP, M, st));
       // gW += A gR (the product's slabs) + Wn M
       if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w, tH, &yp)) != NMF_OK) return s;
       HIP_TRY(nmfk::rowmm_add<T>(W1s, M, m, k, KP, gW, st, yp));
@@ -1897,10 +1893,8 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
                                          st));
       // W sweep with P = A H^T and Q = H H^T
       HIP_TRY(nmfk::hals_adjoint_rows<T>(Wp, Qs + i * KP * KP, gWp, m, k, KP, gW2, gP,
-                                         tW ? w.Ft : nullptr, st));
-      if ((s = tn(Wp, gP, m, T1)) != NMF_OK) return s;
-      if ((s = tn(W0s, gP, m, T2)) != NMF_OK) return s;
-      HIP_TRY(nmfk::hals_gram_grad<T>(T1, T2, KP, M, st));
+                                         tW ? w.Ft : nullptr, W0s, tsl, st));
+      HIP_TRY(nmfk::hals_gram_grad<T>(tsl, (int)hbm, KP, M, st));
       // gH += A^T gP (the product's slabs) + H M
       if ((s = mu_prod_AtF<T>(ctx, pb, m, n, gP, k, KP, tmp, w, tW, &yp)) != NMF_OK) return s;
       HIP_TRY(nmfk::rowmm_add<T>(H0s, M, n, k, KP, gH2, st, yp));

@@ -463,23 +463,37 @@ template <int KP> struct HalsAdjGroup {
   static constexpr int ROWS = 256 / TPR;
 };
 
+// With Xold and Tslab set, the block also writes its shares of the two
+// Gram products of the sweep's Gram gradient, Xnew^T Delta and Xold^T Delta,
+// to slab blockIdx.x of Tslab and of Tslab + nblocks KP^2 (KP x KP each), for
+// ordered sums over the blocks.
 template <typename T, int KP>
 __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
     const T* __restrict__ Xnew, const T* __restrict__ G, const T* __restrict__ gXnew,
-    int64_t rows, int k, T* __restrict__ gXold, T* __restrict__ Delta, T* __restrict__ Dt) {
+    int64_t rows, int k, T* __restrict__ gXold, T* __restrict__ Delta, T* __restrict__ Dt,
+    const T* __restrict__ Xold, T* __restrict__ Tslab) {
   constexpr int TPR = HalsAdjGroup<KP>::TPR, R = HalsAdjGroup<KP>::R;
   constexpr int ROWS = HalsAdjGroup<KP>::ROWS;
   constexpr int VEC = Tr<T>::VEC;
   constexpr int DLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
   __shared__ __attribute__((aligned(16))) T Ds[ROWS * DLD];
+  __shared__ __attribute__((aligned(16))) T XNs[ROWS * DLD];
+  __shared__ __attribute__((aligned(16))) T XOs[ROWS * DLD];
+  const bool grams = Tslab != nullptr;  // uniform over the block
   const int sub = threadIdx.x % TPR;
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
   const int64_t r = rb + threadIdx.x / TPR;
   const int64_t rr = r < rows ? r : rows - 1;
-  // G's loads and the row's values, in flight together
+  // G's loads, the block's rows of Xnew and Xold (for the Gram shares) and
+  // the row's values, in flight together
   SquareStage<T, KP, 256> gst;
+  RowStage<T, KP, ROWS, DLD, 256> xnst, xost;
   gst.load(G, nullptr);
+  if (grams) {
+    xnst.load(Xnew, rb, rows);
+    xost.load(Xold, rb, rows);
+  }
   T g[R], d[R];
   unsigned mask = 0;
 #pragma unroll
@@ -489,6 +503,10 @@ __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
     d[q] = T(0);
   }
   gst.store_t(Gs);
+  if (grams) {
+    xnst.store(XNs, rb, rows);
+    xost.store(XOs, rb, rows);
+  }
   __syncthreads();
 #pragma unroll
   for (int i = KP - 1; i >= 0; --i) {
@@ -515,26 +533,57 @@ __global__ __launch_bounds__(256) void hals_adjoint_rows_kernel(
       Delta[r * KP + sub * R + q] = d[q];
     }
   }
-  if (Dt == nullptr) return;  // uniform over the block
-  // Delta transposed (Dt[i * rows + r]), the layout the next product reads
+  if (Dt == nullptr && !grams) return;  // uniform over the block
 #pragma unroll
   for (int q = 0; q < R; ++q) Ds[(threadIdx.x / TPR) * DLD + sub * R + q] = d[q];
   __syncthreads();
-  store_rows_transposed<T, KP, ROWS, DLD>(Ds, rb, rows, Dt);
+  if (grams) {
+    // rows past the end are zero in XNs and XOs, so their deltas add nothing
+    const int64_t slab = (int64_t)KP * KP;
+    block_gram_partial<T, KP, ROWS, DLD>(XNs, Ds, Tslab + blockIdx.x * slab);
+    block_gram_partial<T, KP, ROWS, DLD>(XOs, Ds, Tslab + (gridDim.x + blockIdx.x) * slab);
+  }
+  // Delta transposed (Dt[i * rows + r]), the layout the next product reads
+  if (Dt) store_rows_transposed<T, KP, ROWS, DLD>(Ds, rb, rows, Dt);
 }
 
 // M = S + S^T with S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (KP x KP): the
 // symmetric Gram gradient of a HALS sweep from T1 = X_new^T Delta and
-// T2 = X_old^T Delta.
+// T2 = X_old^T Delta, each given as nb per-block slabs (T1's at slabs, T2's
+// after them). GG_SUB threads per output add every GG_SUB-th slab, then one
+// thread adds their partial sums in order (a fixed order: reproducible bit for
+// bit), rounds T1 and T2 to T and combines them.
+constexpr int GG_OUT = 16, GG_SUB = 16;
 template <typename T>
-__global__ void hals_gram_grad_kernel(const T* __restrict__ T1, const T* __restrict__ T2, int KP,
-                                      T* __restrict__ M) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= KP * KP) return;
-  const int a = e / KP, b = e % KP;
-  const T sab = a <= b ? T1[a * KP + b] : T2[a * KP + b];
-  const T sba = b <= a ? T1[b * KP + a] : T2[b * KP + a];
-  M[e] = -(sab + sba);
+__global__ __launch_bounds__(GG_OUT * GG_SUB) void hals_gram_grad_kernel(
+    const T* __restrict__ slabs, int nb, int KP, T* __restrict__ M) {
+  __shared__ double sh[2][GG_SUB][GG_OUT];
+  const int o = threadIdx.x % GG_OUT, sub = threadIdx.x / GG_OUT;
+  const int e = blockIdx.x * GG_OUT + o;
+  const bool in = e < KP * KP;
+  const int a = in ? e / KP : 0, b = in ? e % KP : 0;
+  const int64_t sl = (int64_t)KP * KP;
+  const T* pab = slabs + (a <= b ? 0 : nb * sl) + a * KP + b;
+  const T* pba = slabs + (b <= a ? 0 : nb * sl) + b * KP + a;
+  double s1 = 0.0, s2 = 0.0;
+  if (in) {
+    for (int p = sub; p < nb; p += GG_SUB) {
+      s1 += (double)pab[p * sl];
+      s2 += (double)pba[p * sl];
+    }
+  }
+  sh[0][sub][o] = s1;
+  sh[1][sub][o] = s2;
+  __syncthreads();
+  if (sub == 0 && in) {
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < GG_SUB; ++q) {
+      t1 += sh[0][q][o];
+      t2 += sh[1][q][o];
+    }
+    M[e] = -((T)t1 + (T)t2);
+  }
 }
 
 // Column dot products out[c] = sum_r X[r][c] Y[r][c] (rows x KP, KP <= 128)
@@ -696,14 +745,28 @@ hipError_t rank_update(T* D, int64_t ldd, int64_t m, int64_t n, const T* X1, con
 }
 
 template <typename T>
+int64_t hals_adjoint_blocks(int64_t rows, int KP) {
+  switch (KP) {
+    case 16: return cdiv(rows, HalsAdjGroup<16>::ROWS);
+    case 32: return cdiv(rows, HalsAdjGroup<32>::ROWS);
+    case 48: return cdiv(rows, HalsAdjGroup<48>::ROWS);
+    case 64: return cdiv(rows, HalsAdjGroup<64>::ROWS);
+    default: return 0;
+  }
+}
+
+template <typename T>
 hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t rows, int k,
-                             int KP, T* gXold, T* Delta, T* Dt, hipStream_t st) {
+                             int KP, T* gXold, T* Delta, T* Dt, const T* Xold, T* Tslab,
+                             hipStream_t st) {
+  if (Tslab && !Xold) return hipErrorInvalidValue;
   if (rows <= 0) return hipSuccess;
   switch (KP) {
 #define CASE(K)                                                                               \
   case K:                                                                                     \
     hals_adjoint_rows_kernel<T, K><<<(unsigned)cdiv(rows, HalsAdjGroup<K>::ROWS), 256, 0,      \
-                                     st>>>(Xnew, G, gXnew, rows, k, gXold, Delta, Dt);        \
+                                     st>>>(Xnew, G, gXnew, rows, k, gXold, Delta, Dt, Xold,   \
+                                           Tslab);                                            \
     break;
     CASE(16) CASE(32) CASE(48) CASE(64)
 #undef CASE
@@ -713,8 +776,10 @@ hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t 
 }
 
 template <typename T>
-hipError_t hals_gram_grad(const T* T1, const T* T2, int KP, T* M, hipStream_t st) {
-  hals_gram_grad_kernel<T><<<(unsigned)cdiv(KP * KP, 256), 256, 0, st>>>(T1, T2, KP, M);
+hipError_t hals_gram_grad(const T* slabs, int nb, int KP, T* M, hipStream_t st) {
+  if (nb < 1) return hipErrorInvalidValue;
+  hals_gram_grad_kernel<T><<<(unsigned)cdiv(KP * KP, GG_OUT), GG_OUT * GG_SUB, 0, st>>>(
+      slabs, nb, KP, M);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -747,8 +812,9 @@ hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc,
 
 #define INST(T)                                                                               \
   template hipError_t hals_adjoint_rows<T>(const T*, const T*, const T*, int64_t, int, int,   \
-                                           T*, T*, T*, hipStream_t);                          \
-  template hipError_t hals_gram_grad<T>(const T*, const T*, int, T*, hipStream_t);            \
+                                           T*, T*, T*, const T*, T*, hipStream_t);            \
+  template int64_t hals_adjoint_blocks<T>(int64_t, int);                                      \
+  template hipError_t hals_gram_grad<T>(const T*, int, int, T*, hipStream_t);                 \
   template hipError_t coldot<T>(const T*, const T*, int64_t, int, double*, double*,           \
                                 hipStream_t);                                                 \
   template hipError_t hals_norm_adjoint<T>(const T*, const T*, int64_t, const T*, int64_t,    \

@@ -189,14 +189,21 @@ int64_t mu_adjoint_blocks(int64_t rows, int KP);
 // Reverse of the HALS sweep on rows x KP rows (KP in {16, 32, 48, 64}): from
 // the sweep's output Xnew, the Gram G and gXnew = dL/dXnew, writes
 // gXold = dL/dX (input) and Delta = dL/dP (one delta per row and column);
-// Dt (nullable) receives Delta transposed, Dt[i * rows + r].
+// Dt (nullable) receives Delta transposed, Dt[i * rows + r]. With Xold (the
+// sweep's input) and Tslab set, the row blocks' shares of Xnew^T Delta and
+// Xold^T Delta go to Tslab: hals_adjoint_blocks slabs of KP x KP each, then as
+// many again, to be summed in order.
 template <typename T>
 hipError_t hals_adjoint_rows(const T* Xnew, const T* G, const T* gXnew, int64_t rows, int k,
-                             int KP, T* gXold, T* Delta, T* Dt, hipStream_t st);
-// M = S + S^T, S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (the sweep's Gram
-// gradient from T1 = Xnew^T Delta and T2 = Xold^T Delta).
+                             int KP, T* gXold, T* Delta, T* Dt, const T* Xold, T* Tslab,
+                             hipStream_t st);
 template <typename T>
-hipError_t hals_gram_grad(const T* T1, const T* T2, int KP, T* M, hipStream_t st);
+int64_t hals_adjoint_blocks(int64_t rows, int KP);
+// M = S + S^T, S[a][b] = -(a <= b ? T1[a][b] : T2[a][b]) (the sweep's Gram
+// gradient from T1 = Xnew^T Delta and T2 = Xold^T Delta, given as the nb
+// per-block slabs of each that hals_adjoint_rows writes).
+template <typename T>
+hipError_t hals_gram_grad(const T* slabs, int nb, int KP, T* M, hipStream_t st);
 // out[c] = sum_r X[r][c] Y[r][c] (double, fixed order); part holds
 // coldot_partials(KP) doubles.
 int64_t coldot_partials(int KP);
