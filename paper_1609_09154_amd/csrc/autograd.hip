@@ -567,9 +567,25 @@ __global__ __launch_bounds__(GG_OUT * GG_SUB) void hals_gram_grad_kernel(
   const T* pba = slabs + (b <= a ? 0 : nb * sl) + b * KP + a;
   double s1 = 0.0, s2 = 0.0;
   if (in) {
-    for (int p = sub; p < nb; p += GG_SUB) {
-      s1 += (double)pab[p * sl];
-      s2 += (double)pba[p * sl];
+    // eight slabs' loads in flight at a time, added in slab order
+    constexpr int NB = 8;
+    int p = sub;
+    for (; p + (NB - 1) * GG_SUB < nb; p += NB * GG_SUB) {
+      T va[NB], vb[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        va[u] = pab[(int64_t)(p + u * GG_SUB) * sl];
+        vb[u] = pba[(int64_t)(p + u * GG_SUB) * sl];
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        s1 += (double)va[u];
+        s2 += (double)vb[u];
+      }
+    }
+    for (; p < nb; p += GG_SUB) {
+      s1 += (double)pab[(int64_t)p * sl];
+      s2 += (double)pba[(int64_t)p * sl];
     }
   }
   sh[0][sub][o] = s1;

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(64) void gram_inverse_kernel(const TS* __restrict__
 }
 
 template <typename TS, int KP>
-__global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
+__global__ __launch_bounds__(64 * BPP_WAVES, 2) void bpp_quad_kernel(
     TS* __restrict__ X, const TS* __restrict__ P, const TS* __restrict__ G,
     const double* __restrict__ Ginv, const int* __restrict__ ginv_ok, int64_t rows, int k,
     int max_pivots, int warm, int* __restrict__ status, unsigned long long* __restrict__ pivots) {
@@ -332,9 +332,23 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
   // flops, sizes, wavefront-maximum sizes and size classes (BPP_T_* order)
   __shared__ unsigned long long tally_l[BPP_WAVES][BPP_RPW][BPP_TALLIES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
-  for (int e = threadIdx.x; e < (KP + 1) * LD; e += blockDim.x) {
-    const int r = e / LD, c = e % LD;
-    Gs[e] = (r < KP && c < KP) ? (double)G[r * KP + c] : 0.0;
+  {
+    // all of a thread's loads of G issued before its first LDS write (one
+    // memory latency, not one per element); the padding row and column are 0
+    constexpr int NG = (KP + 1) * LD, PER = (NG + 64 * BPP_WAVES - 1) / (64 * BPP_WAVES);
+    TS gv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = u * 64 * BPP_WAVES + (int)threadIdx.x;
+      const int r = e / LD, c = e % LD;
+      gv[u] = G[(e < NG && r < KP && c < KP) ? r * KP + c : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = u * 64 * BPP_WAVES + (int)threadIdx.x;
+      const int r = e / LD, c = e % LD;
+      if (e < NG) Gs[e] = (r < KP && c < KP) ? (double)gv[u] : 0.0;
+    }
   }
   for (int e = threadIdx.x; e < BPP_WAVES * BPP_RPW * CNF; e += blockDim.x)
     (&idx_l[0][0][0])[e] = KP;
@@ -368,6 +382,11 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
   const int64_t stride = (int64_t)gridDim.x * BPP_WAVES * BPP_RPW;
   int64_t r = ((int64_t)blockIdx.x * BPP_WAVES + wv) * BPP_RPW + g - stride;
   double x[JS], y[JS];
+  // the next right-hand side's entries of P and warm-start signs, loaded
+  // while the current one is solved
+  TS pnext[JS];
+  unsigned wnext = 0;   // bit s: warm-start sign of slot s
+  bool have_next = false;
   uint64_t F = 0;
   bool live = true, done = true, have_cp = false, bad = false, first = false, from_warm = false;
   int budget = 3, best = k + 1, npiv = 0;
@@ -389,15 +408,37 @@ __global__ __launch_bounds__(64 * BPP_WAVES) void bpp_quad_kernel(
         live = r < rows;
         if (!live) break;
         const int64_t ro = r * KP;
+        if (!have_next) {
+          wnext = 0;
+#pragma unroll
+          for (int s = 0; s < JS; ++s) {
+            const int j = 16 * s + i;
+            pnext[s] = j < k ? P[ro + j] : TS(0);
+            wnext |= (warm && X[ro + j] > TS(0) ? 1u : 0u) << s;
+          }
+        }
         bool wpos[JS];
 #pragma unroll
         for (int s = 0; s < JS; ++s) {
           const int j = 16 * s + i;
-          const double pj = j < k ? (double)P[ro + j] : 0.0;
+          const double pj = (double)pnext[s];
           pl[j] = pj;
           x[s] = 0.0;
           y[s] = -pj;
-          wpos[s] = warm && act[s] && X[ro + j] > TS(0);
+          wpos[s] = act[s] && ((wnext >> s) & 1u);
+        }
+        // this row's next right-hand side (it is the only reader and writer
+        // of its rows of X and P)
+        const int64_t rn = r + stride;
+        have_next = rn < rows;
+        if (have_next) {
+          wnext = 0;
+#pragma unroll
+          for (int s = 0; s < JS; ++s) {
+            const int j = 16 * s + i;
+            pnext[s] = j < k ? P[rn * KP + j] : TS(0);
+            wnext |= (warm && X[rn * KP + j] > TS(0) ? 1u : 0u) << s;
+          }
         }
         F = row_bits<JS>(wpos, g) & all;
         done = false;

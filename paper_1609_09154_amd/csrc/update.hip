@@ -258,8 +258,12 @@ hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, in
 // --- HALS normalisation ----------------------------------------------------
 // One block: norms s_i = sqrt(S_ii) (0 if S_ii <= 0), then S <- D^-1 S D^-1
 // on the entries whose norms are positive.
+// The entries of S a thread rescales are loaded in batches of NB before any
+// is written, so the block waits for one memory latency per batch rather
+// than one per entry.
 template <typename T>
 __global__ void hals_norms_kernel(T* __restrict__ S, T* __restrict__ norms, int k, int KP) {
+  constexpr int NB = 16;
   __shared__ double s_sh[NMF_MAX_K];
   for (int i = threadIdx.x; i < KP; i += blockDim.x) {
     const T d = S[i * KP + i];
@@ -268,10 +272,23 @@ __global__ void hals_norms_kernel(T* __restrict__ S, T* __restrict__ norms, int 
     norms[i] = (T)s;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) {
-    const int i = e / KP, j = e - i * KP;
-    const double si = s_sh[i], sj = s_sh[j];
-    if (si > 0.0 && sj > 0.0) S[e] = (T)((double)S[e] / (si * sj));
+  const int total = KP * KP, step = (int)blockDim.x;
+  for (int e0 = threadIdx.x; e0 < total; e0 += NB * step) {
+    T v[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = e0 + u * step;
+      v[u] = S[e < total ? e : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = e0 + u * step;
+      if (e < total) {
+        const int i = e / KP, j = e - i * KP;
+        const double si = s_sh[i], sj = s_sh[j];
+        if (si > 0.0 && sj > 0.0) S[e] = (T)((double)v[u] / (si * sj));
+      }
+    }
   }
 }
 
