@@ -337,6 +337,8 @@ nmf_status nmf_projected_gradient_sq(nmf_ctx* ctx, nmf_dtype dtype, int64_t rows
  * segment of c iterations from its checkpoint and runs the adjoint through
  * it in reverse, so its memory grows with c, not with T. It must be given the
  * same m, n, A, k, T, eps and c as the forward pass that wrote the buffer.
+ * The gradients of W_0 and H_0 do not depend on c, bit for bit; dL/dA is
+ * summed one segment at a time, so its float rounding does.
  */
 
 /* Elements of dtype in the checkpoint buffer, or -1 for invalid sizes. */
