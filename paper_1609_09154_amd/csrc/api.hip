@@ -263,7 +263,7 @@ nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, i
   hipStream_t st = ctx->stream;
   if (algo == NMF_MU)
     HIP_TRY(nmfk::mu_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, (T)o->eps_mu,
-                             nullptr, nullptr, st));
+                             nullptr, nullptr, nullptr, st));
   else if (algo == NMF_HALS)
     HIP_TRY(nmfk::hals_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, nullptr, st));
   else {
@@ -1545,26 +1545,44 @@ bool rows_transposable(int64_t rows, int KP) {
 // and R are set (nullable). The products reach the updates as their split
 // slabs. *ft: on entry, whether w.Ft holds Ht's transposed copy; on return,
 // whether it holds Htn's (the update writes it for the next iteration's
-// product).
+// product). With gsl set (KP <= 64), the Grams are summed from row-block
+// shares: each update writes the shares of its output's Gram into gsl, and
+// *qready says whether gsl holds Ht's on entry (else they are formed here);
+// on return it holds Htn's. The shares' blocking and order are the same
+// whichever kernel forms them, so a recomputation from a checkpoint repeats
+// the Grams of the first pass bit for bit.
 template <typename T>
 nmf_status mu_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
                         T eps, const T* W, const T* Ht, T* Wn, T* Htn, T* P, T* Q, T* R, T* S,
-                        MuWork<T>& w, bool* ft, T* Qt = nullptr, T* St = nullptr) {
+                        MuWork<T>& w, bool* ft, T* Qt = nullptr, T* St = nullptr,
+                        T* gsl = nullptr, bool* qready = nullptr) {
   hipStream_t st = ctx->stream;
   nmf_status s;
   const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
   nmfk::Split<T> sp;
   T* Pd = P ? P : w.P;
   T* Rd = R ? R : w.R;
-  if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part, Qt)) != NMF_OK) return s;
+  const int64_t nbm = gsl ? nmfk::gram_share_blocks<T>(m, KP) : 0;
+  const int64_t nbn = gsl ? nmfk::gram_share_blocks<T>(n, KP) : 0;
+  if (gsl) {
+    if (!*qready) HIP_TRY(nmfk::gram_shares<T>(Ht, n, KP, gsl, st));
+    HIP_TRY(nmfk::reduce_splits<T>(gsl, (int)nbn, KP * KP, KP, KP, KP, Q, KP, st, Qt));
+  } else if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part, Qt)) != NMF_OK) {
+    return s;
+  }
   if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, Pd, w, *ft, &sp)) != NMF_OK) return s;
   HIP_TRY(nmfk::mu_rows<T>(W, Wn, sp, Q, m, k, KP, eps, tW ? w.Ft : nullptr,
-                           sp.n > 1 ? P : nullptr, st));
-  if ((s = gram<T>(ctx, Wn, m, KP, S, w.part, St)) != NMF_OK) return s;
+                           sp.n > 1 ? P : nullptr, gsl, st));
+  if (gsl) {
+    HIP_TRY(nmfk::reduce_splits<T>(gsl, (int)nbm, KP * KP, KP, KP, KP, S, KP, st, St));
+  } else if ((s = gram<T>(ctx, Wn, m, KP, S, w.part, St)) != NMF_OK) {
+    return s;
+  }
   if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, Rd, w, tW, &sp)) != NMF_OK) return s;
   HIP_TRY(nmfk::mu_rows<T>(Ht, Htn, sp, S, n, k, KP, eps, tH ? w.Ft : nullptr,
-                           sp.n > 1 ? R : nullptr, st));
+                           sp.n > 1 ? R : nullptr, gsl, st));
   *ft = tH;
+  if (gsl) *qready = true;
   return NMF_OK;
 }
 
@@ -1583,16 +1601,20 @@ nmf_status mu_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64
   Carve cv;
   size_t off[8];
   mu_plan_common<T>(m, n, KP, cv, off);
+  // the updates' Gram shares (k <= 64 here)
+  const int64_t nbs = std::max(nmfk::gram_share_blocks<T>(m, KP), nmfk::gram_share_blocks<T>(n, KP));
+  const size_t ogsl = cv.take<T>(nbs * KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   MuWork<T> w = mu_bind<T>(ctx, off);
+  T* gsl = nbs > 0 ? at<T>(ctx, ogsl) : nullptr;
   hipStream_t st = ctx->stream;
   HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, st));
   HIP_TRY(nmfk::transpose_in<T>(H, k, n, w.Ht, KP, st));
   Prob<T> pb;
   if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
   const int64_t slot = (m + n) * KP;
-  bool ft = false;
+  bool ft = false, qready = false;
   for (int t = 0; t < iters; ++t) {
     if (ckpt && t % every == 0) {
       T* c = ckpt + (int64_t)(t / every) * slot;
@@ -1600,7 +1622,7 @@ nmf_status mu_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64
       HIP_TRY(hipMemcpyAsync(c + m * KP, w.Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
     }
     s = mu_iteration<T>(ctx, pb, m, n, k, KP, eps, w.W, w.Ht, w.W, w.Ht, nullptr, w.Q, nullptr,
-                        w.S, w, &ft);
+                        w.S, w, &ft, nullptr, nullptr, gsl, &qready);
     if (s != NMF_OK) return s;
   }
   HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
@@ -1640,6 +1662,9 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
   // the adjoints' per-block shares of the Gram gradients
   const int64_t nbm = nmfk::mu_adjoint_blocks<T>(m, KP), nbn = nmfk::mu_adjoint_blocks<T>(n, KP);
   const size_t ogsl = cv.take<T>(std::max(nbm, nbn) * KP * KP);
+  // the recomputation's Gram shares
+  const int64_t nbs = std::max(nmfk::gram_share_blocks<T>(m, KP), nmfk::gram_share_blocks<T>(n, KP));
+  const size_t orsl = cv.take<T>(nbs * KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   MuWork<T> w = mu_bind<T>(ctx, off);
@@ -1649,6 +1674,7 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
   T *gD = at<T>(ctx, ogD), *tmp = at<T>(ctx, otmp), *gG = at<T>(ctx, ogG), *gGs = at<T>(ctx, ogGs);
   T *Qts = at<T>(ctx, oQts), *Sts = at<T>(ctx, oSts), *gGt = at<T>(ctx, ogGt);
   T* gsl = at<T>(ctx, ogsl);
+  T* rsl = nbs > 0 ? at<T>(ctx, orsl) : nullptr;
   hipStream_t st = ctx->stream;
   const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
   HIP_TRY(nmfk::pad_rows<T>(gWT, m, k, gW, KP, st));
@@ -1671,12 +1697,12 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
     HIP_TRY(hipMemcpyAsync(Ws, ckpt + j * slot, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(Hs, ckpt + j * slot + m * KP, sizeof(T) * n * KP,
                            hipMemcpyDeviceToDevice, st));
-    bool ft = false;
+    bool ft = false, qready = false;
     for (int i = 0; i < L; ++i) {
       s = mu_iteration<T>(ctx, pb, m, n, k, KP, eps, Ws + i * m * KP, Hs + i * n * KP,
                           Ws + (i + 1) * m * KP, Hs + (i + 1) * n * KP, Ps + i * m * KP,
                           Qs + i * KP * KP, Rs + i * n * KP, Ss + i * KP * KP, w, &ft,
-                          Qts + i * KP * KP, Sts + i * KP * KP);
+                          Qts + i * KP * KP, Sts + i * KP * KP, rsl, &qready);
       if (s != NMF_OK) return s;
     }
     for (int i = L - 1; i >= 0; --i) {

@@ -156,6 +156,31 @@ __device__ __forceinline__ void slab_sum(const T* p, int n, int64_t stride, doub
   }
 }
 
+// slab[a][b] = sum_q Xs[q][a] Ds[q][b] over a block's ROWS staged rows (LDS,
+// pitch LD): the block's share of the Gram product X^T D, on the matrix
+// cores. The block's waves take the 16 x 16 output tiles in turn; each tile
+// runs down the rows four at a time (lane l: row k0 + l / 16, column l % 16
+// of both operands). Rows past the end are zero in both.
+template <typename T, int KP, int ROWS, int LD>
+__device__ __forceinline__ void block_gram_partial(const T* Xs, const T* Ds, T* __restrict__ slab) {
+  constexpr int NTL = KP / 16, TILES = NTL * NTL;
+  typedef typename Tr<T>::acc4 acc4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  for (int t = wave; t < TILES; t += nwaves) {
+    const int a0 = (t / NTL) * 16, b0 = (t % NTL) * 16;
+    acc4 acc = zero4<T>();
+#pragma unroll 8
+    for (int k0 = 0; k0 < ROWS; k0 += 4) {
+      const int q = k0 + (lane >> 4);
+      acc = mfma16(Xs[q * LD + a0 + (lane & 15)], Ds[q * LD + b0 + (lane & 15)], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      slab[(a0 + acc_row<T>(lane, r)) * KP + b0 + (lane & 15)] = acc[r];
+  }
+}
+
 // Writes rows [rb, rb + ROWS) of a rows x KP block held in LDS as
 // tile[q * LD + i] (q = row - rb) to out[i * rows + row]. Column i's rows of
 // the block go out as whole 16-byte runs when rows is a multiple of VEC (out

@@ -28,7 +28,7 @@ namespace nmfk {
 // sums) and store nothing. TPR (4, 8 or 16 lanes per row) is chosen from the
 // number of rows: many rows fill the chip with small groups, which take fewer
 // permutation steps per column; few rows need larger groups to fill it.
-template <typename T, int KP, int TPR>
+template <typename T, int KP, int TPR, bool TOUT, bool SLABS>
 __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, Split<T> P,
                                                             const T* __restrict__ G,
                                                             int64_t rows, int k,
@@ -37,7 +37,9 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, S
   constexpr int VEC = Tr<T>::VEC;
   constexpr int XLD = KP + VEC;
   __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
-  __shared__ __attribute__((aligned(16))) T Xs[KP <= 64 ? ROWS * XLD : VEC];
+  // the output tile for the transposed store only when one is asked for
+  // (TOUT): the sweep runs with many blocks per CU, whose LDS it would share
+  __shared__ __attribute__((aligned(16))) T Xs[TOUT && KP <= 64 ? ROWS * XLD : VEC];
   const int sub = threadIdx.x % TPR;
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
   const int64_t r = rb + threadIdx.x / TPR;
@@ -49,12 +51,18 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, S
   T x[R], p[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) x[q] = X[rr * KP + sub * R + q];
-  double ps[R];
+  if constexpr (SLABS) {
+    double ps[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) ps[q] = 0.0;
-  slab_sum<T, R>(P.p + rr * KP + sub * R, P.n, P.stride, ps);
+    for (int q = 0; q < R; ++q) ps[q] = 0.0;
+    slab_sum<T, R>(P.p + rr * KP + sub * R, P.n, P.stride, ps);
 #pragma unroll
-  for (int q = 0; q < R; ++q) p[q] = (T)ps[q];
+    for (int q = 0; q < R; ++q) p[q] = (T)ps[q];
+  } else {
+    // one slab: the product itself (a sum of one term rounds to itself)
+#pragma unroll
+    for (int q = 0; q < R; ++q) p[q] = P.p[rr * KP + sub * R + q];
+  }
   gst.store_t(Gs);
   __syncthreads();
 #pragma unroll
@@ -78,8 +86,7 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, S
 #pragma unroll
     for (int q = 0; q < R; ++q) Xn[r * KP + sub * R + q] = x[q];
   }
-  if constexpr (KP <= 64) {
-    if (Xt == nullptr) return;  // uniform over the block
+  if constexpr (TOUT && KP <= 64) {
 #pragma unroll
     for (int q = 0; q < R; ++q) Xs[(threadIdx.x / TPR) * XLD + sub * R + q] = x[q];
     __syncthreads();
@@ -102,11 +109,12 @@ template <int KP> struct RowSplit {
   static constexpr int ROWS = 256 / TPR;
 };
 
-template <typename T, int KP>
+template <typename T, int KP, bool SLABS>
 __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(const T* X, T* Xn, Split<T> P,
                                                           const T* __restrict__ G, int64_t rows,
                                                           int k, T eps, T* __restrict__ Xt,
-                                                          T* __restrict__ Pout) {
+                                                          T* __restrict__ Pout,
+                                                          T* __restrict__ Gslab) {
   constexpr int TPR = RowSplit<KP>::TPR, RPT = RowSplit<KP>::RPT, ROWS = RowSplit<KP>::ROWS;
   constexpr int VEC = Tr<T>::VEC;
   static_assert(RPT % VEC == 0, "16-byte reads of G");
@@ -127,7 +135,15 @@ __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(const T* X, T* Xn, Spl
   double ps[RPT];
 #pragma unroll
   for (int ii = 0; ii < RPT; ++ii) ps[ii] = 0.0;
-  if (live) slab_sum<T, RPT>(P.p + r * KP + i0, P.n, P.stride, ps);
+  if (live) {
+    if constexpr (SLABS) {
+      slab_sum<T, RPT>(P.p + r * KP + i0, P.n, P.stride, ps);
+    } else {
+      // one slab: the product itself (a sum of one term rounds to itself)
+#pragma unroll
+      for (int ii = 0; ii < RPT; ++ii) ps[ii] = (double)P.p[r * KP + i0 + ii];
+    }
+  }
   gst.store(Gs);
   xst.store(Xs, rb, rows);
   __syncthreads();
@@ -158,12 +174,29 @@ __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(const T* X, T* Xn, Spl
       Xn[r * KP + i] = out[ii];
     }
   }
-  if (Xt == nullptr) return;  // uniform over the block
+  if (Xt == nullptr && Gslab == nullptr) return;  // uniform over the block
   __syncthreads();            // every read of the staged rows is done
 #pragma unroll
   for (int ii = 0; ii < RPT; ++ii) Xs[lr * XLD + i0 + ii] = out[ii];
   __syncthreads();
-  store_rows_transposed<T, KP, ROWS, XLD>(Xs, rb, rows, Xt);
+  // the block's share of Xn^T Xn (rows past the end are zero)
+  if (Gslab) block_gram_partial<T, KP, ROWS, XLD>(Xs, Xs, Gslab + (int64_t)blockIdx.x * KP * KP);
+  if (Xt) store_rows_transposed<T, KP, ROWS, XLD>(Xs, rb, rows, Xt);
+}
+
+// The block's share of X^T X for the rows x KP factor X (slab blockIdx.x,
+// KP x KP), with the row blocks and the order of mu_rows_tpr_kernel's shares,
+// so that either gives the same Gram after the ordered sum.
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void gram_rows_kernel(const T* __restrict__ X, int64_t rows,
+                                                        T* __restrict__ Gslab) {
+  constexpr int ROWS = RowSplit<KP>::ROWS;
+  constexpr int XLD = KP + Tr<T>::VEC;
+  __shared__ __attribute__((aligned(16))) T Xs[ROWS * XLD];
+  const int64_t rb = (int64_t)blockIdx.x * ROWS;
+  stage_rows<T, KP, ROWS, XLD, 256>(Xs, X, rb, rows);
+  __syncthreads();
+  block_gram_partial<T, KP, ROWS, XLD>(Xs, Xs, Gslab + (int64_t)blockIdx.x * KP * KP);
 }
 
 // MU at ranks above 64: each thread's row kept in LDS (column tid of a
@@ -207,30 +240,87 @@ __global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(const T* X, T* Xn
       FALLBACK;                                                \
   }
 
+// One slab (the product as it came) needs no double accumulation: that form
+// keeps fewer registers live.
+template <typename T, int KP>
+void launch_mu_rows_tpr(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, T eps,
+                        T* Xt, T* Pout, T* Gslab, hipStream_t st) {
+  const unsigned nb = (unsigned)cdiv(rows, RowSplit<KP>::ROWS);
+  if (P.n > 1)
+    mu_rows_tpr_kernel<T, KP, true><<<nb, 256, 0, st>>>(X, Xn, P, G, rows, k, eps, Xt, Pout,
+                                                          Gslab);
+  else
+    mu_rows_tpr_kernel<T, KP, false><<<nb, 256, 0, st>>>(X, Xn, P, G, rows, k, eps, Xt, Pout,
+                                                           Gslab);
+}
+
 template <typename T>
 hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
-                   T* Xt, T* Pout, hipStream_t st) {
+                   T* Xt, T* Pout, T* Gslab, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  if ((Xt && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
-  KP_SWITCH(KP, (mu_rows_tpr_kernel<T, KPc><<<(unsigned)cdiv(rows, RowSplit<KPc>::ROWS), 256,
-                                               0, st>>>(X, Xn, P, G, rows, k, eps, Xt, Pout)),
+  if (((Xt || Gslab) && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
+  KP_SWITCH(KP, (launch_mu_rows_tpr<T, KPc>(X, Xn, P, G, rows, k, eps, Xt, Pout, Gslab, st)),
             (mu_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
                 X, Xn, P, G, rows, k, KP, eps, Pout)));
   return NMF_LAUNCH_CHECK();
 }
 
+template <typename T>
+int64_t gram_share_blocks(int64_t rows, int KP) {
+  switch (KP) {
+    case 16: return cdiv(rows, RowSplit<16>::ROWS);
+    case 32: return cdiv(rows, RowSplit<32>::ROWS);
+    case 48: return cdiv(rows, RowSplit<48>::ROWS);
+    case 64: return cdiv(rows, RowSplit<64>::ROWS);
+    default: return 0;
+  }
+}
+
+template <typename T>
+hipError_t gram_shares(const T* X, int64_t rows, int KP, T* Gslab, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  switch (KP) {
+#define CASE(K)                                                                              \
+  case K:                                                                                    \
+    gram_rows_kernel<T, K><<<(unsigned)cdiv(rows, RowSplit<K>::ROWS), 256, 0, st>>>(X, rows,   \
+                                                                                  Gslab);    \
+    break;
+    CASE(16) CASE(32) CASE(48) CASE(64)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return NMF_LAUNCH_CHECK();
+}
+
+template <typename T, int KP, bool TOUT, bool SLABS>
+void launch_hals_grp_t(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int tpr,
+                       T* Xt, hipStream_t st) {
+  if (tpr == 4)
+    hals_rows_grp_kernel<T, KP, 4, TOUT, SLABS><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(
+        X, Xn, P, G, rows, k, Xt);
+  else if (tpr == 8)
+    hals_rows_grp_kernel<T, KP, 8, TOUT, SLABS><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(
+        X, Xn, P, G, rows, k, Xt);
+  else
+    hals_rows_grp_kernel<T, KP, 16, TOUT, SLABS><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(
+        X, Xn, P, G, rows, k, Xt);
+}
+
+// The sweep on its own (nmf_dense: no transposed copy, one slab) keeps the
+// small register and LDS footprint that lets many blocks share a CU; the
+// unrolled layers' form (product slabs, transposed copy) is a variant.
 template <typename T, int KP>
 void launch_hals_grp(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int tpr,
                      T* Xt, hipStream_t st) {
-  if (tpr == 4)
-    hals_rows_grp_kernel<T, KP, 4><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(X, Xn, P, G, rows,
-                                                                             k, Xt);
-  else if (tpr == 8)
-    hals_rows_grp_kernel<T, KP, 8><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(X, Xn, P, G, rows,
-                                                                             k, Xt);
-  else
-    hals_rows_grp_kernel<T, KP, 16><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(X, Xn, P, G, rows,
-                                                                              k, Xt);
+  if constexpr (KP <= 64) {
+    if (Xt) {
+      if (P.n > 1) launch_hals_grp_t<T, KP, true, true>(X, Xn, P, G, rows, k, tpr, Xt, st);
+      else launch_hals_grp_t<T, KP, true, false>(X, Xn, P, G, rows, k, tpr, Xt, st);
+      return;
+    }
+  }
+  if (P.n > 1) launch_hals_grp_t<T, KP, false, true>(X, Xn, P, G, rows, k, tpr, Xt, st);
+  else launch_hals_grp_t<T, KP, false, false>(X, Xn, P, G, rows, k, tpr, Xt, st);
 }
 
 template <typename T>
@@ -304,10 +394,14 @@ __global__ void hals_scale_kernel(const T* W, T* Wn, int64_t m, const T* Ht, T* 
     const int i = (int)(e - r * KP);
     const T s = i < k ? norms[i] : T(0);
     const bool sc = s > T(0);
+    // entries that do not change are not touched in place (the padding and
+    // the zero columns), only copied out of place
     if (r < m) {
+      if (!sc && Wn == W) continue;
       const T v = W[r * KP + i];
       Wn[r * KP + i] = sc ? v / s : v;
     } else {
+      if (!sc && Htn == Ht) continue;
       const T v = Ht[(r - m) * KP + i];
       Htn[(r - m) * KP + i] = sc ? v * s : v;
     }
@@ -551,7 +645,9 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
 
 #define INST(T)                                                                             \
   template hipError_t mu_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T, T*, \
-                                 T*, hipStream_t); \
+                                 T*, T*, hipStream_t); \
+  template int64_t gram_share_blocks<T>(int64_t, int); \
+  template hipError_t gram_shares<T>(const T*, int64_t, int, T*, hipStream_t); \
   template hipError_t hals_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T*, \
                                    hipStream_t);                                            \
   template hipError_t hals_normalize<T>(const T*, T*, int64_t, const T*, T*, int64_t, T*, T*, \
