@@ -149,6 +149,47 @@ int64_t gram_splits(int64_t rows) {
   return big <= 1024 ? 1024 : (big > 4096 ? 4096 : big);
 }
 
+// Grams from the updates' row-block shares (MU and HALS at ranks up to 64):
+// each update writes its blocks' shares of its output's Gram, and one ordered
+// sum (reduce_splits) forms it, so the factor is not read again for its
+// Gram and no Gram kernel is launched. A share is KP x KP for a block of
+// 16-128 rows, about as large as the rows it covers, so past SHARE_CAP
+// blocks (2^17-2^19 rows) the separate Gram, whose slabs grow to at least
+// 1024 rows, moves fewer bytes and is used instead. At 65,536 rows and KP =
+// 64 (2048 MU shares) the shares took 49.5 us per iteration against 57.6 us
+// for the separate Grams. The same rule holds in the plain iteration and in
+// the unrolled layers, so their Grams agree bit for bit.
+constexpr int64_t SHARE_CAP = 4096;
+struct Shares {
+  int rpm = 0, rpn = 0;       // rows per block for W and for H^T (0: no shares)
+  int64_t nbm = 0, nbn = 0;   // blocks, that is shares, of each
+  bool on() const { return rpm > 0; }
+  int64_t blocks() const { return std::max(nbm, nbn); }
+};
+
+Shares plan_shares(int algo, int64_t m, int64_t n, int KP) {
+  Shares sh;
+  if (algo != NMF_MU && algo != NMF_HALS) return sh;
+  const nmfk::ShareOf u = algo == NMF_MU ? nmfk::ShareOf::MU : nmfk::ShareOf::HALS;
+  const int rpm = nmfk::share_rows(u, m, KP), rpn = nmfk::share_rows(u, n, KP);
+  if (rpm <= 0 || rpn <= 0) return sh;
+  const int64_t nbm = cdiv(m, rpm), nbn = cdiv(n, rpn);
+  if (nbm > SHARE_CAP || nbn > SHARE_CAP) return sh;
+  sh.rpm = rpm;
+  sh.rpn = rpn;
+  sh.nbm = nbm;
+  sh.nbn = nbn;
+  return sh;
+}
+
+// G = the ordered sum of nb shares at gsl (Gt, nullable: its transpose).
+template <typename T>
+nmf_status sum_shares(nmf_ctx* ctx, const T* gsl, int64_t nb, int KP, T* G, T* Gt = nullptr) {
+  HIP_TRY(nmfk::reduce_splits<T>(gsl, (int)nb, (int64_t)KP * KP, KP, KP, KP, G, KP, ctx->stream,
+                                 Gt));
+  return NMF_OK;
+}
+
 nmf_status bind_device(nmf_ctx* ctx) {
   if (ctx->device < 0) return fail(ctx, NMF_EDEVICE, "context is not bound to a device");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, NMF_EDEVICE, "hipSetDevice failed");
@@ -256,16 +297,19 @@ struct StopInfo {
 
 // status points at 4 device ints: [0] ABPP flags, [1] input check, [2] G^-1 ok.
 // ginv: KP*KP doubles of scratch for ABPP.
+// Gslab (nullable; MU and HALS at KP <= 64): receives the row blocks' shares
+// of the updated factor's Gram.
 template <typename T>
 nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, int64_t rows,
                         int k, int KP, const nmf_opts* o, int* status,
-                        unsigned long long* pivots, double* ginv) {
+                        unsigned long long* pivots, double* ginv, T* Gslab = nullptr) {
   hipStream_t st = ctx->stream;
   if (algo == NMF_MU)
     HIP_TRY(nmfk::mu_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, (T)o->eps_mu,
-                             nullptr, nullptr, nullptr, st));
+                             nullptr, nullptr, Gslab, st));
   else if (algo == NMF_HALS)
-    HIP_TRY(nmfk::hals_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, nullptr, st));
+    HIP_TRY(nmfk::hals_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, nullptr, Gslab,
+                               st));
   else {
     const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
     // the incoming X (the current iterate) starts each right-hand side's pivoting
@@ -295,6 +339,10 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   part = std::max<int64_t>(part, ps_r > 1 ? ps_r * n * KP : 0);
   part = std::max<int64_t>(part, gram_splits(std::max(m, n)) * KP * KP);
   part = std::max<int64_t>(part, extra_part);
+  // the updates' Gram shares, for either update that writes them
+  part = std::max<int64_t>(part, std::max(plan_shares(NMF_MU, m, n, KP).blocks(),
+                                          plan_shares(NMF_HALS, m, n, KP).blocks()) *
+                                     KP * KP);
   off[0] = cv.take<T>(m * KP);
   off[1] = cv.take<T>(n * KP);
   off[2] = cv.take<T>(m * KP);
@@ -462,15 +510,18 @@ nmf_status product_AtF(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, co
 // whether w.Q holds the Gram of the current Ht (the sparse form needs it).
 template <typename T>
 nmf_status objective(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
-                     Work<T>& w, int slot) {
+                     Work<T>& w, int slot, bool grams_current = false) {
   hipStream_t st = ctx->stream;
   if (pb.sparse) {
     if constexpr (sizeof(T) == 4) {
-      // <W^T W, H H^T> covers the zeros; both Grams of the current factors.
-      nmf_status s = gram<T>(ctx, w.W, m, KP, w.S, w.part);
-      if (s != NMF_OK) return s;
-      s = gram<T>(ctx, w.Ht, n, KP, w.Q, w.part);
-      if (s != NMF_OK) return s;
+      // <W^T W, H H^T> covers the zeros; both Grams of the current factors
+      // (already in S and Q when grams_current).
+      if (!grams_current) {
+        nmf_status s = gram<T>(ctx, w.W, m, KP, w.S, w.part);
+        if (s != NMF_OK) return s;
+        s = gram<T>(ctx, w.Ht, n, KP, w.Q, w.part);
+        if (s != NMF_OK) return s;
+      }
       HIP_TRY(nmfk::csr_residual_sq(pb.rp, pb.ci, pb.cv, m, w.W, w.Ht, KP, w.obj_part, st));
       HIP_TRY(nmfk::finish_relerr<T>(w.obj_part, nmfk::csr_residual_partials(m), w.S, w.Q, KP,
                                      w.normA, w.relerr + slot, st));
@@ -573,10 +624,20 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   const bool tH = big && !pb.sparse && !pb.lp && (n * (int64_t)sizeof(T)) % 16 == 0;
   const bool tW = big && !pb.sparse && !pb.lp && (m * (int64_t)sizeof(T)) % 16 == 0;
   if (tH && o->iters > 0) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
+  // the updates' Gram shares go to w.part and are summed before the next
+  // product uses it; qready: Q already holds the current H's Gram
+  const Shares sh = plan_shares(o->algo, m, n, KP);
+  T* gsl = sh.on() ? w.part : nullptr;
+  bool qready = false;
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
     tm.mark(PH_GRAM);
-    RUN(gram<T>(ctx, w.Ht, n, KP, w.Q, w.part));
+    if (!sh.on()) {
+      RUN(gram<T>(ctx, w.Ht, n, KP, w.Q, w.part));
+    } else if (!qready) {
+      HIP_TRY(nmfk::gram_shares<T>(w.Ht, n, KP, sh.rpn, gsl, st));
+      RUN(sum_shares<T>(ctx, gsl, sh.nbn, KP, w.Q));
+    }
     tm.mark(PH_MM);
     RUN(product_AF<T>(ctx, pb, m, n, w.Ht, tH ? w.Hk : nullptr, k, KP, w.P, w.part));
     if (pgstop) {
@@ -593,10 +654,12 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
       }
     }
     tm.mark(PH_LUC);
-    RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv));
+    RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv,
+                        gsl));
     // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
     tm.mark(PH_GRAM);
-    RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
+    if (sh.on()) RUN(sum_shares<T>(ctx, gsl, sh.nbm, KP, w.S));
+    else RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
     if (o->algo == NMF_HALS) {
       tm.mark(PH_LUC);
       HIP_TRY(nmfk::hals_normalize<T>(w.W, w.W, m, w.Ht, w.Ht, n, w.S, w.norms, k, KP, st));
@@ -605,7 +668,14 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     tm.mark(PH_MM_T);
     RUN(product_AtF<T>(ctx, pb, m, n, w.W, tW ? w.Wt : nullptr, k, KP, w.R, w.part));
     tm.mark(PH_LUC);
-    RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots, w.ginv));
+    RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots, w.ginv,
+                        gsl));
+    if (sh.on()) {
+      // the next iteration's Q, from the H update's shares
+      tm.mark(PH_GRAM);
+      RUN(sum_shares<T>(ctx, gsl, sh.nbn, KP, w.Q));
+      qready = true;
+    }
     if (tH && t + 1 < o->iters) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
     if (pgstop) {
       tm.mark(PH_OBJ);
@@ -613,7 +683,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     }
     if (want_obj) {
       tm.mark(PH_OBJ);
-      RUN(objective<T>(ctx, pb, m, n, k, KP, w, t + 1));
+      RUN(objective<T>(ctx, pb, m, n, k, KP, w, t + 1, sh.on()));
     }
     if (errstop) {
       double e[2];
@@ -1545,12 +1615,13 @@ bool rows_transposable(int64_t rows, int KP) {
 // and R are set (nullable). The products reach the updates as their split
 // slabs. *ft: on entry, whether w.Ft holds Ht's transposed copy; on return,
 // whether it holds Htn's (the update writes it for the next iteration's
-// product). With gsl set (KP <= 64), the Grams are summed from row-block
-// shares: each update writes the shares of its output's Gram into gsl, and
-// *qready says whether gsl holds Ht's on entry (else they are formed here);
-// on return it holds Htn's. The shares' blocking and order are the same
-// whichever kernel forms them, so a recomputation from a checkpoint repeats
-// the Grams of the first pass bit for bit.
+// product). With gsl set (room for plan_shares' blocks), the Grams are
+// summed from row-block shares where plan_shares takes them: each update
+// writes the shares of its output's Gram into gsl, and *qready says whether
+// gsl holds Ht's on entry (else they are formed here); on return it holds
+// Htn's. The shares' blocking and order are the same whichever kernel forms
+// them, so a recomputation from a checkpoint repeats the Grams of the first
+// pass bit for bit.
 template <typename T>
 nmf_status mu_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
                         T eps, const T* W, const T* Ht, T* Wn, T* Htn, T* P, T* Q, T* R, T* S,
@@ -1562,11 +1633,11 @@ nmf_status mu_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, i
   nmfk::Split<T> sp;
   T* Pd = P ? P : w.P;
   T* Rd = R ? R : w.R;
-  const int64_t nbm = gsl ? nmfk::gram_share_blocks<T>(m, KP) : 0;
-  const int64_t nbn = gsl ? nmfk::gram_share_blocks<T>(n, KP) : 0;
+  const Shares sh = gsl ? plan_shares(NMF_MU, m, n, KP) : Shares{};
+  if (!sh.on()) gsl = nullptr;
   if (gsl) {
-    if (!*qready) HIP_TRY(nmfk::gram_shares<T>(Ht, n, KP, gsl, st));
-    HIP_TRY(nmfk::reduce_splits<T>(gsl, (int)nbn, KP * KP, KP, KP, KP, Q, KP, st, Qt));
+    if (!*qready) HIP_TRY(nmfk::gram_shares<T>(Ht, n, KP, sh.rpn, gsl, st));
+    if ((s = sum_shares<T>(ctx, gsl, sh.nbn, KP, Q, Qt)) != NMF_OK) return s;
   } else if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part, Qt)) != NMF_OK) {
     return s;
   }
@@ -1574,7 +1645,7 @@ nmf_status mu_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, i
   HIP_TRY(nmfk::mu_rows<T>(W, Wn, sp, Q, m, k, KP, eps, tW ? w.Ft : nullptr,
                            sp.n > 1 ? P : nullptr, gsl, st));
   if (gsl) {
-    HIP_TRY(nmfk::reduce_splits<T>(gsl, (int)nbm, KP * KP, KP, KP, KP, S, KP, st, St));
+    if ((s = sum_shares<T>(ctx, gsl, sh.nbm, KP, S, St)) != NMF_OK) return s;
   } else if ((s = gram<T>(ctx, Wn, m, KP, S, w.part, St)) != NMF_OK) {
     return s;
   }
@@ -1601,8 +1672,8 @@ nmf_status mu_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int64
   Carve cv;
   size_t off[8];
   mu_plan_common<T>(m, n, KP, cv, off);
-  // the updates' Gram shares (k <= 64 here)
-  const int64_t nbs = std::max(nmfk::gram_share_blocks<T>(m, KP), nmfk::gram_share_blocks<T>(n, KP));
+  // the updates' Gram shares
+  const int64_t nbs = plan_shares(NMF_MU, m, n, KP).blocks();
   const size_t ogsl = cv.take<T>(nbs * KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
@@ -1663,7 +1734,7 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
   const int64_t nbm = nmfk::mu_adjoint_blocks<T>(m, KP), nbn = nmfk::mu_adjoint_blocks<T>(n, KP);
   const size_t ogsl = cv.take<T>(std::max(nbm, nbn) * KP * KP);
   // the recomputation's Gram shares
-  const int64_t nbs = std::max(nmfk::gram_share_blocks<T>(m, KP), nmfk::gram_share_blocks<T>(n, KP));
+  const int64_t nbs = plan_shares(NMF_MU, m, n, KP).blocks();
   const size_t orsl = cv.take<T>(nbs * KP * KP);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
@@ -1767,25 +1838,39 @@ nmf_status mu_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int6
 // sweep. Wp and Hc (nullable) receive W after the sweep and H^T after the
 // rescaling, which the backward pass needs; every step writes its output
 // where the next one reads it, so nothing is copied. *ft: on entry, whether
-// w.Ft holds Ht's transposed copy; on return, whether it holds Htn's.
+// w.Ft holds Ht's transposed copy; on return, whether it holds Htn's. gsl
+// and *qready: the Gram shares, as for mu_iteration (with the sweeps'
+// blocking).
 template <typename T>
 nmf_status hals_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int k, int KP,
                           const T* W, const T* Ht, T* Wn, T* Htn, T* Wp, T* Hc, T* nrm, T* Q,
-                          T* S, MuWork<T>& w, bool* ft) {
+                          T* S, MuWork<T>& w, bool* ft, T* gsl, bool* qready) {
   hipStream_t st = ctx->stream;
   nmf_status s;
   const bool tH = rows_transposable<T>(n, KP);
   nmfk::Split<T> sp;
   T* Wsw = Wp ? Wp : Wn;    // the W sweep's output
   T* Hsc = Hc ? Hc : Htn;   // H^T after the rescaling
-  if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part)) != NMF_OK) return s;
+  const Shares sh = gsl ? plan_shares(NMF_HALS, m, n, KP) : Shares{};
+  if (!sh.on()) gsl = nullptr;
+  if (gsl) {
+    if (!*qready) HIP_TRY(nmfk::gram_shares<T>(Ht, n, KP, sh.rpn, gsl, st));
+    if ((s = sum_shares<T>(ctx, gsl, sh.nbn, KP, Q)) != NMF_OK) return s;
+  } else if ((s = gram<T>(ctx, Ht, n, KP, Q, w.part)) != NMF_OK) {
+    return s;
+  }
   if ((s = mu_prod_AF<T>(ctx, pb, m, n, Ht, k, KP, w.P, w, *ft, &sp)) != NMF_OK) return s;
-  HIP_TRY(nmfk::hals_rows<T>(W, Wsw, sp, Q, m, k, KP, nullptr, st));
-  if ((s = gram<T>(ctx, Wsw, m, KP, S, w.part)) != NMF_OK) return s;
+  HIP_TRY(nmfk::hals_rows<T>(W, Wsw, sp, Q, m, k, KP, nullptr, gsl, st));
+  if (gsl) {
+    if ((s = sum_shares<T>(ctx, gsl, sh.nbm, KP, S)) != NMF_OK) return s;
+  } else if ((s = gram<T>(ctx, Wsw, m, KP, S, w.part)) != NMF_OK) {
+    return s;
+  }
   HIP_TRY(nmfk::hals_normalize<T>(Wsw, Wn, m, Ht, Hsc, n, S, nrm, k, KP, st));
   if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, w.R, w, false, &sp)) != NMF_OK) return s;
-  HIP_TRY(nmfk::hals_rows<T>(Hsc, Htn, sp, S, n, k, KP, tH ? w.Ft : nullptr, st));
+  HIP_TRY(nmfk::hals_rows<T>(Hsc, Htn, sp, S, n, k, KP, tH ? w.Ft : nullptr, gsl, st));
   *ft = tH;
+  if (gsl) *qready = true;
   return NMF_OK;
 }
 
@@ -1797,17 +1882,20 @@ nmf_status hals_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int
   size_t off[8];
   mu_plan_common<T>(m, n, KP, cv, off);
   const size_t onrm = cv.take<T>(KP);
+  const int64_t nbs = plan_shares(NMF_HALS, m, n, KP).blocks();
+  const size_t ogsl = cv.take<T>(nbs * KP * KP);   // the sweeps' Gram shares
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;
   MuWork<T> w = mu_bind<T>(ctx, off);
   T* nrm = at<T>(ctx, onrm);
+  T* gsl = nbs > 0 ? at<T>(ctx, ogsl) : nullptr;
   hipStream_t st = ctx->stream;
   HIP_TRY(nmfk::pad_rows<T>(W, m, k, w.W, KP, st));
   HIP_TRY(nmfk::transpose_in<T>(H, k, n, w.Ht, KP, st));
   Prob<T> pb;
   if (iters > 0 && (s = mu_prepare_A<T>(ctx, A, lda, m, n, pb)) != NMF_OK) return s;
   const int64_t slot = (m + n) * KP;
-  bool ft = false;
+  bool ft = false, qready = false;
   for (int t = 0; t < iters; ++t) {
     if (ckpt && t % every == 0) {
       T* c = ckpt + (int64_t)(t / every) * slot;
@@ -1815,7 +1903,7 @@ nmf_status hals_forward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int
       HIP_TRY(hipMemcpyAsync(c + m * KP, w.Ht, sizeof(T) * n * KP, hipMemcpyDeviceToDevice, st));
     }
     s = hals_iteration<T>(ctx, pb, m, n, k, KP, w.W, w.Ht, w.W, w.Ht, nullptr, nullptr, nrm,
-                          w.Q, w.S, w, &ft);
+                          w.Q, w.S, w, &ft, gsl, &qready);
     if (s != NMF_OK) return s;
   }
   HIP_TRY(nmfk::unpad_rows<T>(w.W, m, k, KP, W, st));
@@ -1858,6 +1946,9 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   // the reverse sweeps' per-block shares of their two Gram products
   const int64_t hbm = nmfk::hals_adjoint_blocks<T>(m, KP), hbn = nmfk::hals_adjoint_blocks<T>(n, KP);
   const size_t otsl = cv.take<T>(2 * std::max(hbm, hbn) * KP * KP);
+  // the recomputation's Gram shares
+  const int64_t nbs = plan_shares(NMF_HALS, m, n, KP).blocks();
+  const size_t orsl = cv.take<T>(nbs * KP * KP);
   const size_t odots = cv.take<double>(2 * KP);
   const size_t odpart = cv.take<double>(nmfk::coldot_partials(KP));
   nmf_status s = ensure_ws(ctx, cv.off);
@@ -1871,6 +1962,7 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
   T *tmp = at<T>(ctx, otmp), *M = at<T>(ctx, oM);
   double *dots = at<double>(ctx, odots), *dpart = at<double>(ctx, odpart);
   T* tsl = at<T>(ctx, otsl);
+  T* rsl = nbs > 0 ? at<T>(ctx, orsl) : nullptr;
   hipStream_t st = ctx->stream;
   const bool tW = rows_transposable<T>(m, KP), tH = rows_transposable<T>(n, KP);
   nmfk::Split<T> yp{nullptr, 0, 0};
@@ -1887,12 +1979,12 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
     HIP_TRY(hipMemcpyAsync(Ws, ckpt + j * slot, sizeof(T) * m * KP, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(Hs, ckpt + j * slot + m * KP, sizeof(T) * n * KP,
                            hipMemcpyDeviceToDevice, st));
-    bool ft = false;
+    bool ft = false, qready = false;
     for (int i = 0; i < L; ++i) {
       s = hals_iteration<T>(ctx, pb, m, n, k, KP, Ws + i * m * KP, Hs + i * n * KP,
                             Ws + (i + 1) * m * KP, Hs + (i + 1) * n * KP, Wps + i * m * KP,
                             Hcs + i * n * KP, Ns + i * KP, Qs + i * KP * KP, Ss + i * KP * KP, w,
-                            &ft);
+                            &ft, rsl, &qready);
       if (s != NMF_OK) return s;
     }
     for (int i = L - 1; i >= 0; --i) {

@@ -371,6 +371,26 @@ __global__ __launch_bounds__(256, WPE) void gemm_tn_kernel(
   }
 }
 
+// s += src[p * stride] for p = p0, p0 + step, ... < splits, added in that
+// order in double. The loads go out RS_BATCH at a time before any is added,
+// so a thread waits for one memory latency per batch rather than per slab.
+constexpr int RS_BATCH = 8;
+template <typename T>
+__device__ __forceinline__ double ordered_sum(const T* __restrict__ src, int p0, int step,
+                                              int splits, int64_t stride) {
+  double s = 0.0;
+  int p = p0;
+  for (; p + (RS_BATCH - 1) * step < splits; p += RS_BATCH * step) {
+    T v[RS_BATCH];
+#pragma unroll
+    for (int u = 0; u < RS_BATCH; ++u) v[u] = src[(int64_t)(p + u * step) * stride];
+#pragma unroll
+    for (int u = 0; u < RS_BATCH; ++u) s += (double)v[u];
+  }
+  for (; p < splits; p += step) s += (double)src[(int64_t)p * stride];
+  return s;
+}
+
 // out[i] = sum_s part[s * stride + i] in order s = 0, 1, ... (double sums);
 // outt (nullable) receives the transpose, outt[c * rows + r].
 template <typename T>
@@ -380,8 +400,7 @@ __global__ void reduce_splits_kernel(const T* __restrict__ part, int splits, int
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t r = idx / cols, cc = idx - r * cols;
-  double s = 0.0;
-  for (int p = 0; p < splits; ++p) s += (double)part[p * stride + r * ldp + cc];
+  const double s = ordered_sum<T>(part + r * ldp + cc, 0, 1, splits, stride);
   out[r * ldo + cc] = (T)s;
   if (outt) outt[cc * rows + r] = (T)s;
 }
@@ -401,10 +420,7 @@ __global__ __launch_bounds__(RS_OUT * RS_SUB) void reduce_splits_wide_kernel(
   const int64_t total = rows * cols;
   const int64_t r = idx / cols, cc = idx - r * cols;
   double s = 0.0;
-  if (idx < total) {
-    const T* src = part + r * ldp + cc;
-    for (int p = sub; p < splits; p += RS_SUB) s += (double)src[(int64_t)p * stride];
-  }
+  if (idx < total) s = ordered_sum<T>(part + r * ldp + cc, sub, RS_SUB, splits, stride);
   sh[sub][o] = s;
   __syncthreads();
   if (sub == 0 && idx < total) {

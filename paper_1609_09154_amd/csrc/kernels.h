@@ -78,22 +78,26 @@ hipError_t pack_fp8_t(const float* F, int64_t rows, int KP, uint8_t* Ft, int64_t
 
 // Local updates on rows x KP row-major factors (leading dimension KP); k is
 // the true rank, entries k..KP-1 are zero padding and stay zero.
-// mu_rows writes the updated rows of X to Xn (Xn == X: in place) and, when
-// Xt is set (KP <= 64), their transpose Xt[i * rows + r] as well; P is summed
-// from its slabs, and Pout (nullable) receives the sum. Gslab (nullable, KP
-// <= 64) receives the row blocks' shares of Xn^T Xn, one KP x KP slab per
-// block (gram_share_blocks of them), for an ordered sum (reduce_splits).
+// mu_rows and hals_rows write the updated rows of X to Xn (Xn == X: in
+// place) and, when Xt is set (KP <= 64), their transpose Xt[i * rows + r] as
+// well; P is summed from its slabs (mu_rows: Pout, nullable, receives the
+// sum). Gslab (nullable, KP <= 64) receives the row blocks' shares of
+// Xn^T Xn, one KP x KP slab per block of share_rows rows (cdiv(rows,
+// share_rows) of them), for an ordered sum (reduce_splits).
 template <typename T>
 hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
                    T* Xt, T* Pout, T* Gslab, hipStream_t st);
-// The same shares of X^T X for a factor that no update produced (KP <= 64).
-template <typename T>
-hipError_t gram_shares(const T* X, int64_t rows, int KP, T* Gslab, hipStream_t st);
-template <typename T>
-int64_t gram_share_blocks(int64_t rows, int KP);
 template <typename T>
 hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP,
-                     T* Xt, hipStream_t st);
+                     T* Xt, T* Gslab, hipStream_t st);
+// Rows per block of an update's Gram shares (0: the update writes none at
+// this KP): mu_rows at any row count, hals_rows at `rows` rows.
+enum class ShareOf { MU, HALS };
+int share_rows(ShareOf u, int64_t rows, int KP);
+// The same shares of X^T X over blocks of rpb rows (a share_rows value) for
+// a factor that no update produced (KP <= 64).
+template <typename T>
+hipError_t gram_shares(const T* X, int64_t rows, int KP, int rpb, T* Gslab, hipStream_t st);
 
 // HALS normalisation: s_i = sqrt(S[i][i]); W[:, i] /= s_i, Ht[:, i] *= s_i and
 // S[i][j] /= s_i s_j for s_i > 0. norms (nullable) receives s.

@@ -10,6 +10,14 @@
 
 namespace nmfk {
 
+template <typename T>
+__device__ __forceinline__ void store16(T* p, const V16<T>& r) {
+  if constexpr (sizeof(T) == 4)
+    *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  else
+    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
+}
+
 // Staging from global memory to LDS for the row kernels (NTHR threads per
 // block). Each thread issues all of its 16-byte loads (load) before its first
 // LDS write (store), so a block waits for one memory latency rather than one

@@ -28,18 +28,26 @@ namespace nmfk {
 // sums) and store nothing. TPR (4, 8 or 16 lanes per row) is chosen from the
 // number of rows: many rows fill the chip with small groups, which take fewer
 // permutation steps per column; few rows need larger groups to fill it.
-template <typename T, int KP, int TPR, bool TOUT, bool SLABS>
+// With TILE (KP <= 64), after the sweep the LDS that held G takes the
+// block's new rows (zero past the end) for their transposed copy (Xt,
+// nullable) and the block's share of Xn^T Xn (Gslab + blockIdx.x * KP * KP,
+// nullable), formed on the matrix cores. The tile shares G's space; only at
+// 64 rows per block does its padding need more (17 KB against 16 KB at KP =
+// 64), which the form without TILE, for calls that want neither output,
+// does not take.
+template <typename T, int KP, int TPR, bool SLABS, bool TILE>
 __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, Split<T> P,
                                                             const T* __restrict__ G,
                                                             int64_t rows, int k,
-                                                            T* __restrict__ Xt) {
+                                                            T* __restrict__ Xt,
+                                                            T* __restrict__ Gslab) {
   constexpr int R = KP / TPR, ROWS = 256 / TPR;
   constexpr int VEC = Tr<T>::VEC;
   constexpr int XLD = KP + VEC;
-  __shared__ __attribute__((aligned(16))) T Gs[KP * KP];
-  // the output tile for the transposed store only when one is asked for
-  // (TOUT): the sweep runs with many blocks per CU, whose LDS it would share
-  __shared__ __attribute__((aligned(16))) T Xs[TOUT && KP <= 64 ? ROWS * XLD : VEC];
+  constexpr int TS = TILE && KP <= 64 ? ROWS * XLD : 0;
+  constexpr int LS = KP * KP > TS ? KP * KP : TS;
+  __shared__ __attribute__((aligned(16))) T Ls[LS];
+  T* Gs = Ls;
   const int sub = threadIdx.x % TPR;
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
   const int64_t r = rb + threadIdx.x / TPR;
@@ -86,11 +94,15 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, S
 #pragma unroll
     for (int q = 0; q < R; ++q) Xn[r * KP + sub * R + q] = x[q];
   }
-  if constexpr (TOUT && KP <= 64) {
+  if constexpr (TILE && KP <= 64) {
+    if (Xt == nullptr && Gslab == nullptr) return;  // uniform over the block
+    __syncthreads();  // every read of G is done
+    const bool in = r < rows;
 #pragma unroll
-    for (int q = 0; q < R; ++q) Xs[(threadIdx.x / TPR) * XLD + sub * R + q] = x[q];
+    for (int q = 0; q < R; ++q) Ls[(threadIdx.x / TPR) * XLD + sub * R + q] = in ? x[q] : T(0);
     __syncthreads();
-    store_rows_transposed<T, KP, ROWS, XLD>(Xs, rb, rows, Xt);
+    if (Gslab) block_gram_partial<T, KP, ROWS, XLD>(Ls, Ls, Gslab + (int64_t)blockIdx.x * KP * KP);
+    if (Xt) store_rows_transposed<T, KP, ROWS, XLD>(Ls, rb, rows, Xt);
   }
 }
 
@@ -185,12 +197,12 @@ __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(const T* X, T* Xn, Spl
 }
 
 // The block's share of X^T X for the rows x KP factor X (slab blockIdx.x,
-// KP x KP), with the row blocks and the order of mu_rows_tpr_kernel's shares,
-// so that either gives the same Gram after the ordered sum.
-template <typename T, int KP>
+// KP x KP) over blocks of ROWS rows, staged and multiplied as the updates
+// stage and multiply theirs (mu_rows_tpr_kernel, hals_rows_grp_kernel), so
+// that either gives the same Gram after the ordered sum.
+template <typename T, int KP, int ROWS>
 __global__ __launch_bounds__(256) void gram_rows_kernel(const T* __restrict__ X, int64_t rows,
                                                         T* __restrict__ Gslab) {
-  constexpr int ROWS = RowSplit<KP>::ROWS;
   constexpr int XLD = KP + Tr<T>::VEC;
   __shared__ __attribute__((aligned(16))) T Xs[ROWS * XLD];
   const int64_t rb = (int64_t)blockIdx.x * ROWS;
@@ -265,81 +277,98 @@ hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int 
   return NMF_LAUNCH_CHECK();
 }
 
-template <typename T>
-int64_t gram_share_blocks(int64_t rows, int KP) {
+static int hals_tpr(int64_t rows) { return rows >= 65536 ? 4 : (rows >= 16384 ? 8 : 16); }
+
+int share_rows(ShareOf u, int64_t rows, int KP) {
+  if (KP > 64 || KP % 16 || KP < 16) return 0;
+  if (u == ShareOf::HALS) return 256 / hals_tpr(rows);
   switch (KP) {
-    case 16: return cdiv(rows, RowSplit<16>::ROWS);
-    case 32: return cdiv(rows, RowSplit<32>::ROWS);
-    case 48: return cdiv(rows, RowSplit<48>::ROWS);
-    case 64: return cdiv(rows, RowSplit<64>::ROWS);
-    default: return 0;
+    case 16: return RowSplit<16>::ROWS;
+    case 32: return RowSplit<32>::ROWS;
+    case 48: return RowSplit<48>::ROWS;
+    default: return RowSplit<64>::ROWS;
+  }
+}
+
+template <typename T, int KP>
+static bool launch_gram_rows(const T* X, int64_t rows, int rpb, T* Gslab, hipStream_t st) {
+  const unsigned nb = (unsigned)cdiv(rows, rpb);
+  switch (rpb) {
+    case 16: gram_rows_kernel<T, KP, 16><<<nb, 256, 0, st>>>(X, rows, Gslab); return true;
+    case 32: gram_rows_kernel<T, KP, 32><<<nb, 256, 0, st>>>(X, rows, Gslab); return true;
+    case 64: gram_rows_kernel<T, KP, 64><<<nb, 256, 0, st>>>(X, rows, Gslab); return true;
+    case 128:
+      if constexpr (KP == 16) {
+        gram_rows_kernel<T, KP, 128><<<nb, 256, 0, st>>>(X, rows, Gslab);
+        return true;
+      }
+      return false;
+    default: return false;
   }
 }
 
 template <typename T>
-hipError_t gram_shares(const T* X, int64_t rows, int KP, T* Gslab, hipStream_t st) {
+hipError_t gram_shares(const T* X, int64_t rows, int KP, int rpb, T* Gslab, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
+  bool ok = false;
   switch (KP) {
-#define CASE(K)                                                                              \
-  case K:                                                                                    \
-    gram_rows_kernel<T, K><<<(unsigned)cdiv(rows, RowSplit<K>::ROWS), 256, 0, st>>>(X, rows,   \
-                                                                                  Gslab);    \
-    break;
-    CASE(16) CASE(32) CASE(48) CASE(64)
-#undef CASE
-    default: return hipErrorInvalidValue;
+    case 16: ok = launch_gram_rows<T, 16>(X, rows, rpb, Gslab, st); break;
+    case 32: ok = launch_gram_rows<T, 32>(X, rows, rpb, Gslab, st); break;
+    case 48: ok = launch_gram_rows<T, 48>(X, rows, rpb, Gslab, st); break;
+    case 64: ok = launch_gram_rows<T, 64>(X, rows, rpb, Gslab, st); break;
+    default: break;
   }
+  if (!ok) return hipErrorInvalidValue;
   return NMF_LAUNCH_CHECK();
 }
 
-template <typename T, int KP, bool TOUT, bool SLABS>
+template <typename T, int KP, bool SLABS, bool TILE>
 void launch_hals_grp_t(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int tpr,
-                       T* Xt, hipStream_t st) {
+                       T* Xt, T* Gslab, hipStream_t st) {
   if (tpr == 4)
-    hals_rows_grp_kernel<T, KP, 4, TOUT, SLABS><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(
-        X, Xn, P, G, rows, k, Xt);
+    hals_rows_grp_kernel<T, KP, 4, SLABS, TILE><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(
+        X, Xn, P, G, rows, k, Xt, Gslab);
   else if (tpr == 8)
-    hals_rows_grp_kernel<T, KP, 8, TOUT, SLABS><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(
-        X, Xn, P, G, rows, k, Xt);
+    hals_rows_grp_kernel<T, KP, 8, SLABS, TILE><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(
+        X, Xn, P, G, rows, k, Xt, Gslab);
   else
-    hals_rows_grp_kernel<T, KP, 16, TOUT, SLABS><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(
-        X, Xn, P, G, rows, k, Xt);
+    hals_rows_grp_kernel<T, KP, 16, SLABS, TILE><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(
+        X, Xn, P, G, rows, k, Xt, Gslab);
 }
 
-// The sweep on its own (nmf_dense: no transposed copy, one slab) keeps the
-// small register and LDS footprint that lets many blocks share a CU; the
-// unrolled layers' form (product slabs, transposed copy) is a variant.
+// One slab (the product as it came) needs no double accumulation: that form
+// keeps the small register footprint that lets many blocks share a CU.
 template <typename T, int KP>
 void launch_hals_grp(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int tpr,
-                     T* Xt, hipStream_t st) {
+                     T* Xt, T* Gslab, hipStream_t st) {
   if constexpr (KP <= 64) {
-    if (Xt) {
-      if (P.n > 1) launch_hals_grp_t<T, KP, true, true>(X, Xn, P, G, rows, k, tpr, Xt, st);
-      else launch_hals_grp_t<T, KP, true, false>(X, Xn, P, G, rows, k, tpr, Xt, st);
+    if (Xt || Gslab) {
+      if (P.n > 1) launch_hals_grp_t<T, KP, true, true>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
+      else launch_hals_grp_t<T, KP, false, true>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
       return;
     }
   }
-  if (P.n > 1) launch_hals_grp_t<T, KP, false, true>(X, Xn, P, G, rows, k, tpr, Xt, st);
-  else launch_hals_grp_t<T, KP, false, false>(X, Xn, P, G, rows, k, tpr, Xt, st);
+  if (P.n > 1) launch_hals_grp_t<T, KP, true, false>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
+  else launch_hals_grp_t<T, KP, false, false>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
 }
 
 template <typename T>
 hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP,
-                     T* Xt, hipStream_t st) {
+                     T* Xt, T* Gslab, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  if ((Xt && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
-  const int tpr = rows >= 65536 ? 4 : (rows >= 16384 ? 8 : 16);
+  if (((Xt || Gslab) && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
+  const int tpr = hals_tpr(rows);
   // every padded rank up to NMF_MAX_K takes the grouped sweep; G (KP x KP)
   // is staged in LDS, at most 64 KB (float) or 128 KB (double) at KP = 128
   switch (KP) {
-    case 16: launch_hals_grp<T, 16>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
-    case 32: launch_hals_grp<T, 32>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
-    case 48: launch_hals_grp<T, 48>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
-    case 64: launch_hals_grp<T, 64>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
-    case 80: launch_hals_grp<T, 80>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
-    case 96: launch_hals_grp<T, 96>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
-    case 112: launch_hals_grp<T, 112>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
-    case 128: launch_hals_grp<T, 128>(X, Xn, P, G, rows, k, tpr, Xt, st); break;
+    case 16: launch_hals_grp<T, 16>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 32: launch_hals_grp<T, 32>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 48: launch_hals_grp<T, 48>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 64: launch_hals_grp<T, 64>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 80: launch_hals_grp<T, 80>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 96: launch_hals_grp<T, 96>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 112: launch_hals_grp<T, 112>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 128: launch_hals_grp<T, 128>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
     default: return hipErrorInvalidValue;
   }
   return NMF_LAUNCH_CHECK();
@@ -384,27 +413,34 @@ __global__ void hals_norms_kernel(T* __restrict__ S, T* __restrict__ norms, int 
 
 // Wn[:, i] = W[:, i] / s_i (rows 0..m-1), Htn[:, i] = Ht[:, i] * s_i (rows
 // m..m+n-1 of the grid); columns with s_i = 0 (and the padding) are copied.
-// Wn and Htn may be W and Ht.
+// Wn and Htn may be W and Ht. Each thread takes one 16-byte run of a row (KP
+// is a multiple of 16, so runs never cross rows); in place, runs whose
+// columns all keep their values (the padding, zero columns) are skipped.
 template <typename T>
 __global__ void hals_scale_kernel(const T* W, T* Wn, int64_t m, const T* Ht, T* Htn, int64_t n,
                                   const T* __restrict__ norms, int k, int KP) {
-  const int64_t total = (m + n) * KP, stride = (int64_t)gridDim.x * blockDim.x;
+  constexpr int VEC = Tr<T>::VEC;
+  const int CPR = KP / VEC;
+  const int64_t total = (m + n) * CPR, stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    const int64_t r = e / KP;
-    const int i = (int)(e - r * KP);
-    const T s = i < k ? norms[i] : T(0);
-    const bool sc = s > T(0);
-    // entries that do not change are not touched in place (the padding and
-    // the zero columns), only copied out of place
-    if (r < m) {
-      if (!sc && Wn == W) continue;
-      const T v = W[r * KP + i];
-      Wn[r * KP + i] = sc ? v / s : v;
-    } else {
-      if (!sc && Htn == Ht) continue;
-      const T v = Ht[(r - m) * KP + i];
-      Htn[(r - m) * KP + i] = sc ? v * s : v;
+    const int64_t r = e / CPR;
+    const int i0 = (int)(e - r * CPR) * VEC;
+    T s[VEC];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      s[q] = i0 + q < k ? norms[i0 + q] : T(0);
+      any = any || s[q] > T(0);
     }
+    const bool w = r < m;
+    const T* src = w ? W + r * KP + i0 : Ht + (r - m) * KP + i0;
+    T* dst = w ? Wn + r * KP + i0 : Htn + (r - m) * KP + i0;
+    if (!any && dst == src) continue;
+    V16<T> v = load16<T>(src);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+      if (s[q] > T(0)) v.v[q] = w ? v.v[q] / s[q] : v.v[q] * s[q];
+    store16<T>(dst, v);
   }
 }
 
@@ -414,7 +450,7 @@ hipError_t hals_normalize(const T* W, T* Wn, int64_t m, const T* Ht, T* Htn, int
   hals_norms_kernel<T><<<1, 256, 0, st>>>(S, norms, k, KP);
   hipError_t e = NMF_LAUNCH_CHECK();
   if (e != hipSuccess) return e;
-  const int64_t total = (m + n) * KP;
+  const int64_t total = (m + n) * (KP / Tr<T>::VEC);
   if (total == 0) return hipSuccess;
   hals_scale_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(W, Wn, m, Ht, Htn, n, norms,
                                                                       k, KP);
@@ -646,10 +682,9 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
 #define INST(T)                                                                             \
   template hipError_t mu_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T, T*, \
                                  T*, T*, hipStream_t); \
-  template int64_t gram_share_blocks<T>(int64_t, int); \
-  template hipError_t gram_shares<T>(const T*, int64_t, int, T*, hipStream_t); \
+  template hipError_t gram_shares<T>(const T*, int64_t, int, int, T*, hipStream_t); \
   template hipError_t hals_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T*, \
-                                   hipStream_t);                                            \
+                                   T*, hipStream_t);                                        \
   template hipError_t hals_normalize<T>(const T*, T*, int64_t, const T*, T*, int64_t, T*, T*, \
                                         int, int, hipStream_t);                             \
   template hipError_t pad_rows<T>(const T*, int64_t, int, T*, int, hipStream_t);            \

@@ -26,6 +26,23 @@ def _maxrel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.abs(b).max(), 1e-300))
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("m,n,k", [(300, 208, 12), (1000, 700, 64)])
+def test_forward_is_nmf_dense_mu(dt, m, n, k):
+    """The unrolled forward pass is the MU iteration of the driver, kernel for
+    kernel (the products, the Grams summed from the updates' row-block
+    shares, the updates): both give the same factors bit for bit."""
+    iters = 6
+    A, W0, H0, _, _ = _problem(m, n, k, seed=4)
+    Ad = to_dev(A, dt)
+    step("mu unrolled forward vs nmf_dense %s %dx%d k=%d" % (np.dtype(dt).name, m, n, k))
+    W, H, _ = nmf.nmf_mu_unrolled_forward(Ad, to_dev(W0, dt), to_dev(H0, dt), iters,
+                                          want_ckpt=False)
+    Wd, Hd = to_dev(W0, dt), to_dev(H0, dt)
+    nmf.nmf_dense(Ad, Wd, Hd, algo="mu", iters=iters, objective=False)
+    assert np.array_equal(host(W), host(Wd)) and np.array_equal(host(H), host(Hd))
+
+
 @pytest.mark.parametrize("iters,every", [(10, 10), (12, 5)])
 def test_fd_check_fp64_256x128_k8(iters, every):
     """Directional finite differences of the library's own FP64 forward
