@@ -297,18 +297,19 @@ struct StopInfo {
 
 // status points at 4 device ints: [0] ABPP flags, [1] input check, [2] G^-1 ok.
 // ginv: KP*KP doubles of scratch for ABPP.
-// Gslab (nullable; MU and HALS at KP <= 64): receives the row blocks' shares
-// of the updated factor's Gram.
+// Gslab and Xt (nullable; MU and HALS at KP <= 64): receive the row blocks'
+// shares of the updated factor's Gram and its transposed copy (KP x rows).
 template <typename T>
 nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, int64_t rows,
                         int k, int KP, const nmf_opts* o, int* status,
-                        unsigned long long* pivots, double* ginv, T* Gslab = nullptr) {
+                        unsigned long long* pivots, double* ginv, T* Gslab = nullptr,
+                        T* Xt = nullptr) {
   hipStream_t st = ctx->stream;
   if (algo == NMF_MU)
     HIP_TRY(nmfk::mu_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, (T)o->eps_mu,
-                             nullptr, nullptr, Gslab, st));
+                             Xt, nullptr, Gslab, st));
   else if (algo == NMF_HALS)
-    HIP_TRY(nmfk::hals_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, nullptr, Gslab,
+    HIP_TRY(nmfk::hals_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, Xt, Gslab,
                                st));
   else {
     const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
@@ -629,6 +630,11 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   const Shares sh = plan_shares(o->algo, m, n, KP);
   T* gsl = sh.on() ? w.part : nullptr;
   bool qready = false;
+  // MU and HALS at KP <= 64 write the transposed copies the next product
+  // reads from their own output tiles (not HALS's W, which the
+  // normalisation rescales after the sweep)
+  const bool own_t = (o->algo == NMF_MU || o->algo == NMF_HALS) && KP <= 64;
+  T* Wt_upd = own_t && o->algo == NMF_MU && tW ? w.Wt : nullptr;
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
     tm.mark(PH_GRAM);
@@ -655,7 +661,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     }
     tm.mark(PH_LUC);
     RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv,
-                        gsl));
+                        gsl, Wt_upd));
     // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
     tm.mark(PH_GRAM);
     if (sh.on()) RUN(sum_shares<T>(ctx, gsl, sh.nbm, KP, w.S));
@@ -664,19 +670,20 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
       tm.mark(PH_LUC);
       HIP_TRY(nmfk::hals_normalize<T>(w.W, w.W, m, w.Ht, w.Ht, n, w.S, w.norms, k, KP, st));
     }
-    if (tW) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
+    if (tW && !Wt_upd) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
     tm.mark(PH_MM_T);
     RUN(product_AtF<T>(ctx, pb, m, n, w.W, tW ? w.Wt : nullptr, k, KP, w.R, w.part));
     tm.mark(PH_LUC);
+    const bool next_t = tH && t + 1 < o->iters;
     RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots, w.ginv,
-                        gsl));
+                        gsl, own_t && next_t ? w.Hk : nullptr));
     if (sh.on()) {
       // the next iteration's Q, from the H update's shares
       tm.mark(PH_GRAM);
       RUN(sum_shares<T>(ctx, gsl, sh.nbn, KP, w.Q));
       qready = true;
     }
-    if (tH && t + 1 < o->iters) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
+    if (next_t && !own_t) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
     if (pgstop) {
       tm.mark(PH_OBJ);
       RUN(pg_half<T>(ctx, w.Ht, w.R, w.S, n, k, KP, w, 0));
