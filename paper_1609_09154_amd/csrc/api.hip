@@ -284,6 +284,7 @@ template <typename T> struct Work {
   double* ginv;  // KP x KP, ABPP
   double *obj_part, *relerr, *normA;
   double *pg_part, *pg_val;  // projected-gradient partials; [0] H half, [1] W half
+  T* gsl;  // the updates' Gram shares
   int* status;
   unsigned long long* pivots;
   int64_t obj_np;
@@ -297,21 +298,23 @@ struct StopInfo {
 
 // status points at 4 device ints: [0] ABPP flags, [1] input check, [2] G^-1 ok.
 // ginv: KP*KP doubles of scratch for ABPP.
-// Gslab and Xt (nullable; MU and HALS at KP <= 64): receive the row blocks'
-// shares of the updated factor's Gram and its transposed copy (KP x rows).
+// P: the product, or (MU and HALS) its split slabs, which the update adds in
+// slab order. Gslab and Xt (nullable; MU and HALS at KP <= 64): receive the
+// row blocks' shares of the updated factor's Gram and its transposed copy
+// (KP x rows).
 template <typename T>
-nmf_status local_update(nmf_ctx* ctx, int algo, T* X, const T* Pm, const T* G, int64_t rows,
-                        int k, int KP, const nmf_opts* o, int* status,
+nmf_status local_update(nmf_ctx* ctx, int algo, T* X, nmfk::Split<T> P, const T* G,
+                        int64_t rows, int k, int KP, const nmf_opts* o, int* status,
                         unsigned long long* pivots, double* ginv, T* Gslab = nullptr,
                         T* Xt = nullptr) {
   hipStream_t st = ctx->stream;
   if (algo == NMF_MU)
-    HIP_TRY(nmfk::mu_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, (T)o->eps_mu,
-                             Xt, nullptr, Gslab, st));
+    HIP_TRY(nmfk::mu_rows<T>(X, X, P, G, rows, k, KP, (T)o->eps_mu, Xt, nullptr, Gslab, st));
   else if (algo == NMF_HALS)
-    HIP_TRY(nmfk::hals_rows<T>(X, X, nmfk::Split<T>{Pm, 1, 0}, G, rows, k, KP, Xt, Gslab,
-                               st));
+    HIP_TRY(nmfk::hals_rows<T>(X, X, P, G, rows, k, KP, Xt, Gslab, st));
   else {
+    if (P.n != 1) return NMF_EINVAL;
+    const T* Pm = P.p;
     const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
     // the incoming X (the current iterate) starts each right-hand side's pivoting
     HIP_TRY(nmfk::bpp_rows_compact<T>(X, Pm, G, rows, k, KP, cap, 1, ginv, status + 2, status,
@@ -331,7 +334,7 @@ nmf_status gram(nmf_ctx* ctx, const T* X, int64_t rows, int KP, T* G, T* part,
 // Workspace offsets for an AU-NMF call on an m x n problem.
 template <typename T>
 size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_t extra_part,
-                 Carve& cv, size_t off[17], bool sparse = false) {
+                 Carve& cv, size_t off[18], bool sparse = false) {
   // split partials of the dense products (the sparse products use none)
   const int64_t ps_p = sparse ? 1 : std::max(nmfk::gemm_auto_splits<T>(nmfk::GemmKind::NN, m, KP, n),
                                              nmfk::gemm_auto_splits<T>(nmfk::GemmKind::TN, m, KP, n));
@@ -340,10 +343,6 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   part = std::max<int64_t>(part, ps_r > 1 ? ps_r * n * KP : 0);
   part = std::max<int64_t>(part, gram_splits(std::max(m, n)) * KP * KP);
   part = std::max<int64_t>(part, extra_part);
-  // the updates' Gram shares, for either update that writes them
-  part = std::max<int64_t>(part, std::max(plan_shares(NMF_MU, m, n, KP).blocks(),
-                                          plan_shares(NMF_HALS, m, n, KP).blocks()) *
-                                     KP * KP);
   off[0] = cv.take<T>(m * KP);
   off[1] = cv.take<T>(n * KP);
   off[2] = cv.take<T>(m * KP);
@@ -362,11 +361,15 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[14] = cv.take<double>(KP * KP);
   off[15] = cv.take<double>(nmfk::pgrad_partials(std::max(m, n)));
   off[16] = cv.take<double>(4);
+  // the updates' Gram shares, for either update that writes them (apart from
+  // the product slabs, which an update may still be reading)
+  off[17] = cv.take<T>(std::max(plan_shares(NMF_MU, m, n, KP).blocks(),
+                                plan_shares(NMF_HALS, m, n, KP).blocks()) * KP * KP);
   return cv.off;
 }
 
 template <typename T>
-Work<T> bind_work(nmf_ctx* ctx, const size_t off[17], int64_t obj_np) {
+Work<T> bind_work(nmf_ctx* ctx, const size_t off[18], int64_t obj_np) {
   Work<T> w;
   w.W = at<T>(ctx, off[0]);
   w.Ht = at<T>(ctx, off[1]);
@@ -386,6 +389,7 @@ Work<T> bind_work(nmf_ctx* ctx, const size_t off[17], int64_t obj_np) {
   w.ginv = at<double>(ctx, off[14]);
   w.pg_part = at<double>(ctx, off[15]);
   w.pg_val = at<double>(ctx, off[16]);
+  w.gsl = at<T>(ctx, off[17]);
   w.obj_np = obj_np;
   return w;
 }
@@ -625,11 +629,21 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   const bool tH = big && !pb.sparse && !pb.lp && (n * (int64_t)sizeof(T)) % 16 == 0;
   const bool tW = big && !pb.sparse && !pb.lp && (m * (int64_t)sizeof(T)) % 16 == 0;
   if (tH && o->iters > 0) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));
-  // the updates' Gram shares go to w.part and are summed before the next
-  // product uses it; qready: Q already holds the current H's Gram
+  // the updates' Gram shares (w.gsl); qready: Q already holds the current H's
+  // Gram
+  int nsp_w_v = 1, nsp_h_v = 1;
   const Shares sh = plan_shares(o->algo, m, n, KP);
-  T* gsl = sh.on() ? w.part : nullptr;
+  T* gsl = sh.on() ? w.gsl : nullptr;
   bool qready = false;
+  // Dense products hand their split slabs to an MU or HALS update that adds
+  // them as the ordered sum would (bit for bit), where that costs the update
+  // no occupancy; P and R are then not formed, so not with the
+  // projected-gradient stop, which reads them.
+  const bool hand = (o->algo == NMF_MU || o->algo == NMF_HALS) && !pgstop && !pb.sparse &&
+                    !pb.lp;
+  const nmfk::ShareOf upd = o->algo == NMF_MU ? nmfk::ShareOf::MU : nmfk::ShareOf::HALS;
+  int* nsp_w = hand && nmfk::takes_slabs(upd, m) ? &nsp_w_v : nullptr;
+  int* nsp_h = hand && nmfk::takes_slabs(upd, n) ? &nsp_h_v : nullptr;
   // MU and HALS at KP <= 64 write the transposed copies the next product
   // reads from their own output tiles (not HALS's W, which the
   // normalisation rescales after the sweep)
@@ -645,7 +659,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
       RUN(sum_shares<T>(ctx, gsl, sh.nbn, KP, w.Q));
     }
     tm.mark(PH_MM);
-    RUN(product_AF<T>(ctx, pb, m, n, w.Ht, tH ? w.Hk : nullptr, k, KP, w.P, w.part));
+    RUN(product_AF<T>(ctx, pb, m, n, w.Ht, tH ? w.Hk : nullptr, k, KP, w.P, w.part, nsp_w));
     if (pgstop) {
       tm.mark(PH_OBJ);
       RUN(pg_half<T>(ctx, w.W, w.P, w.Q, m, k, KP, w, 1));
@@ -660,7 +674,8 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
       }
     }
     tm.mark(PH_LUC);
-    RUN(local_update<T>(ctx, o->algo, w.W, w.P, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv,
+    const nmfk::Split<T> spw{nsp_w_v > 1 ? w.part : w.P, nsp_w_v, m * KP};
+    RUN(local_update<T>(ctx, o->algo, w.W, spw, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv,
                         gsl, Wt_upd));
     // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
     tm.mark(PH_GRAM);
@@ -672,10 +687,11 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     }
     if (tW && !Wt_upd) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
     tm.mark(PH_MM_T);
-    RUN(product_AtF<T>(ctx, pb, m, n, w.W, tW ? w.Wt : nullptr, k, KP, w.R, w.part));
+    RUN(product_AtF<T>(ctx, pb, m, n, w.W, tW ? w.Wt : nullptr, k, KP, w.R, w.part, nsp_h));
     tm.mark(PH_LUC);
     const bool next_t = tH && t + 1 < o->iters;
-    RUN(local_update<T>(ctx, o->algo, w.Ht, w.R, w.S, n, k, KP, o, w.status, w.pivots, w.ginv,
+    const nmfk::Split<T> sph{nsp_h_v > 1 ? w.part : w.R, nsp_h_v, n * KP};
+    RUN(local_update<T>(ctx, o->algo, w.Ht, sph, w.S, n, k, KP, o, w.status, w.pivots, w.ginv,
                         gsl, own_t && next_t ? w.Hk : nullptr));
     if (sh.on()) {
       // the next iteration's Q, from the H update's shares
@@ -849,7 +865,7 @@ nmf_status dense_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, int lp, co
   const int64_t obj_np = std::max(nmfk::residual_partials<T>(m, n), nmfk::sumsq_partials<T>(m, n));
   const LpPlan bp = lp ? lp_plan(lp, m, n, KP) : LpPlan{0, 0};
   Carve cv;
-  size_t off[17];
+  size_t off[18];
   plan_work<T>(m, n, KP, o->iters, obj_np, bp.part_elems, cv, off);
   const LpOffsets lo = lp_carve(cv, bp, KP);
   nmf_status s = ensure_ws(ctx, cv.off);
@@ -1034,7 +1050,7 @@ nmf_status nmf_csr(nmf_ctx* ctx, int64_t m, int64_t n, int64_t nnz, const int64_
   const bool want_obj = opts->objective != NMF_OBJ_NONE;
   const int64_t obj_np = std::max<int64_t>(nmfk::csr_residual_partials(m), 1024);
   Carve cv;
-  size_t off[17];
+  size_t off[18];
   plan_work<T>(m, n, KP, opts->iters, obj_np, 0, cv, off, true);
   const size_t o_rpt = cv.take<int64_t>(n + 1);
   const size_t o_cit = cv.take<int32_t>(nnz);
@@ -1217,7 +1233,8 @@ nmf_status update_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, const T* G, 
   if (KP > k) HIP_TRY(hipMemsetAsync(Gp + (size_t)k * KP, 0, sizeof(T) * (KP - k) * KP, st));
   HIP_TRY(nmfk::pad_rows<T>(Pm, rows, k, Pp, KP, st));
   HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
-  if ((s = local_update<T>(ctx, algo, Xp, Pp, Gp, rows, k, KP, o, dst, dpv, at<double>(ctx, oI))) !=
+  if ((s = local_update<T>(ctx, algo, Xp, nmfk::Split<T>{Pp, 1, 0}, Gp, rows, k, KP, o, dst, dpv,
+                          at<double>(ctx, oI))) !=
       NMF_OK)
     return s;
   HIP_TRY(nmfk::unpad_rows<T>(Xp, rows, k, KP, X, st));
@@ -1268,7 +1285,8 @@ nmf_status update_noalloc_impl(nmf_ctx* ctx, int algo, int64_t rows, int k, cons
   }
   HIP_TRY(nmfk::pad_rows<T>(Pm, rows, k, Pp, KP, st));
   HIP_TRY(nmfk::pad_rows<T>(X, rows, k, Xp, KP, st));
-  nmf_status s = local_update<T>(ctx, algo, Xp, Pp, Gp, rows, k, KP, o, dst, dpv,
+  nmf_status s = local_update<T>(ctx, algo, Xp, nmfk::Split<T>{Pp, 1, 0}, Gp, rows, k, KP, o,
+                                 dst, dpv,
                                  (double*)(base + pl.oI));
   if (s != NMF_OK) return s;
   HIP_TRY(nmfk::unpad_rows<T>(Xp, rows, k, KP, X, st));
@@ -1312,7 +1330,7 @@ nmf_status relerr_impl(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, in
                                    : std::max(nmfk::residual_partials<T>(m, n),
                                               nmfk::sumsq_partials<T>(m, n));
   Carve cv;
-  size_t off[17];
+  size_t off[18];
   plan_work<T>(m, n, KP, 0, obj_np, 0, cv, off, pb.sparse);
   nmf_status s = ensure_ws(ctx, cv.off);
   if (s != NMF_OK) return s;

@@ -94,6 +94,10 @@ hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, in
 // this KP): mu_rows at any row count, hals_rows at `rows` rows.
 enum class ShareOf { MU, HALS };
 int share_rows(ShareOf u, int64_t rows, int KP);
+// Whether the update at `rows` rows takes a product's split slabs without
+// losing occupancy (the HALS sweep's slab sums need registers that its
+// many-row forms share out among more waves).
+bool takes_slabs(ShareOf u, int64_t rows);
 // The same shares of X^T X over blocks of rpb rows (a share_rows value) for
 // a factor that no update produced (KP <= 64).
 template <typename T>

@@ -279,6 +279,8 @@ hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int 
 
 static int hals_tpr(int64_t rows) { return rows >= 65536 ? 4 : (rows >= 16384 ? 8 : 16); }
 
+bool takes_slabs(ShareOf u, int64_t rows) { return u == ShareOf::MU || hals_tpr(rows) == 16; }
+
 int share_rows(ShareOf u, int64_t rows, int KP) {
   if (KP > 64 || KP % 16 || KP < 16) return 0;
   if (u == ShareOf::HALS) return 256 / hals_tpr(rows);
