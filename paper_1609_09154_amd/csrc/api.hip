@@ -649,6 +649,8 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   // normalisation rescales after the sweep)
   const bool own_t = (o->algo == NMF_MU || o->algo == NMF_HALS) && KP <= 64;
   T* Wt_upd = own_t && o->algo == NMF_MU && tW ? w.Wt : nullptr;
+  // HALS: the normalisation writes W's copy after rescaling W
+  T* Wt_nrm = own_t && o->algo == NMF_HALS && tW ? w.Wt : nullptr;
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
     tm.mark(PH_GRAM);
@@ -683,9 +685,10 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     else RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
     if (o->algo == NMF_HALS) {
       tm.mark(PH_LUC);
-      HIP_TRY(nmfk::hals_normalize<T>(w.W, w.W, m, w.Ht, w.Ht, n, w.S, w.norms, k, KP, st));
+      HIP_TRY(nmfk::hals_normalize<T>(w.W, w.W, m, w.Ht, w.Ht, n, w.S, w.norms, k, KP, st,
+                                      Wt_nrm));
     }
-    if (tW && !Wt_upd) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
+    if (tW && !Wt_upd && !Wt_nrm) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
     tm.mark(PH_MM_T);
     RUN(product_AtF<T>(ctx, pb, m, n, w.W, tW ? w.Wt : nullptr, k, KP, w.R, w.part, nsp_h));
     tm.mark(PH_LUC);
@@ -1891,8 +1894,12 @@ nmf_status hals_iteration(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n,
   } else if ((s = gram<T>(ctx, Wsw, m, KP, S, w.part)) != NMF_OK) {
     return s;
   }
-  HIP_TRY(nmfk::hals_normalize<T>(Wsw, Wn, m, Ht, Hsc, n, S, nrm, k, KP, st));
-  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, w.R, w, false, &sp)) != NMF_OK) return s;
+  // the normalisation writes Wn's transposed copy for the product (w.Ft, whose
+  // copy of Ht the product above has read)
+  const bool tW = rows_transposable<T>(m, KP);
+  HIP_TRY(nmfk::hals_normalize<T>(Wsw, Wn, m, Ht, Hsc, n, S, nrm, k, KP, st,
+                                  tW ? w.Ft : nullptr));
+  if ((s = mu_prod_AtF<T>(ctx, pb, m, n, Wn, k, KP, w.R, w, tW, &sp)) != NMF_OK) return s;
   HIP_TRY(nmfk::hals_rows<T>(Hsc, Htn, sp, S, n, k, KP, tH ? w.Ft : nullptr, gsl, st));
   *ft = tH;
   if (gsl) *qready = true;

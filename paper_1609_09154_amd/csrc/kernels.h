@@ -104,10 +104,12 @@ template <typename T>
 hipError_t gram_shares(const T* X, int64_t rows, int KP, int rpb, T* Gslab, hipStream_t st);
 
 // HALS normalisation: s_i = sqrt(S[i][i]); W[:, i] /= s_i, Ht[:, i] *= s_i and
-// S[i][j] /= s_i s_j for s_i > 0. norms (nullable) receives s.
+// S[i][j] /= s_i s_j for s_i > 0. norms receives s. Wt (nullable, KP <= 64,
+// m a multiple of 16 / sizeof(T)) receives the transpose of the rescaled W,
+// Wt[i * m + r].
 template <typename T>
 hipError_t hals_normalize(const T* W, T* Wn, int64_t m, const T* Ht, T* Htn, int64_t n, T* S,
-                          T* norms, int k, int KP, hipStream_t st);
+                          T* norms, int k, int KP, hipStream_t st, T* Wt = nullptr);
 
 // Copies between the caller's layouts (ld = k) and the padded row layout.
 template <typename T>

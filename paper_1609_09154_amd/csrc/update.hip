@@ -446,14 +446,72 @@ __global__ void hals_scale_kernel(const T* W, T* Wn, int64_t m, const T* Ht, T* 
   }
 }
 
+// The same rescaling by tiles of SCALE_ROWS rows (W's tiles, then Ht's), for
+// KP <= 64 with W's transposed copy: each tile of Wn also goes through LDS
+// and out as Wt[i * m + r], the layout the next product reads, so that copy
+// needs no launch of its own.
+constexpr int SCALE_ROWS = 64;
+template <typename T, int KP>
+__global__ __launch_bounds__(256) void hals_scale_t_kernel(const T* W, T* Wn, int64_t m,
+                                                           const T* Ht, T* Htn, int64_t n,
+                                                           const T* __restrict__ norms, int k,
+                                                           T* __restrict__ Wt) {
+  constexpr int VEC = Tr<T>::VEC, CPR = KP / VEC, XLD = KP + VEC;
+  __shared__ __attribute__((aligned(16))) T tile[SCALE_ROWS * XLD];
+  const int64_t tw = cdiv(m, SCALE_ROWS), tt = tw + cdiv(n, SCALE_ROWS);
+  for (int64_t tb = blockIdx.x; tb < tt; tb += gridDim.x) {
+    const bool w = tb < tw;  // uniform over the block
+    const int64_t rb = (w ? tb : tb - tw) * SCALE_ROWS, rows = w ? m : n;
+    for (int e = threadIdx.x; e < SCALE_ROWS * CPR; e += blockDim.x) {
+      const int q = e / CPR, i0 = (e % CPR) * VEC;
+      const int64_t r = rb + q;
+      if (r >= rows) continue;
+      T s[VEC];
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) {
+        s[u] = i0 + u < k ? norms[i0 + u] : T(0);
+        any = any || s[u] > T(0);
+      }
+      const T* src = (w ? W : Ht) + r * KP + i0;
+      T* dst = (w ? Wn : Htn) + r * KP + i0;
+      V16<T> v = load16<T>(src);
+#pragma unroll
+      for (int u = 0; u < VEC; ++u)
+        if (s[u] > T(0)) v.v[u] = w ? v.v[u] / s[u] : v.v[u] * s[u];
+      if (any || dst != src) store16<T>(dst, v);
+      if (w) {
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) tile[q * XLD + i0 + u] = v.v[u];
+      }
+    }
+    if (w) {
+      __syncthreads();
+      store_rows_transposed<T, KP, SCALE_ROWS, XLD>(tile, rb, m, Wt);
+      __syncthreads();  // the tile is rewritten by the block's next W tile
+    }
+  }
+}
+
 template <typename T>
 hipError_t hals_normalize(const T* W, T* Wn, int64_t m, const T* Ht, T* Htn, int64_t n, T* S,
-                          T* norms, int k, int KP, hipStream_t st) {
+                          T* norms, int k, int KP, hipStream_t st, T* Wt) {
   hals_norms_kernel<T><<<1, 256, 0, st>>>(S, norms, k, KP);
   hipError_t e = NMF_LAUNCH_CHECK();
   if (e != hipSuccess) return e;
   const int64_t total = (m + n) * (KP / Tr<T>::VEC);
   if (total == 0) return hipSuccess;
+  if (Wt) {
+    const unsigned nb = capped_grid(cdiv(m, SCALE_ROWS) + cdiv(n, SCALE_ROWS));
+    switch (KP) {
+      case 16: hals_scale_t_kernel<T, 16><<<nb, 256, 0, st>>>(W, Wn, m, Ht, Htn, n, norms, k, Wt); break;
+      case 32: hals_scale_t_kernel<T, 32><<<nb, 256, 0, st>>>(W, Wn, m, Ht, Htn, n, norms, k, Wt); break;
+      case 48: hals_scale_t_kernel<T, 48><<<nb, 256, 0, st>>>(W, Wn, m, Ht, Htn, n, norms, k, Wt); break;
+      case 64: hals_scale_t_kernel<T, 64><<<nb, 256, 0, st>>>(W, Wn, m, Ht, Htn, n, norms, k, Wt); break;
+      default: return hipErrorInvalidValue;
+    }
+    return NMF_LAUNCH_CHECK();
+  }
   hals_scale_kernel<T><<<capped_grid(cdiv(total, 256)), 256, 0, st>>>(W, Wn, m, Ht, Htn, n, norms,
                                                                       k, KP);
   return NMF_LAUNCH_CHECK();
@@ -688,7 +746,7 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
   template hipError_t hals_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T*, \
                                    T*, hipStream_t);                                        \
   template hipError_t hals_normalize<T>(const T*, T*, int64_t, const T*, T*, int64_t, T*, T*, \
-                                        int, int, hipStream_t);                             \
+                                        int, int, hipStream_t, T*);                         \
   template hipError_t pad_rows<T>(const T*, int64_t, int, T*, int, hipStream_t);            \
   template hipError_t unpad_rows<T>(const T*, int64_t, int, int, T*, hipStream_t);          \
   template hipError_t transpose_in<T>(const T*, int, int64_t, T*, int, hipStream_t);        \
