@@ -313,7 +313,7 @@ nmf_status local_update(nmf_ctx* ctx, int algo, T* X, nmfk::Split<T> P, const T*
   else if (algo == NMF_HALS)
     HIP_TRY(nmfk::hals_rows<T>(X, X, P, G, rows, k, KP, Xt, Gslab, st));
   else {
-    if (P.n != 1) return NMF_EINVAL;
+    if (P.n != 1) return fail(ctx, NMF_EINVAL, "ABPP takes the summed product, not its slabs");
     const T* Pm = P.p;
     const int cap = o->max_pivots > 0 ? o->max_pivots : 50 * k;
     // the incoming X (the current iterate) starts each right-hand side's pivoting

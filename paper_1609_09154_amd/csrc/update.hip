@@ -112,9 +112,11 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, S
 // update, Xn = X, reads nothing a lane has already written) and read with
 // 16-byte loads. Xn receives every entry of the new rows (entries k..KP-1
 // copied from X); Xt (nullable) receives their transpose, Xt[i * rows + r],
-// the layout the next product reads the factor in. P arrives as the product's
-// slabs, summed here in slab order in double (Pout, nullable, receives the
-// sum), so that a split product needs no pass of its own to add them.
+// the layout the next product reads the factor in, and Gslab (nullable) the
+// block's share of Xn^T Xn, formed on the matrix cores from the same staged
+// rows. P arrives as the product's slabs, summed here in slab order in double
+// (Pout, nullable, receives the sum), so that a split product needs no pass
+// of its own to add them.
 template <int KP> struct RowSplit {
   static constexpr int TPR = KP == 48 ? 4 : KP / 8;
   static constexpr int RPT = KP / TPR;
