@@ -301,17 +301,18 @@ struct StopInfo {
 // P: the product, or (MU and HALS) its split slabs, which the update adds in
 // slab order. Gslab and Xt (nullable; MU and HALS at KP <= 64): receive the
 // row blocks' shares of the updated factor's Gram and its transposed copy
-// (KP x rows).
+// (KP x rows). Xs (nullable; HALS): scales the incoming rows first (the
+// normalisation's compensation of H).
 template <typename T>
 nmf_status local_update(nmf_ctx* ctx, int algo, T* X, nmfk::Split<T> P, const T* G,
                         int64_t rows, int k, int KP, const nmf_opts* o, int* status,
                         unsigned long long* pivots, double* ginv, T* Gslab = nullptr,
-                        T* Xt = nullptr) {
+                        T* Xt = nullptr, const T* Xs = nullptr) {
   hipStream_t st = ctx->stream;
   if (algo == NMF_MU)
     HIP_TRY(nmfk::mu_rows<T>(X, X, P, G, rows, k, KP, (T)o->eps_mu, Xt, nullptr, Gslab, st));
   else if (algo == NMF_HALS)
-    HIP_TRY(nmfk::hals_rows<T>(X, X, P, G, rows, k, KP, Xt, Gslab, st));
+    HIP_TRY(nmfk::hals_rows<T>(X, X, P, G, rows, k, KP, Xt, Gslab, st, Xs));
   else {
     if (P.n != 1) return fail(ctx, NMF_EINVAL, "ABPP takes the summed product, not its slabs");
     const T* Pm = P.p;
@@ -685,7 +686,9 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     else RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
     if (o->algo == NMF_HALS) {
       tm.mark(PH_LUC);
-      HIP_TRY(nmfk::hals_normalize<T>(w.W, w.W, m, w.Ht, w.Ht, n, w.S, w.norms, k, KP, st,
+      // W's columns rescaled here; H's compensation is applied by the H sweep
+      // as it reads the rows (the same products, one pass over H fewer)
+      HIP_TRY(nmfk::hals_normalize<T>(w.W, w.W, m, w.Ht, w.Ht, 0, w.S, w.norms, k, KP, st,
                                       Wt_nrm));
     }
     if (tW && !Wt_upd && !Wt_nrm) HIP_TRY(nmfk::transpose_rows<T>(w.W, m, KP, w.Wt, st));
@@ -695,7 +698,8 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     const bool next_t = tH && t + 1 < o->iters;
     const nmfk::Split<T> sph{nsp_h_v > 1 ? w.part : w.R, nsp_h_v, n * KP};
     RUN(local_update<T>(ctx, o->algo, w.Ht, sph, w.S, n, k, KP, o, w.status, w.pivots, w.ginv,
-                        gsl, own_t && next_t ? w.Hk : nullptr));
+                        gsl, own_t && next_t ? w.Hk : nullptr,
+                        o->algo == NMF_HALS ? w.norms : nullptr));
     if (sh.on()) {
       // the next iteration's Q, from the H update's shares
       tm.mark(PH_GRAM);

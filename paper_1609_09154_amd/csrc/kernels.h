@@ -87,9 +87,11 @@ hipError_t pack_fp8_t(const float* F, int64_t rows, int KP, uint8_t* Ft, int64_t
 template <typename T>
 hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
                    T* Xt, T* Pout, T* Gslab, hipStream_t st);
+// hals_rows' Xs (nullable, KP entries): the incoming rows are scaled first,
+// x_i *= Xs[i] where Xs[i] > 0 (the normalisation's compensation of H).
 template <typename T>
 hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP,
-                     T* Xt, T* Gslab, hipStream_t st);
+                     T* Xt, T* Gslab, hipStream_t st, const T* Xs = nullptr);
 // Rows per block of an update's Gram shares (0: the update writes none at
 // this KP): mu_rows at any row count, hals_rows at `rows` rows.
 enum class ShareOf { MU, HALS };

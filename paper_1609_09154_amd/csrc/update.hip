@@ -35,12 +35,16 @@ namespace nmfk {
 // 64 rows per block does its padding need more (17 KB against 16 KB at KP =
 // 64), which the form without TILE, for calls that want neither output,
 // does not take.
+// Xs (nullable) scales the incoming rows first, x_i *= Xs[i] where Xs[i] > 0
+// (the normalisation's compensation of H, applied as the sweep reads the rows
+// rather than by a pass of its own; the same product, so the same bits).
 template <typename T, int KP, int TPR, bool SLABS, bool TILE>
 __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, Split<T> P,
                                                             const T* __restrict__ G,
                                                             int64_t rows, int k,
                                                             T* __restrict__ Xt,
-                                                            T* __restrict__ Gslab) {
+                                                            T* __restrict__ Gslab,
+                                                            const T* __restrict__ Xscale) {
   constexpr int R = KP / TPR, ROWS = 256 / TPR;
   constexpr int VEC = Tr<T>::VEC;
   constexpr int XLD = KP + VEC;
@@ -59,6 +63,13 @@ __global__ __launch_bounds__(256) void hals_rows_grp_kernel(const T* X, T* Xn, S
   T x[R], p[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) x[q] = X[rr * KP + sub * R + q];
+  if (Xscale) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const T sc = Xscale[sub * R + q];
+      if (sc > T(0)) x[q] = x[q] * sc;
+    }
+  }
   if constexpr (SLABS) {
     double ps[R];
 #pragma unroll
@@ -328,51 +339,53 @@ hipError_t gram_shares(const T* X, int64_t rows, int KP, int rpb, T* Gslab, hipS
 
 template <typename T, int KP, bool SLABS, bool TILE>
 void launch_hals_grp_t(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int tpr,
-                       T* Xt, T* Gslab, hipStream_t st) {
+                       T* Xt, T* Gslab, const T* Xs, hipStream_t st) {
   if (tpr == 4)
     hals_rows_grp_kernel<T, KP, 4, SLABS, TILE><<<(unsigned)cdiv(rows, 64), 256, 0, st>>>(
-        X, Xn, P, G, rows, k, Xt, Gslab);
+        X, Xn, P, G, rows, k, Xt, Gslab, Xs);
   else if (tpr == 8)
     hals_rows_grp_kernel<T, KP, 8, SLABS, TILE><<<(unsigned)cdiv(rows, 32), 256, 0, st>>>(
-        X, Xn, P, G, rows, k, Xt, Gslab);
+        X, Xn, P, G, rows, k, Xt, Gslab, Xs);
   else
     hals_rows_grp_kernel<T, KP, 16, SLABS, TILE><<<(unsigned)cdiv(rows, 16), 256, 0, st>>>(
-        X, Xn, P, G, rows, k, Xt, Gslab);
+        X, Xn, P, G, rows, k, Xt, Gslab, Xs);
 }
 
 // One slab (the product as it came) needs no double accumulation: that form
 // keeps the small register footprint that lets many blocks share a CU.
 template <typename T, int KP>
 void launch_hals_grp(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int tpr,
-                     T* Xt, T* Gslab, hipStream_t st) {
+                     T* Xt, T* Gslab, const T* Xs, hipStream_t st) {
   if constexpr (KP <= 64) {
     if (Xt || Gslab) {
-      if (P.n > 1) launch_hals_grp_t<T, KP, true, true>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
-      else launch_hals_grp_t<T, KP, false, true>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
+      if (P.n > 1)
+        launch_hals_grp_t<T, KP, true, true>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st);
+      else
+        launch_hals_grp_t<T, KP, false, true>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st);
       return;
     }
   }
-  if (P.n > 1) launch_hals_grp_t<T, KP, true, false>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
-  else launch_hals_grp_t<T, KP, false, false>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st);
+  if (P.n > 1) launch_hals_grp_t<T, KP, true, false>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st);
+  else launch_hals_grp_t<T, KP, false, false>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st);
 }
 
 template <typename T>
 hipError_t hals_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP,
-                     T* Xt, T* Gslab, hipStream_t st) {
+                     T* Xt, T* Gslab, hipStream_t st, const T* Xs) {
   if (rows <= 0) return hipSuccess;
   if (((Xt || Gslab) && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
   const int tpr = hals_tpr(rows);
   // every padded rank up to NMF_MAX_K takes the grouped sweep; G (KP x KP)
   // is staged in LDS, at most 64 KB (float) or 128 KB (double) at KP = 128
   switch (KP) {
-    case 16: launch_hals_grp<T, 16>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
-    case 32: launch_hals_grp<T, 32>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
-    case 48: launch_hals_grp<T, 48>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
-    case 64: launch_hals_grp<T, 64>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
-    case 80: launch_hals_grp<T, 80>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
-    case 96: launch_hals_grp<T, 96>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
-    case 112: launch_hals_grp<T, 112>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
-    case 128: launch_hals_grp<T, 128>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, st); break;
+    case 16: launch_hals_grp<T, 16>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
+    case 32: launch_hals_grp<T, 32>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
+    case 48: launch_hals_grp<T, 48>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
+    case 64: launch_hals_grp<T, 64>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
+    case 80: launch_hals_grp<T, 80>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
+    case 96: launch_hals_grp<T, 96>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
+    case 112: launch_hals_grp<T, 112>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
+    case 128: launch_hals_grp<T, 128>(X, Xn, P, G, rows, k, tpr, Xt, Gslab, Xs, st); break;
     default: return hipErrorInvalidValue;
   }
   return NMF_LAUNCH_CHECK();
@@ -746,7 +759,7 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
                                  T*, T*, hipStream_t); \
   template hipError_t gram_shares<T>(const T*, int64_t, int, int, T*, hipStream_t); \
   template hipError_t hals_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T*, \
-                                   T*, hipStream_t);                                        \
+                                   T*, hipStream_t, const T*);                              \
   template hipError_t hals_normalize<T>(const T*, T*, int64_t, const T*, T*, int64_t, T*, T*, \
                                         int, int, hipStream_t, T*);                         \
   template hipError_t pad_rows<T>(const T*, int64_t, int, T*, int, hipStream_t);            \
