@@ -160,6 +160,11 @@ int64_t gram_splits(int64_t rows) {
 // for the separate Grams. The same rule holds in the plain iteration and in
 // the unrolled layers, so their Grams agree bit for bit.
 constexpr int64_t SHARE_CAP = 4096;
+// Where the shares of a factor's Gram hold at most GSUM_MAX elements (a
+// 2000-row factor at k = 10: 16 shares of 16 x 16), the MU update that needs
+// the Gram adds them itself as it stages G, so the Grams take no launches of
+// their own; each update then keeps its shares in its own buffer.
+constexpr int64_t GSUM_MAX = 1 << 14;
 struct Shares {
   int rpm = 0, rpn = 0;       // rows per block for W and for H^T (0: no shares)
   int64_t nbm = 0, nbn = 0;   // blocks, that is shares, of each
@@ -307,10 +312,11 @@ template <typename T>
 nmf_status local_update(nmf_ctx* ctx, int algo, T* X, nmfk::Split<T> P, const T* G,
                         int64_t rows, int k, int KP, const nmf_opts* o, int* status,
                         unsigned long long* pivots, double* ginv, T* Gslab = nullptr,
-                        T* Xt = nullptr, const T* Xs = nullptr) {
+                        T* Xt = nullptr, const T* Xs = nullptr, int gn = 1) {
   hipStream_t st = ctx->stream;
+  if (gn != 1 && algo != NMF_MU) return fail(ctx, NMF_EINVAL, "only MU sums Gram shares");
   if (algo == NMF_MU)
-    HIP_TRY(nmfk::mu_rows<T>(X, X, P, G, rows, k, KP, (T)o->eps_mu, Xt, nullptr, Gslab, st));
+    HIP_TRY(nmfk::mu_rows<T>(X, X, P, G, rows, k, KP, (T)o->eps_mu, Xt, nullptr, Gslab, st, gn));
   else if (algo == NMF_HALS)
     HIP_TRY(nmfk::hals_rows<T>(X, X, P, G, rows, k, KP, Xt, Gslab, st, Xs));
   else {
@@ -364,8 +370,9 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[16] = cv.take<double>(4);
   // the updates' Gram shares, for either update that writes them (apart from
   // the product slabs, which an update may still be reading)
-  off[17] = cv.take<T>(std::max(plan_shares(NMF_MU, m, n, KP).blocks(),
-                                plan_shares(NMF_HALS, m, n, KP).blocks()) * KP * KP);
+  const int64_t shn = std::max(plan_shares(NMF_MU, m, n, KP).blocks(),
+                               plan_shares(NMF_HALS, m, n, KP).blocks()) * KP * KP;
+  off[17] = cv.take<T>(shn <= GSUM_MAX ? 2 * shn : shn);
   return cv.off;
 }
 
@@ -636,6 +643,14 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   const Shares sh = plan_shares(o->algo, m, n, KP);
   T* gsl = sh.on() ? w.gsl : nullptr;
   bool qready = false;
+  // small MU problems: each update sums the other factor's shares itself (S
+  // and Q are then not formed, so not with the objective or the
+  // projected-gradient stop); the H update's shares (for Q) go to gslq
+  // (at most 16 shares, which reduce_splits also adds one after another, so
+  // either way gives the same bits)
+  const bool gin = sh.on() && o->algo == NMF_MU && !pgstop && !want_obj &&
+                   sh.blocks() * KP * KP <= GSUM_MAX && sh.blocks() <= 16;
+  T* gslq = gin ? gsl + sh.blocks() * KP * KP : gsl;
   // Dense products hand their split slabs to an MU or HALS update that adds
   // them as the ordered sum would (bit for bit), where that costs the update
   // no occupancy; P and R are then not formed, so not with the
@@ -652,14 +667,16 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   T* Wt_upd = own_t && o->algo == NMF_MU && tW ? w.Wt : nullptr;
   // HALS: the normalisation writes W's copy after rescaling W
   T* Wt_nrm = own_t && o->algo == NMF_HALS && tW ? w.Wt : nullptr;
+  // A phase mark records an event on the stream, which costs the stream a few
+  // microseconds: marks are set only where work follows them.
   for (int t = 0; t < o->iters; ++t) {
     // W given H: Q = H H^T, P = A H^T, UpdateW.
-    tm.mark(PH_GRAM);
+    if (!sh.on() || !qready) tm.mark(PH_GRAM);
     if (!sh.on()) {
       RUN(gram<T>(ctx, w.Ht, n, KP, w.Q, w.part));
     } else if (!qready) {
-      HIP_TRY(nmfk::gram_shares<T>(w.Ht, n, KP, sh.rpn, gsl, st));
-      RUN(sum_shares<T>(ctx, gsl, sh.nbn, KP, w.Q));
+      HIP_TRY(nmfk::gram_shares<T>(w.Ht, n, KP, sh.rpn, gslq, st));
+      if (!gin) RUN(sum_shares<T>(ctx, gslq, sh.nbn, KP, w.Q));
     }
     tm.mark(PH_MM);
     RUN(product_AF<T>(ctx, pb, m, n, w.Ht, tH ? w.Hk : nullptr, k, KP, w.P, w.part, nsp_w));
@@ -678,12 +695,12 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     }
     tm.mark(PH_LUC);
     const nmfk::Split<T> spw{nsp_w_v > 1 ? w.part : w.P, nsp_w_v, m * KP};
-    RUN(local_update<T>(ctx, o->algo, w.W, spw, w.Q, m, k, KP, o, w.status, w.pivots, w.ginv,
-                        gsl, Wt_upd));
+    RUN(local_update<T>(ctx, o->algo, w.W, spw, gin ? gslq : w.Q, m, k, KP, o, w.status,
+                        w.pivots, w.ginv, gsl, Wt_upd, nullptr, gin ? (int)sh.nbn : 1));
     // H given W: S = W^T W, (HALS: normalise), R = A^T W, UpdateH.
-    tm.mark(PH_GRAM);
-    if (sh.on()) RUN(sum_shares<T>(ctx, gsl, sh.nbm, KP, w.S));
-    else RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
+    if (!gin) tm.mark(PH_GRAM);
+    if (!sh.on()) RUN(gram<T>(ctx, w.W, m, KP, w.S, w.part));
+    else if (!gin) RUN(sum_shares<T>(ctx, gsl, sh.nbm, KP, w.S));
     if (o->algo == NMF_HALS) {
       tm.mark(PH_LUC);
       // W's columns rescaled here; H's compensation is applied by the H sweep
@@ -697,13 +714,15 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
     tm.mark(PH_LUC);
     const bool next_t = tH && t + 1 < o->iters;
     const nmfk::Split<T> sph{nsp_h_v > 1 ? w.part : w.R, nsp_h_v, n * KP};
-    RUN(local_update<T>(ctx, o->algo, w.Ht, sph, w.S, n, k, KP, o, w.status, w.pivots, w.ginv,
-                        gsl, own_t && next_t ? w.Hk : nullptr,
-                        o->algo == NMF_HALS ? w.norms : nullptr));
+    RUN(local_update<T>(ctx, o->algo, w.Ht, sph, gin ? gsl : w.S, n, k, KP, o, w.status,
+                        w.pivots, w.ginv, gslq, own_t && next_t ? w.Hk : nullptr,
+                        o->algo == NMF_HALS ? w.norms : nullptr, gin ? (int)sh.nbm : 1));
     if (sh.on()) {
       // the next iteration's Q, from the H update's shares
-      tm.mark(PH_GRAM);
-      RUN(sum_shares<T>(ctx, gsl, sh.nbn, KP, w.Q));
+      if (!gin) {
+        tm.mark(PH_GRAM);
+        RUN(sum_shares<T>(ctx, gslq, sh.nbn, KP, w.Q));
+      }
       qready = true;
     }
     if (next_t && !own_t) HIP_TRY(nmfk::transpose_rows<T>(w.Ht, n, KP, w.Hk, st));

@@ -84,9 +84,11 @@ hipError_t pack_fp8_t(const float* F, int64_t rows, int KP, uint8_t* Ft, int64_t
 // sum). Gslab (nullable, KP <= 64) receives the row blocks' shares of
 // Xn^T Xn, one KP x KP slab per block of share_rows rows (cdiv(rows,
 // share_rows) of them), for an ordered sum (reduce_splits).
+// mu_rows' gn (KP <= 64 when above 1): G is given as gn KP x KP shares at
+// stride KP * KP, which the update adds in order as it stages them.
 template <typename T>
 hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
-                   T* Xt, T* Pout, T* Gslab, hipStream_t st);
+                   T* Xt, T* Pout, T* Gslab, hipStream_t st, int gn = 1);
 // hals_rows' Xs (nullable, KP entries): the incoming rows are scaled first,
 // x_i *= Xs[i] where Xs[i] > 0 (the normalisation's compensation of H).
 template <typename T>

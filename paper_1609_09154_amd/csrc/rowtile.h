@@ -42,6 +42,10 @@ template <typename T, int KP, int NTHR> struct SquareStage {
       }
     }
   }
+  // The sum of n KP x KP slabs at G + q * stride, added in slab order in
+  // double and rounded to T: the same bits as the ordered sum of those slabs
+  // as a separate pass (reduce_splits).
+  __device__ __forceinline__ void load_sum(const T* __restrict__ G, int n, int64_t stride);
   __device__ __forceinline__ void store(T* dst) const {
 #pragma unroll
     for (int u = 0; u < PER; ++u)
@@ -161,6 +165,21 @@ __device__ __forceinline__ void slab_sum(const T* p, int n, int64_t stride, doub
     for (; q < n; ++q)
 #pragma unroll
       for (int e = 0; e < RPT; ++e) acc[e] += (double)p[q * stride + e];
+  }
+}
+
+template <typename T, int KP, int NTHR>
+__device__ __forceinline__ void SquareStage<T, KP, NTHR>::load_sum(const T* __restrict__ G, int n,
+                                                                   int64_t stride) {
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int ic = slot(u) < NV ? slot(u) : NV - 1;
+    double acc[VEC];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) acc[q] = 0.0;
+    slab_sum<T, VEC>(G + ic * VEC, n, stride, acc);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) v[u].v[q] = (T)acc[q];
   }
 }
 

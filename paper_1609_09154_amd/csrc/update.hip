@@ -134,12 +134,14 @@ template <int KP> struct RowSplit {
   static constexpr int ROWS = 256 / TPR;
 };
 
-template <typename T, int KP, bool SLABS>
+// GSUM: G arrives as gn KP x KP shares, summed while staged (in slab order
+// in double, as the separate ordered sum would).
+template <typename T, int KP, bool SLABS, bool GSUM>
 __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(const T* X, T* Xn, Split<T> P,
                                                           const T* __restrict__ G, int64_t rows,
                                                           int k, T eps, T* __restrict__ Xt,
                                                           T* __restrict__ Pout,
-                                                          T* __restrict__ Gslab) {
+                                                          T* __restrict__ Gslab, int gn) {
   constexpr int TPR = RowSplit<KP>::TPR, RPT = RowSplit<KP>::RPT, ROWS = RowSplit<KP>::ROWS;
   constexpr int VEC = Tr<T>::VEC;
   static_assert(RPT % VEC == 0, "16-byte reads of G");
@@ -155,7 +157,8 @@ __global__ __launch_bounds__(256) void mu_rows_tpr_kernel(const T* X, T* Xn, Spl
   // all in flight together
   SquareStage<T, KP, 256> gst;
   RowStage<T, KP, ROWS, XLD, 256> xst;
-  gst.load(G, nullptr);
+  if constexpr (GSUM) gst.load_sum(G, gn, (int64_t)KP * KP);
+  else gst.load(G, nullptr);
   xst.load(X, rb, rows);
   double ps[RPT];
 #pragma unroll
@@ -267,24 +270,32 @@ __global__ __launch_bounds__(LDS_ROWS) void mu_rows_lds_kernel(const T* X, T* Xn
 
 // One slab (the product as it came) needs no double accumulation: that form
 // keeps fewer registers live.
-template <typename T, int KP>
-void launch_mu_rows_tpr(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, T eps,
-                        T* Xt, T* Pout, T* Gslab, hipStream_t st) {
+template <typename T, int KP, bool GSUM>
+void launch_mu_rows_tpr_g(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, T eps,
+                          T* Xt, T* Pout, T* Gslab, int gn, hipStream_t st) {
   const unsigned nb = (unsigned)cdiv(rows, RowSplit<KP>::ROWS);
   if (P.n > 1)
-    mu_rows_tpr_kernel<T, KP, true><<<nb, 256, 0, st>>>(X, Xn, P, G, rows, k, eps, Xt, Pout,
-                                                          Gslab);
+    mu_rows_tpr_kernel<T, KP, true, GSUM><<<nb, 256, 0, st>>>(X, Xn, P, G, rows, k, eps, Xt,
+                                                                Pout, Gslab, gn);
   else
-    mu_rows_tpr_kernel<T, KP, false><<<nb, 256, 0, st>>>(X, Xn, P, G, rows, k, eps, Xt, Pout,
-                                                           Gslab);
+    mu_rows_tpr_kernel<T, KP, false, GSUM><<<nb, 256, 0, st>>>(X, Xn, P, G, rows, k, eps, Xt,
+                                                                 Pout, Gslab, gn);
+}
+
+template <typename T, int KP>
+void launch_mu_rows_tpr(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, T eps,
+                        T* Xt, T* Pout, T* Gslab, int gn, hipStream_t st) {
+  if (gn > 1) launch_mu_rows_tpr_g<T, KP, true>(X, Xn, P, G, rows, k, eps, Xt, Pout, Gslab, gn, st);
+  else launch_mu_rows_tpr_g<T, KP, false>(X, Xn, P, G, rows, k, eps, Xt, Pout, Gslab, 1, st);
 }
 
 template <typename T>
 hipError_t mu_rows(const T* X, T* Xn, Split<T> P, const T* G, int64_t rows, int k, int KP, T eps,
-                   T* Xt, T* Pout, T* Gslab, hipStream_t st) {
+                   T* Xt, T* Pout, T* Gslab, hipStream_t st, int gn) {
   if (rows <= 0) return hipSuccess;
-  if (((Xt || Gslab) && KP > 64) || !P.p || P.n < 1) return hipErrorInvalidValue;
-  KP_SWITCH(KP, (launch_mu_rows_tpr<T, KPc>(X, Xn, P, G, rows, k, eps, Xt, Pout, Gslab, st)),
+  if (((Xt || Gslab || gn > 1) && KP > 64) || !P.p || P.n < 1 || gn < 1)
+    return hipErrorInvalidValue;
+  KP_SWITCH(KP, (launch_mu_rows_tpr<T, KPc>(X, Xn, P, G, rows, k, eps, Xt, Pout, Gslab, gn, st)),
             (mu_rows_lds_kernel<T><<<(unsigned)cdiv(rows, LDS_ROWS), LDS_ROWS, 0, st>>>(
                 X, Xn, P, G, rows, k, KP, eps, Pout)));
   return NMF_LAUNCH_CHECK();
@@ -756,7 +767,7 @@ hipError_t transpose_out(const T* Ht, int k, int64_t n, int KP, T* H, hipStream_
 
 #define INST(T)                                                                             \
   template hipError_t mu_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T, T*, \
-                                 T*, T*, hipStream_t); \
+                                 T*, T*, hipStream_t, int); \
   template hipError_t gram_shares<T>(const T*, int64_t, int, int, T*, hipStream_t); \
   template hipError_t hals_rows<T>(const T*, T*, Split<T>, const T*, int64_t, int, int, T*, \
                                    T*, hipStream_t, const T*);                              \
