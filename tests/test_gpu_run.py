@@ -298,3 +298,47 @@ def test_csr_relerr_matches_oracle():
     ref = oracle.relative_error(scipy_csr(csr), W.astype(np.float32).astype(np.float64),
                                 H.astype(np.float32).astype(np.float64))
     assert abs(got - ref) <= 1e-5 * ref
+
+
+@pytest.mark.parametrize("algo,npdt,m,n,k", [("mu", np.float64, 2000, 1000, 10),
+                                             ("mu", np.float32, 1500, 900, 12),
+                                             ("mu", np.float32, 3000, 2600, 50),
+                                             ("hals", np.float32, 1200, 700, 20),
+                                             ("hals", np.float64, 700, 500, 33)])
+def test_sums_inside_the_updates_match_the_separate_sums(algo, npdt, m, n, k):
+    """The MU and HALS updates add the products' split slabs themselves (HALS
+    below 16,384 rows), and small MU problems' updates add the other factor's
+    Gram shares as they stage them, each in the order of the separate ordered
+    sum. With the objective on, the Grams are formed apart; with the
+    projected-gradient stop (tolerance 0: every iteration runs), the products'
+    slabs are summed apart too. The factors are the same bit for bit."""
+    A, W0, H0 = dense_case(m, n, k, k, 31, npdt)
+    Ad = to_dev(A, npdt)
+    outs = []
+    for kw in (dict(objective=False), dict(objective=True),
+               dict(objective=False, stop="pgrad", tol=0.0)):
+        step("fused sums %s %s %dx%d k=%d %s" % (algo, np.dtype(npdt).name, m, n, k, kw))
+        Wd, Hd = to_dev(W0, npdt), to_dev(H0, npdt)
+        nmf.nmf_dense(Ad, Wd, Hd, algo=algo, iters=5, **kw)
+        outs.append((host(Wd), host(Hd)))
+    for W, H in outs[1:]:
+        np.testing.assert_array_equal(W, outs[0][0])
+        np.testing.assert_array_equal(H, outs[0][1])
+
+
+def test_csr_mu_gram_sums_inside_the_updates_match_the_separate_sums():
+    """The sparse path's small MU problems: the updates add the Gram shares
+    themselves without the objective, and the Grams are formed apart with it
+    (the sparse objective reads them); the factors agree bit for bit."""
+    m, n, k = 1500, 1100, 10
+    csr = erdos_renyi_csr(m, n, 60.0 / n, seed=12)
+    W0, H0 = init_factors(m, n, k, seed=13)
+    rp, ci, cv = csr_dev(csr)
+    outs = []
+    for obj in (False, True):
+        step("csr mu fused gram sums objective=%s" % obj)
+        Wd, Hd = to_dev(W0, np.float32), to_dev(H0, np.float32)
+        nmf.nmf_csr(rp, ci, cv, n, Wd, Hd, algo="mu", iters=6, objective=obj)
+        outs.append((host(Wd), host(Hd)))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
