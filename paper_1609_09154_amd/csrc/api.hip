@@ -187,6 +187,23 @@ Shares plan_shares(int algo, int64_t m, int64_t n, int KP) {
   return sh;
 }
 
+// Whether the MU updates add these shares themselves as they stage G (few
+// enough: at most 16, which reduce_splits also adds one after another, so
+// either way gives the same bits).
+bool gsum_fits(const Shares& sh, int KP) {
+  return sh.on() && sh.blocks() * KP * KP <= GSUM_MAX && sh.blocks() <= 16;
+}
+
+// Elements of the updates' share workspace for an m x n problem: room for
+// either update's shares, and for two sets (one per factor) where the MU
+// updates add them themselves.
+int64_t share_elems(int64_t m, int64_t n, int KP) {
+  const Shares mu = plan_shares(NMF_MU, m, n, KP), ha = plan_shares(NMF_HALS, m, n, KP);
+  int64_t need = std::max(mu.blocks(), ha.blocks()) * KP * KP;
+  if (gsum_fits(mu, KP)) need = std::max<int64_t>(need, 2 * mu.blocks() * KP * KP);
+  return need;
+}
+
 // G = the ordered sum of nb shares at gsl (Gt, nullable: its transpose).
 template <typename T>
 nmf_status sum_shares(nmf_ctx* ctx, const T* gsl, int64_t nb, int KP, T* G, T* Gt = nullptr) {
@@ -370,9 +387,7 @@ size_t plan_work(int64_t m, int64_t n, int KP, int iters, int64_t obj_np, int64_
   off[16] = cv.take<double>(4);
   // the updates' Gram shares, for either update that writes them (apart from
   // the product slabs, which an update may still be reading)
-  const int64_t shn = std::max(plan_shares(NMF_MU, m, n, KP).blocks(),
-                               plan_shares(NMF_HALS, m, n, KP).blocks()) * KP * KP;
-  off[17] = cv.take<T>(shn <= GSUM_MAX ? 2 * shn : shn);
+  off[17] = cv.take<T>(share_elems(m, n, KP));
   return cv.off;
 }
 
@@ -646,10 +661,7 @@ nmf_status run_au_nmf(nmf_ctx* ctx, const Prob<T>& pb, int64_t m, int64_t n, int
   // small MU problems: each update sums the other factor's shares itself (S
   // and Q are then not formed, so not with the objective or the
   // projected-gradient stop); the H update's shares (for Q) go to gslq
-  // (at most 16 shares, which reduce_splits also adds one after another, so
-  // either way gives the same bits)
-  const bool gin = sh.on() && o->algo == NMF_MU && !pgstop && !want_obj &&
-                   sh.blocks() * KP * KP <= GSUM_MAX && sh.blocks() <= 16;
+  const bool gin = o->algo == NMF_MU && !pgstop && !want_obj && gsum_fits(sh, KP);
   T* gslq = gin ? gsl + sh.blocks() * KP * KP : gsl;
   // Dense products hand their split slabs to an MU or HALS update that adds
   // them as the ordered sum would (bit for bit), where that costs the update

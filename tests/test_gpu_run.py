@@ -302,6 +302,8 @@ def test_csr_relerr_matches_oracle():
 
 @pytest.mark.parametrize("algo,npdt,m,n,k", [("mu", np.float64, 2000, 1000, 10),
                                              ("mu", np.float32, 1500, 900, 12),
+                                             ("mu", np.float32, 100, 90, 64),
+                                             ("hals", np.float32, 100, 90, 64),
                                              ("mu", np.float32, 3000, 2600, 50),
                                              ("hals", np.float32, 1200, 700, 20),
                                              ("hals", np.float64, 700, 500, 33)])
