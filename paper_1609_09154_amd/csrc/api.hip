@@ -2072,8 +2072,7 @@ nmf_status hals_backward_impl(nmf_ctx* ctx, int64_t m, int64_t n, const T* A, in
       if ((s = mu_prod_AF<T>(ctx, pb, m, n, gR, k, KP, tmp, w, tH, &yp)) != NMF_OK) return s;
       HIP_TRY(nmfk::rowmm_add<T>(W1s, M, m, k, KP, gW, st, yp));
       // normalisation: Wn = W' / s, Hc = s H
-      HIP_TRY(nmfk::coldot<T>(gW, W1s, m, KP, dpart, dots, st));
-      HIP_TRY(nmfk::coldot<T>(gHc, H0s, n, KP, dpart, dots + KP, st));
+      HIP_TRY(nmfk::coldot2<T>(gW, W1s, m, gHc, H0s, n, KP, dpart, dots, st));
       HIP_TRY(nmfk::hals_norm_adjoint<T>(gW, W1s, m, gHc, n, Ns + i * KP, dots, k, KP, gWp, gH2,
                                          st));
       // W sweep with P = A H^T and Q = H H^T

@@ -578,44 +578,59 @@ __global__ __launch_bounds__(GG_OUT * GG_SUB) void hals_gram_grad_kernel(
 }
 
 // Column dot products out[c] = sum_r X[r][c] Y[r][c] (rows x KP, KP <= 128)
-// in double: each block sums a slice of rows per column (256 / KP row lanes,
-// combined in LDS), and a second kernel adds the block partials of each
-// column in a fixed tree.
+// in double, for two pairs (X, Y) at once: each block sums a slice of one
+// pair's rows per column (256 / KP row lanes, combined in LDS), and a second
+// kernel adds the block partials of each column in a fixed tree.
 constexpr int COLDOT_BLOCKS = 256;
 template <typename T>
-__global__ __launch_bounds__(256) void coldot_partials_kernel(const T* __restrict__ X,
-                                                              const T* __restrict__ Y,
-                                                              int64_t rows, int KP,
+__global__ __launch_bounds__(256) void coldot_partials_kernel(const T* __restrict__ X1,
+                                                              const T* __restrict__ Y1,
+                                                              int64_t rows1, int nb1,
+                                                              const T* __restrict__ X2,
+                                                              const T* __restrict__ Y2,
+                                                              int64_t rows2, int KP,
                                                               double* __restrict__ part) {
   __shared__ double sh[256];
+  // blocks [0, nb1) take the first pair, the rest the second, each pair
+  // striding over its rows with its own block count
+  const bool two = (int)blockIdx.x >= nb1;
+  const T* X = two ? X2 : X1;
+  const T* Y = two ? Y2 : Y1;
+  const int64_t rows = two ? rows2 : rows1;
+  const int b = two ? (int)blockIdx.x - nb1 : (int)blockIdx.x;
+  const int nb = two ? (int)gridDim.x - nb1 : nb1;
   const int lanes = 256 / KP;
   const int c = threadIdx.x % KP, lr = threadIdx.x / KP;
   double acc = 0.0;
   if (lr < lanes)
-    for (int64_t r = (int64_t)blockIdx.x * lanes + lr; r < rows; r += (int64_t)gridDim.x * lanes)
+    for (int64_t r = (int64_t)b * lanes + lr; r < rows; r += (int64_t)nb * lanes)
       acc += (double)X[r * KP + c] * (double)Y[r * KP + c];
   sh[threadIdx.x] = acc;
   __syncthreads();
   if ((int)threadIdx.x < KP) {
     double t = 0.0;
     for (int q = 0; q < lanes; ++q) t += sh[q * KP + threadIdx.x];
-    part[(int64_t)blockIdx.x * KP + threadIdx.x] = t;
+    part[((two ? COLDOT_BLOCKS : 0) + (int64_t)b) * KP + threadIdx.x] = t;
   }
 }
 
-// One block per column: the block partials (at most COLDOT_BLOCKS) are added
-// pairwise in a fixed tree in LDS.
+// One block per column of both pairs (column c of the second pair is block
+// KP + c): the block partials (at most COLDOT_BLOCKS) are added pairwise in
+// a fixed tree in LDS.
 __global__ __launch_bounds__(COLDOT_BLOCKS) void coldot_finish_kernel(
-    const double* __restrict__ part, int nblocks, int KP, double* __restrict__ out) {
+    const double* __restrict__ part, int nb1, int nb2, int KP, double* __restrict__ out) {
   __shared__ double sh[COLDOT_BLOCKS];
-  const int c = blockIdx.x, t = threadIdx.x;
-  sh[t] = t < nblocks ? part[(int64_t)t * KP + c] : 0.0;
+  const bool two = (int)blockIdx.x >= KP;
+  const int c = two ? (int)blockIdx.x - KP : (int)blockIdx.x, t = threadIdx.x;
+  const int nblocks = two ? nb2 : nb1;
+  const double* p = part + (two ? (int64_t)COLDOT_BLOCKS * KP : 0);
+  sh[t] = t < nblocks ? p[(int64_t)t * KP + c] : 0.0;
   __syncthreads();
   for (int h = COLDOT_BLOCKS / 2; h > 0; h >>= 1) {
     if (t < h) sh[t] += sh[t + h];
     __syncthreads();
   }
-  if (t == 0) out[c] = sh[0];
+  if (t == 0) out[blockIdx.x] = sh[0];
 }
 
 // Adjoint of the HALS normalisation Wn = W' diag(1/s), Hc = diag(s) H
@@ -774,19 +789,23 @@ hipError_t hals_gram_grad(const T* slabs, int nb, int KP, T* M, hipStream_t st) 
   return NMF_LAUNCH_CHECK();
 }
 
-int64_t coldot_partials(int KP) { return (int64_t)COLDOT_BLOCKS * KP; }
+int64_t coldot_partials(int KP) { return 2 * (int64_t)COLDOT_BLOCKS * KP; }
 
 template <typename T>
-hipError_t coldot(const T* X, const T* Y, int64_t rows, int KP, double* part, double* out,
-                  hipStream_t st) {
+hipError_t coldot2(const T* X1, const T* Y1, int64_t rows1, const T* X2, const T* Y2,
+                   int64_t rows2, int KP, double* part, double* out, hipStream_t st) {
   if (KP < 1 || KP > 128) return hipErrorInvalidValue;
   const int lanes = 256 / KP;
-  int64_t blocks = cdiv(rows > 0 ? rows : 1, lanes);
-  blocks = blocks < COLDOT_BLOCKS ? blocks : COLDOT_BLOCKS;
-  coldot_partials_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(X, Y, rows, KP, part);
+  auto blocks_for = [&](int64_t rows) {
+    const int64_t b = cdiv(rows > 0 ? rows : 1, lanes);
+    return (int)(b < COLDOT_BLOCKS ? b : COLDOT_BLOCKS);
+  };
+  const int nb1 = blocks_for(rows1), nb2 = blocks_for(rows2);
+  coldot_partials_kernel<T><<<(unsigned)(nb1 + nb2), 256, 0, st>>>(X1, Y1, rows1, nb1, X2, Y2,
+                                                                    rows2, KP, part);
   hipError_t e = NMF_LAUNCH_CHECK();
   if (e != hipSuccess) return e;
-  coldot_finish_kernel<<<(unsigned)KP, COLDOT_BLOCKS, 0, st>>>(part, (int)blocks, KP, out);
+  coldot_finish_kernel<<<(unsigned)(2 * KP), COLDOT_BLOCKS, 0, st>>>(part, nb1, nb2, KP, out);
   return NMF_LAUNCH_CHECK();
 }
 
@@ -806,8 +825,8 @@ hipError_t hals_norm_adjoint(const T* gWn, const T* Wn, int64_t m, const T* gHc,
                                            T*, T*, T*, const T*, T*, hipStream_t);            \
   template int64_t hals_adjoint_blocks<T>(int64_t, int);                                      \
   template hipError_t hals_gram_grad<T>(const T*, int, int, T*, hipStream_t);                 \
-  template hipError_t coldot<T>(const T*, const T*, int64_t, int, double*, double*,           \
-                                hipStream_t);                                                 \
+  template hipError_t coldot2<T>(const T*, const T*, int64_t, const T*, const T*, int64_t,    \
+                                 int, double*, double*, hipStream_t);                         \
   template hipError_t hals_norm_adjoint<T>(const T*, const T*, int64_t, const T*, int64_t,    \
                                            const T*, const double*, int, int, T*, T*,         \
                                            hipStream_t);                                      \

@@ -225,12 +225,13 @@ int64_t hals_adjoint_blocks(int64_t rows, int KP);
 // per-block slabs of each that hals_adjoint_rows writes).
 template <typename T>
 hipError_t hals_gram_grad(const T* slabs, int nb, int KP, T* M, hipStream_t st);
-// out[c] = sum_r X[r][c] Y[r][c] (double, fixed order); part holds
-// coldot_partials(KP) doubles.
+// Column dot products of two pairs in one pass: out[c] = sum_r X1[r][c]
+// Y1[r][c] over rows1 rows and out[KP + c] the same for X2, Y2 over rows2
+// (double, fixed order); part holds coldot_partials(KP) doubles.
 int64_t coldot_partials(int KP);
 template <typename T>
-hipError_t coldot(const T* X, const T* Y, int64_t rows, int KP, double* part, double* out,
-                  hipStream_t st);
+hipError_t coldot2(const T* X1, const T* Y1, int64_t rows1, const T* X2, const T* Y2,
+                   int64_t rows2, int KP, double* part, double* out, hipStream_t st);
 // Adjoint of the HALS normalisation (Wn = W' / s, Hc = s H per column):
 // gWp = dL/dW', gHt = dL/dH^T (pre-scaling) from gWn, gHc; dots[c] =
 // <gWn_c, Wn_c>, dots[KP + c] = <gHc_c, Ht_c>.
